@@ -1,0 +1,179 @@
+/*
+ * gap.h -- C ABI of the MI355X (gfx950) sparse-GP (GAP) fit library.
+ *
+ * The library fits the weights c of a sparse Gaussian-process model of total
+ * energies (Sec. Theory of "Massively Parallel Fitting of Gaussian
+ * Approximation Potentials"):
+ *
+ *   E_A = sum_{i in A} eps(x_i),  eps(x) = sum_j c_j k(x, x_j)     (Eqs. 1-2)
+ *   k(x, x') = sigma_w^2 (x . x')^zeta   (dot-product covariance, integer zeta)
+ *   minimise L(c) = (y - K_NM c)^T Sigma^-1 (y - K_NM c) + c^T K_MM c  (Eq. loss)
+ *
+ * by the stable route of Sec. Theory: K_MM (+ jitter on its diagonal) =
+ * L L^T, A = [Sigma^-1/2 K_NM ; L^T] ((N+M) x M), b = [Sigma^-1/2 y ; 0],
+ * A = QR by Householder reflections, c = R^-1 Q^T b.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named x_*, config_offsets, sigma, y, c, c_out, y_out and the
+ *    workspace are DEVICE pointers (HBM of the GPU current when the handle was
+ *    created), owned by the caller; the library never allocates device memory
+ *    and never frees what it is given.  gap_params, gap_solve_info and
+ *    gap_layout_info are host structs.
+ *  - Work is enqueued asynchronously on the handle's HIP stream (a hipStream_t
+ *    passed as void*; NULL = the default stream).  Inputs must stay valid and
+ *    unmodified until that work completes; the sparse set given to
+ *    gap_build_knm must stay valid for later gap_predict calls.
+ *  - Argument errors are detected synchronously, before anything is enqueued,
+ *    and returned as GAP_EINVAL / GAP_ENOMEM / GAP_ESTATE.  Failures found on
+ *    the device (Cholesky pivot not positive, non-finite values) are reported
+ *    through gap_solve_info.device_status and the status returned by
+ *    gap_solve (when it is given an info struct) or gap_sync.
+ *  - A handle is used from one host thread at a time; independent handles
+ *    may run concurrently on different streams.
+ *  - Call order: gap_create -> gap_bind_workspace -> gap_build_knm ->
+ *    gap_solve -> gap_predict*; gap_build_knm may be called again to start a
+ *    new fit in the same handle.
+ *  - Descriptors are used as given: the covariance assumes unit-L2 rows but
+ *    does not renormalise them.
+ */
+#ifndef GAP_H
+#define GAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gap_status {
+    GAP_OK = 0,
+    GAP_EINVAL = 1,      /* bad argument: shape, pointer, zeta outside 1..8, sigma_w <= 0 */
+    GAP_ENOMEM = 2,      /* the bound workspace is smaller than gap_workspace_bytes() */
+    GAP_ENOTPD = 3,      /* K_MM + jitter is not positive definite (Cholesky pivot <= 0) */
+    GAP_ENONFINITE = 4,  /* a NaN or Inf reached the weights */
+    GAP_ENOCONV = 5,     /* mixed precision: refinement did not reach refine_tol */
+    GAP_EDEVICE = 6,     /* a HIP runtime call failed */
+    GAP_ESTATE = 7       /* entry points called out of order */
+} gap_status;
+
+typedef enum gap_precision {
+    GAP_FP64 = 0,        /* every stage in FP64 */
+    GAP_MIXED_FP32 = 1   /* FP64 K_NM/Cholesky; FP32 Householder QR with FP64 reflector norms;
+                            FP64 iterative refinement of c against the FP64 A */
+} gap_precision;
+
+/* Fit parameters (host struct). */
+typedef struct gap_params {
+    int32_t d;                /* descriptor length, >= 1 */
+    int32_t zeta;             /* kernel exponent, 1..8 */
+    double sigma_w;           /* kernel prefactor sigma_w (> 0); k carries sigma_w^2 */
+    double jitter;            /* added to K_MM's diagonal before the Cholesky (>= 0) */
+    int32_t precision;        /* gap_precision */
+    int32_t max_refine_iters; /* mixed precision only: refinement iteration cap */
+    double refine_tol;        /* mixed precision only: stop when ||dc||/||c|| <= refine_tol */
+    uint32_t flags;           /* GAP_FLAG_* */
+} gap_params;
+
+/* Record per-stage durations with HIP events (read back by gap_stage_times). */
+#define GAP_FLAG_TIMING 1u
+
+typedef struct gap_handle_s *gap_handle;
+
+typedef struct gap_solve_info {
+    int32_t device_status;   /* gap_status found on the device (GAP_OK when none) */
+    int32_t refine_iters;    /* mixed precision: refinement iterations done (0 in FP64) */
+    double residual_norm2;   /* ||(Q^T b)[M:]||^2 = min of the loss at the returned c */
+    double grad_rel;         /* mixed precision: last ||dc|| / ||c||; 0 in FP64 */
+    double est_err;          /* reserved: 0 */
+} gap_solve_info;
+
+/* Where the library keeps its stage outputs inside the bound workspace (host struct).
+ * A_aug is column-major with leading dimension lda (in elements):
+ *   rows 0..N-1, cols 0..M-1      Sigma^-1/2 K_NM after gap_build_knm; R and reflectors after gap_solve
+ *   rows N..N+M-1, cols 0..M-1    L^T (upper triangular) after gap_build_knm
+ *   col M                          b = [Sigma^-1/2 y ; 0] during gap_solve, Q^T b after it
+ *   rows m..lda-1 and cols M+1..ncols-1 are zero padding (they do not change the solution). */
+typedef struct gap_layout_info {
+    double *A_aug;
+    int64_t lda;          /* rows of A_aug in memory (>= N + M) */
+    int64_t ncols;        /* columns of A_aug in memory (>= M + 1) */
+    int64_t N, M, n_atoms;
+    double *tau;          /* [M] Householder weights after gap_solve */
+    int32_t *device_status;
+} gap_layout_info;
+
+/* Create a handle bound to the current HIP device and `stream` (hipStream_t or NULL).
+ * Validates p (GAP_EINVAL).  Allocates only host memory and HIP events. */
+gap_status gap_create(const gap_params *p, void *stream, gap_handle *out);
+
+/* Bytes of device workspace a fit of this shape needs.  Pure host function:
+ * usable before any GPU call, e.g. to admit work by HBM footprint.  0 on bad input. */
+size_t gap_workspace_bytes(const gap_params *p, int64_t n_configs, int64_t n_atoms, int64_t M);
+
+/* Hand the library a caller-owned device buffer (256-byte aligned) of `bytes`
+ * bytes.  The library carves every scratch array from it.  GAP_EINVAL on NULL
+ * or misaligned pointers. */
+gap_status gap_bind_workspace(gap_handle h, void *dev_ptr, size_t bytes);
+
+/*
+ * Build the stacked matrix's blocks (Sec. Theory: K_NM, K_MM, Cholesky; the
+ * upper block of A and its lower block L^T).
+ *   x_atoms        [n_atoms x d] row-major FP64, atoms of a configuration contiguous
+ *   config_offsets [n_configs + 1] int64: configuration A owns atoms
+ *                  offsets[A] .. offsets[A+1]-1; offsets[0] = 0, nondecreasing,
+ *                  offsets[n_configs] = n_atoms (checked on the device; a violation
+ *                  is reported as GAP_EINVAL through the device status)
+ *   x_sparse       [M x d] row-major FP64 sparse points
+ *   sigma          [n_configs] FP64 standard deviation of each target (> 0)
+ * Requires n_configs >= 1, M >= 1, n_atoms >= 1, workspace >= gap_workspace_bytes.
+ */
+gap_status gap_build_knm(gap_handle h, const double *x_atoms, int64_t n_atoms,
+                         const int64_t *config_offsets, int64_t n_configs,
+                         const double *x_sparse, int64_t M, const double *sigma);
+
+/*
+ * Solve for the weights (Sec. Theory: b = [Sigma^-1/2 y ; 0], Householder QR of
+ * [A | b] giving R and Q^T b, back-substitution c = R^-1 (Q^T b)[0:M]).
+ *   y      [n_configs] FP64 targets (device)
+ *   c_out  [M] FP64 weights (device)
+ *   info   host struct or NULL.  When non-NULL the call waits for the stream and
+ *          returns the device status; when NULL it returns after enqueueing.
+ * The factorisation overwrites the stacked matrix: call gap_build_knm again
+ * before solving with another y.
+ */
+gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_info *info);
+
+/*
+ * Predict total energies (Eqs. 1-2) of n_configs configurations against the
+ * sparse set bound by the last gap_build_knm:
+ *   y_out[A] = sum_{i in A} sum_j c_j sigma_w^2 (x_i . x_j)^zeta.
+ * x_atoms/offsets as in gap_build_knm; c [M] and y_out [n_configs] device FP64.
+ * Uses no workspace.
+ */
+gap_status gap_predict(gap_handle h, const double *x_atoms, int64_t n_atoms,
+                       const int64_t *offsets, int64_t n_configs, const double *c, double *y_out);
+
+/* Wait for the handle's stream; fill info (nullable) and return the device status. */
+gap_status gap_sync(gap_handle h, gap_solve_info *info);
+
+/* Where the stage outputs live in the workspace (after gap_build_knm). */
+gap_status gap_layout(gap_handle h, gap_layout_info *out);
+
+/* Per-stage milliseconds of the last build/solve when GAP_FLAG_TIMING is set:
+ * [0] K_NM kernel, [1] K_MM kernel, [2] Cholesky, [3] b assembly,
+ * [4] Householder QR incl. Q^T b, [5] back-substitution, [6] refinement.
+ * Waits for the stream.  n = number of floats in ms (up to 8). */
+gap_status gap_stage_times(gap_handle h, float *ms, int n);
+
+/* Human-readable name of a status code (static string). */
+const char *gap_status_string(gap_status s);
+
+/* Release the handle (host memory and events).  The workspace stays the caller's. */
+gap_status gap_destroy(gap_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GAP_H */

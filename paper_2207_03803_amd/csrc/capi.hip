@@ -1,0 +1,383 @@
+// C ABI of the GAP fit library: argument checks, workspace carving and the
+// order in which the kernels are enqueued.  Declarations and the contract of
+// each entry point are in include/gap.h.
+#include <math.h>
+#include <new>
+#include <string.h>
+
+#include "../../include/gap.h"
+#include "kernels.h"
+
+using namespace gap;
+
+namespace {
+
+constexpr int N_STAGES = 8;
+
+enum State { ST_CREATED = 0, ST_BOUND = 1, ST_BUILT = 2, ST_SOLVED = 3 };
+
+struct Layout {
+    int64_t N = 0, M = 0, n_atoms = 0, m = 0, lda = 0, ncols = 0, max_tiles = 0, col_wgs = 0;
+    size_t off_A = 0, off_tau = 0, off_refl = 0, off_colpart = 0, off_wpart = 0, off_T = 0, off_W = 0,
+           off_rhs = 0, off_misc = 0, off_tiles = 0, off_counters = 0, off_status = 0, total = 0;
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+Layout make_layout(int64_t N, int64_t n_atoms, int64_t M)
+{
+    Layout L;
+    L.N = N;
+    L.M = M;
+    L.n_atoms = n_atoms;
+    L.m = N + M;
+    L.lda = (L.m + 63) / 64 * 64;
+    L.ncols = M + 1;
+    L.max_tiles = knm_max_tiles(N, n_atoms);
+    L.col_wgs = qr_max_col_wgs(L.m);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes, 256);
+        return at;
+    };
+    L.off_A = take(sizeof(double) * (size_t)L.lda * (size_t)L.ncols);
+    L.off_tau = take(sizeof(double) * (size_t)M);
+    L.off_refl = take(sizeof(double) * (2 * QR_NB + 2));
+    L.off_colpart = take(sizeof(double) * (size_t)L.col_wgs * (QR_NB + 1));
+    L.off_wpart = take(sizeof(double) * (size_t)qr_max_chunks() * QR_NB * (size_t)(QR_NB + L.ncols));
+    L.off_T = take(sizeof(double) * QR_NB * QR_NB);
+    L.off_W = take(sizeof(double) * QR_NB * (size_t)L.ncols);
+    L.off_rhs = take(sizeof(double) * (size_t)M);
+    L.off_misc = take(sizeof(double) * 512);
+    L.off_tiles = take(sizeof(int32_t) * (size_t)(L.max_tiles + 2));
+    L.off_counters = take(sizeof(unsigned) * 16);
+    L.off_status = take(sizeof(int32_t) * 4);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct gap_handle_s {
+    gap_params p;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    int state = ST_CREATED;
+    Layout L;
+    const double *x_sparse = nullptr;
+    const double *sigma = nullptr;
+    hipEvent_t ev[2 * N_STAGES] = {};
+    bool timed[N_STAGES] = {};
+    bool timing = false;
+
+    template <class T>
+    T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+    double *A() const { return at<double>(L.off_A); }
+    int32_t *status() const { return at<int32_t>(L.off_status); }
+    unsigned *counters() const { return at<unsigned>(L.off_counters); }
+    double *misc() const { return at<double>(L.off_misc); }
+
+    void mark(int stage, bool end)
+    {
+        if (!timing)
+            return;
+        (void)hipEventRecord(ev[2 * stage + (end ? 1 : 0)], stream);
+        if (end)
+            timed[stage] = true;
+    }
+};
+
+namespace {
+
+__global__ void zero_u32_kernel(unsigned *p, int n)
+{
+    if ((int)threadIdx.x < n)
+        p[threadIdx.x] = 0u;
+}
+
+__global__ void copy_kernel(const double *src, double *dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n)
+        dst[i] = src[i];
+}
+
+bool valid_params(const gap_params *p)
+{
+    return p && p->d >= 1 && p->zeta >= 1 && p->zeta <= 8 && p->sigma_w > 0.0 && isfinite(p->sigma_w) &&
+           p->jitter >= 0.0 && isfinite(p->jitter) &&
+           (p->precision == GAP_FP64 || p->precision == GAP_MIXED_FP32);
+}
+
+gap_status dev(hipError_t e) { return e == hipSuccess ? GAP_OK : GAP_EDEVICE; }
+
+#define GAP_TRY(expr)                      \
+    do {                                   \
+        gap_status s_ = (expr);            \
+        if (s_ != GAP_OK)                  \
+            return s_;                     \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char *gap_status_string(gap_status s)
+{
+    switch (s) {
+    case GAP_OK: return "ok";
+    case GAP_EINVAL: return "invalid argument";
+    case GAP_ENOMEM: return "workspace too small";
+    case GAP_ENOTPD: return "K_MM + jitter is not positive definite";
+    case GAP_ENONFINITE: return "non-finite value in the weights";
+    case GAP_ENOCONV: return "refinement did not converge";
+    case GAP_EDEVICE: return "HIP runtime error";
+    case GAP_ESTATE: return "entry point called out of order";
+    }
+    return "unknown status";
+}
+
+size_t gap_workspace_bytes(const gap_params *p, int64_t n_configs, int64_t n_atoms, int64_t M)
+{
+    if (!valid_params(p) || n_configs < 1 || n_atoms < 0 || M < 1)
+        return 0;
+    return make_layout(n_configs, n_atoms, M).total;
+}
+
+gap_status gap_create(const gap_params *p, void *stream, gap_handle *out)
+{
+    if (!out || !valid_params(p))
+        return GAP_EINVAL;
+    *out = nullptr;
+    gap_handle h = new (std::nothrow) gap_handle_s();
+    if (!h)
+        return GAP_EDEVICE;
+    h->p = *p;
+    h->stream = reinterpret_cast<hipStream_t>(stream);
+    h->timing = (p->flags & GAP_FLAG_TIMING) != 0;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return GAP_EDEVICE;
+    }
+    if (h->timing) {
+        for (int i = 0; i < 2 * N_STAGES; ++i)
+            if (hipEventCreate(&h->ev[i]) != hipSuccess) {
+                delete h;
+                return GAP_EDEVICE;
+            }
+    }
+    *out = h;
+    return GAP_OK;
+}
+
+gap_status gap_bind_workspace(gap_handle h, void *dev_ptr, size_t bytes)
+{
+    if (!h || !dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) & 255u))
+        return GAP_EINVAL;
+    h->ws = static_cast<char *>(dev_ptr);
+    h->ws_bytes = bytes;
+    h->state = ST_BOUND;
+    return GAP_OK;
+}
+
+gap_status gap_build_knm(gap_handle h, const double *x_atoms, int64_t n_atoms, const int64_t *config_offsets,
+                         int64_t n_configs, const double *x_sparse, int64_t M, const double *sigma)
+{
+    if (!h)
+        return GAP_EINVAL;
+    if (h->state < ST_BOUND)
+        return GAP_ESTATE;
+    if (!x_atoms || !config_offsets || !x_sparse || !sigma || n_atoms < 1 || n_configs < 1 || M < 1 ||
+        n_configs > INT32_MAX - 1)
+        return GAP_EINVAL;
+    const Layout L = make_layout(n_configs, n_atoms, M);
+    if (L.total > h->ws_bytes)
+        return GAP_ENOMEM;
+    h->L = L;
+    h->x_sparse = x_sparse;
+    h->sigma = sigma;
+    hipStream_t s = h->stream;
+    const gap_params &p = h->p;
+    const double sw2 = p.sigma_w * p.sigma_w;
+
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, h->counters(), 16);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned *>(h->status()), 4);
+    int32_t *tiles = h->at<int32_t>(L.off_tiles);
+    GAP_TRY(dev(launch_plan_tiles(config_offsets, n_configs, n_atoms, tiles, tiles + L.max_tiles + 1,
+                                  L.max_tiles, h->status(), s)));
+
+    KnmArgs a{};
+    a.X = x_atoms;
+    a.offsets = config_offsets;
+    a.tile_cfg = tiles;
+    a.n_tiles_dev = tiles + L.max_tiles + 1;
+    a.XM = x_sparse;
+    a.M = M;
+    a.d = p.d;
+    a.zeta = p.zeta;
+    a.sw2 = sw2;
+    a.sigma = sigma;
+    a.out = h->A();
+    a.ldo = L.lda;
+    a.row_off = 0;
+    a.status = h->status();
+    h->mark(0, false);
+    GAP_TRY(dev(launch_knm(a, L.max_tiles, s)));
+    h->mark(0, true);
+
+    // K_MM + jitter (upper triangle) into rows N..N+M-1, then U = L^T in place.
+    KnmArgs k{};
+    k.X = x_sparse;
+    k.offsets = nullptr;
+    k.n_rows_unit = M;
+    k.XM = x_sparse;
+    k.M = M;
+    k.d = p.d;
+    k.zeta = p.zeta;
+    k.sw2 = sw2;
+    k.sigma = nullptr;
+    k.out = h->A();
+    k.ldo = L.lda;
+    k.row_off = n_configs;
+    k.jitter = p.jitter;
+    k.upper_only = 1;
+    k.status = h->status();
+    h->mark(1, false);
+    GAP_TRY(dev(launch_knm(k, (M + KNM_BM - 1) / KNM_BM, s)));
+    h->mark(1, true);
+    h->mark(2, false);
+    GAP_TRY(dev(launch_potrf_upper(h->A() + n_configs, L.lda, M, h->status(), s)));
+    h->mark(2, true);
+    h->state = ST_BUILT;
+    return GAP_OK;
+}
+
+gap_status gap_sync(gap_handle h, gap_solve_info *info)
+{
+    if (!h)
+        return GAP_EINVAL;
+    if (hipStreamSynchronize(h->stream) != hipSuccess)
+        return GAP_EDEVICE;
+    int32_t st = 0;
+    double res = 0.0;
+    if (h->ws && h->L.total) {
+        if (hipMemcpy(&st, h->status(), sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
+            return GAP_EDEVICE;
+        if (hipMemcpy(&res, h->misc(), sizeof(res), hipMemcpyDeviceToHost) != hipSuccess)
+            return GAP_EDEVICE;
+    }
+    if (info) {
+        memset(info, 0, sizeof(*info));
+        info->device_status = st;
+        info->residual_norm2 = res;
+    }
+    return (gap_status)st;
+}
+
+gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_info *info)
+{
+    if (!h || !y || !c_out)
+        return GAP_EINVAL;
+    if (h->state != ST_BUILT)
+        return GAP_ESTATE;
+    const Layout &L = h->L;
+    hipStream_t s = h->stream;
+    double *A = h->A();
+    h->mark(3, false);
+    GAP_TRY(dev(launch_assemble_b(y, h->sigma, L.N, A + L.M * L.lda, L.lda, s)));
+    h->mark(3, true);
+
+    QrWork w{};
+    w.A = A;
+    w.lda = L.lda;
+    w.m = L.m;
+    w.n = L.M;
+    w.ncols = L.ncols;
+    w.tau = h->at<double>(L.off_tau);
+    w.refl = h->at<double>(L.off_refl);
+    w.colpart = h->at<double>(L.off_colpart);
+    w.wpart = h->at<double>(L.off_wpart);
+    w.T = h->at<double>(L.off_T);
+    w.W = h->at<double>(L.off_W);
+    w.counters = h->counters();
+    w.max_chunks = qr_max_chunks();
+    w.status = h->status();
+    h->mark(4, false);
+    GAP_TRY(dev(launch_geqrf(w, s)));
+    h->mark(4, true);
+
+    double *rhs = h->at<double>(L.off_rhs);
+    const double *qtb = A + L.M * L.lda;
+    h->mark(5, false);
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((L.M + 255) / 256)), dim3(256), 0, s, qtb, rhs, L.M);
+    GAP_TRY(dev(launch_trsv_upper(A, L.lda, L.M, rhs, c_out, h->status(), s)));
+    h->mark(5, true);
+    GAP_TRY(dev(launch_sumsq(qtb + L.M, L.N, h->misc(), h->misc() + 1, h->counters() + 8, s)));
+    h->state = ST_SOLVED;
+    if (info)
+        return gap_sync(h, info);
+    return GAP_OK;
+}
+
+gap_status gap_predict(gap_handle h, const double *x_atoms, int64_t n_atoms, const int64_t *offsets,
+                       int64_t n_configs, const double *c, double *y_out)
+{
+    if (!h || !x_atoms || !offsets || !c || !y_out || n_atoms < 0 || n_configs < 1)
+        return GAP_EINVAL;
+    if (h->state < ST_BUILT || !h->x_sparse)
+        return GAP_ESTATE;
+    const double sw2 = h->p.sigma_w * h->p.sigma_w;
+    return dev(launch_predict(x_atoms, n_atoms, offsets, n_configs, h->x_sparse, h->L.M, h->p.d, h->p.zeta,
+                              sw2, c, y_out, h->stream));
+}
+
+gap_status gap_layout(gap_handle h, gap_layout_info *out)
+{
+    if (!h || !out)
+        return GAP_EINVAL;
+    if (h->state < ST_BUILT)
+        return GAP_ESTATE;
+    out->A_aug = h->A();
+    out->lda = h->L.lda;
+    out->ncols = h->L.ncols;
+    out->N = h->L.N;
+    out->M = h->L.M;
+    out->n_atoms = h->L.n_atoms;
+    out->tau = h->at<double>(h->L.off_tau);
+    out->device_status = h->status();
+    return GAP_OK;
+}
+
+gap_status gap_stage_times(gap_handle h, float *ms, int n)
+{
+    if (!h || !ms || n < 0)
+        return GAP_EINVAL;
+    if (hipStreamSynchronize(h->stream) != hipSuccess)
+        return GAP_EDEVICE;
+    for (int i = 0; i < n && i < N_STAGES; ++i) {
+        ms[i] = 0.0f;
+        if (h->timing && h->timed[i]) {
+            float v = 0.0f;
+            if (hipEventElapsedTime(&v, h->ev[2 * i], h->ev[2 * i + 1]) == hipSuccess)
+                ms[i] = v;
+        }
+    }
+    return GAP_OK;
+}
+
+gap_status gap_destroy(gap_handle h)
+{
+    if (!h)
+        return GAP_EINVAL;
+    if (h->timing)
+        for (int i = 0; i < 2 * N_STAGES; ++i)
+            if (h->ev[i])
+                (void)hipEventDestroy(h->ev[i]);
+    delete h;
+    return GAP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,233 @@
+// Shared device helpers of the GAP fit library (gfx950 / CDNA4 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define DEV __device__ __forceinline__
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Device status word values (same numbering as gap_status).
+enum : int32_t {
+    DST_OK = 0,
+    DST_EINVAL = 1,
+    DST_ENOTPD = 3,
+    DST_ENONFINITE = 4,
+    DST_ENOCONV = 5,
+};
+
+// Record the first failure seen on the device; later ones do not overwrite it.
+DEV void set_status(int32_t *status, int32_t code)
+{
+    atomicCAS(reinterpret_cast<int *>(status), 0, code);
+}
+
+// ---------------------------------------------------------------------------
+// "Last workgroup" completion pattern: every workgroup publishes its partial
+// results, then one arrival counter tells the last one that all partials are
+// visible.  The counter is reset by that last workgroup, ready for the next
+// launch that uses it.  Returns true in every thread of the last workgroup.
+// ---------------------------------------------------------------------------
+DEV bool arrive_last(unsigned *counter, unsigned nblocks, int *flag_lds)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        int last = (prev == nblocks - 1);
+        if (last)
+            __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *flag_lds = last;
+    }
+    __syncthreads();
+    int last = *flag_lds;
+    if (last)
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);  // see the other workgroups' partials
+    return last != 0;
+}
+
+// Publish this workgroup's global writes before it arrives (all threads call).
+DEV void release_writes() { __atomic_thread_fence(__ATOMIC_RELEASE); }
+
+// Wave-wide sum with a fixed butterfly order (deterministic).
+DEV double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 MFMA tile machinery.
+//
+// A workgroup computes a BM x BN tile C = sum_k Aop(m, k) * Bop(n, k).  Both
+// operands are staged in LDS "K-major": As[k * LDA + m], Bs[k * LDB + n].  The
+// WM x WN waves each own a TM x TN sub-tile made of FM x FN blocks of the
+// 16x16x4 FP64 MFMA.  For v_mfma_f64_16x16x4f64, lane l supplies A(l%16, l/16)
+// and B(l/16, l%16); accumulator element e of lane l is C(4*e + l/16, l%16)
+// (measured on gfx950).
+// ---------------------------------------------------------------------------
+template <int BM_, int BN_, int BK_, int WM_, int WN_>
+struct TileShape {
+    static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
+    static constexpr int NT = WM * WN * 64;
+    static constexpr int TM = BM / WM, TN = BN / WN;
+    static constexpr int FM = TM / 16, FN = TN / 16;
+    static constexpr int PAD = 4;
+    static constexpr int LDA = BM + PAD, LDB = BN + PAD;
+    static constexpr int A_ELEMS = BK * LDA, B_ELEMS = BK * LDB;
+    static constexpr int STAGE = A_ELEMS + B_ELEMS;
+    static_assert(TM % 16 == 0 && TN % 16 == 0, "wave tile must be whole MFMA blocks");
+    static_assert(BK % 4 == 0, "BK must be a multiple of the MFMA K (4)");
+};
+
+template <class S>
+DEV void zero_acc(d4 (&acc)[S::FM][S::FN])
+{
+#pragma unroll
+    for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < S::FN; ++j)
+            acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+}
+
+template <class S>
+DEV void mma_stage(const double *__restrict__ As, const double *__restrict__ Bs,
+                   d4 (&acc)[S::FM][S::FN], int wm, int wn, int lane)
+{
+#pragma unroll
+    for (int kk = 0; kk < S::BK; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        double a[S::FM], b[S::FN];
+#pragma unroll
+        for (int i = 0; i < S::FM; ++i)
+            a[i] = As[kr * S::LDA + wm * S::TM + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < S::FN; ++j)
+            b[j] = Bs[kr * S::LDB + wn * S::TN + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+            for (int j = 0; j < S::FN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+// Row / column (within the workgroup tile) of accumulator element e.
+template <class S>
+DEV int acc_row(int wm, int i, int lane, int e) { return wm * S::TM + i * 16 + 4 * e + (lane >> 4); }
+template <class S>
+DEV int acc_col(int wn, int j, int lane) { return wn * S::TN + j * 16 + (lane & 15); }
+
+// Integer power by repeated multiplication, p = g^zeta (zeta >= 1).
+DEV double ipow(double g, int zeta)
+{
+    double p = g;
+    for (int z = 1; z < zeta; ++z)
+        p *= g;
+    return p;
+}
+
+// Map a hardware workgroup id to a logical id so that consecutive logical ids
+// run on the same XCD (workgroups are dispatched to the 8 XCDs round-robin).
+// total_pad must be a multiple of 8.
+DEV int64_t xcd_remap(int64_t w, int64_t total_pad)
+{
+    const int64_t per = total_pad >> 3;
+    return (w & 7) * per + (w >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// Generic LDS-staged MFMA tile product over a K range [0, K):
+//   acc(m, n) += sum_k fa(m, k) * fb(n, k)
+// fa/fb return the operand value (0 outside the valid range).  A_KC / B_KC
+// say whether consecutive k of one row are contiguous in memory (each thread
+// then reads a run along k); otherwise consecutive rows are contiguous (each
+// thread reads a run of rows at one k).  Double-buffered: one barrier per
+// BK-slice, the next slice's global loads in flight during the MFMAs.
+// ---------------------------------------------------------------------------
+template <class S, bool A_KC, bool B_KC, class FA, class FB>
+DEV void gemm_tile(d4 (&acc)[S::FM][S::FN], double *lds, int64_t K, FA fa, FB fb)
+{
+    constexpr int VA = S::BM * S::BK / S::NT;
+    constexpr int VB = S::BN * S::BK / S::NT;
+    static_assert(VA >= 1 && VB >= 1, "tile too small for the thread count");
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave / S::WN, wn = wave % S::WN;
+    double ra[VA], rb[VB];
+    auto load = [&](int64_t k0) {
+        if constexpr (A_KC) {
+            constexpr int TPR = S::BK / VA;
+            const int row = t / TPR, kb = (t % TPR) * VA;
+#pragma unroll
+            for (int e = 0; e < VA; ++e)
+                ra[e] = fa(row, k0 + kb + e);
+        } else {
+            constexpr int TPK = S::BM / VA;
+            const int k = t / TPK, r0 = (t % TPK) * VA;
+#pragma unroll
+            for (int e = 0; e < VA; ++e)
+                ra[e] = fa(r0 + e, k0 + k);
+        }
+        if constexpr (B_KC) {
+            constexpr int TPR = S::BK / VB;
+            const int row = t / TPR, kb = (t % TPR) * VB;
+#pragma unroll
+            for (int e = 0; e < VB; ++e)
+                rb[e] = fb(row, k0 + kb + e);
+        } else {
+            constexpr int TPK = S::BN / VB;
+            const int k = t / TPK, r0 = (t % TPK) * VB;
+#pragma unroll
+            for (int e = 0; e < VB; ++e)
+                rb[e] = fb(r0 + e, k0 + k);
+        }
+    };
+    auto store = [&](double *As, double *Bs) {
+        if constexpr (A_KC) {
+            constexpr int TPR = S::BK / VA;
+            const int row = t / TPR, kb = (t % TPR) * VA;
+#pragma unroll
+            for (int e = 0; e < VA; ++e)
+                As[(kb + e) * S::LDA + row] = ra[e];
+        } else {
+            constexpr int TPK = S::BM / VA;
+            const int k = t / TPK, r0 = (t % TPK) * VA;
+#pragma unroll
+            for (int e = 0; e < VA; ++e)
+                As[k * S::LDA + r0 + e] = ra[e];
+        }
+        if constexpr (B_KC) {
+            constexpr int TPR = S::BK / VB;
+            const int row = t / TPR, kb = (t % TPR) * VB;
+#pragma unroll
+            for (int e = 0; e < VB; ++e)
+                Bs[(kb + e) * S::LDB + row] = rb[e];
+        } else {
+            constexpr int TPK = S::BN / VB;
+            const int k = t / TPK, r0 = (t % TPK) * VB;
+#pragma unroll
+            for (int e = 0; e < VB; ++e)
+                Bs[k * S::LDB + r0 + e] = rb[e];
+        }
+    };
+    const int64_t nk = (K + S::BK - 1) / S::BK;
+    if (nk <= 0)
+        return;
+    load(0);
+    store(lds, lds + S::A_ELEMS);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        double *cur = lds + (kt & 1) * S::STAGE;
+        double *nxt = lds + ((kt + 1) & 1) * S::STAGE;
+        const bool more = kt + 1 < nk;
+        if (more)
+            load((kt + 1) * S::BK);
+        mma_stage<S>(cur, cur + S::A_ELEMS, acc, wm, wn, lane);
+        if (more)
+            store(nxt, nxt + S::A_ELEMS);
+        __syncthreads();
+    }
+}

@@ -1,0 +1,92 @@
+// Internal kernel interfaces of the GAP fit library.  Every launcher enqueues
+// on the given stream and returns the launch error (hipSuccess when none).
+#pragma once
+
+#include "common.h"
+
+namespace gap {
+
+// ----------------------------------------------------------------- K_NM / K_MM
+constexpr int KNM_BM = 256;       // atoms per chunk (GEMM rows)
+constexpr int KNM_BN = 128;       // sparse points per tile (GEMM columns)
+constexpr int KNM_CAP = KNM_BM;   // atom capacity of a packed tile
+constexpr int KNM_MAX_SEG = 256;  // configurations per tile
+
+struct KnmArgs {
+    const double *X;           // [rows x d] row-major descriptors
+    const int64_t *offsets;    // [N+1] CSR offsets; nullptr = unit segments (row r is segment r)
+    const int32_t *tile_cfg;   // [n_tiles+1] first configuration of each tile (from the plan)
+    const int32_t *n_tiles_dev;
+    int64_t n_rows_unit;       // unit segments: number of rows
+    const double *XM;          // [M x d] sparse points
+    int64_t M;
+    int d, zeta;
+    double sw2;                // sigma_w^2
+    const double *sigma;       // [N] or nullptr: the segment sum is divided by sigma
+    double *out;               // column-major: out[col * ldo + row_off + segment]
+    int64_t ldo, row_off;
+    double jitter;             // unit segments: added where segment == column
+    int upper_only;            // unit segments: write 0 where segment > column
+    int64_t n_ct, total_pad;   // filled by launch_knm
+    int32_t *status;
+};
+
+int64_t knm_max_tiles(int64_t N, int64_t n_atoms);
+hipError_t launch_plan_tiles(const int64_t *offsets, int64_t N, int64_t n_atoms, int32_t *tile_cfg,
+                             int32_t *n_tiles, int64_t max_tiles, int32_t *status, hipStream_t s);
+hipError_t launch_knm(KnmArgs a, int64_t max_tiles, hipStream_t s);
+
+// --------------------------------------------------------------------- predict
+hipError_t launch_predict(const double *X, int64_t n_atoms, const int64_t *offsets, int64_t N,
+                          const double *XM, int64_t M, int d, int zeta, double sw2, const double *c,
+                          double *y, hipStream_t s);
+
+// ------------------------------------------------------------------- Cholesky
+constexpr int CHOL_NB = 64;
+// In-place upper Cholesky K = U^T U of the n x n matrix at U (column-major,
+// leading dimension ld; only the upper triangle is read, U written there, the
+// strictly lower part of each diagonal block zeroed).  First non-positive
+// pivot -> status DST_ENOTPD.
+hipError_t launch_potrf_upper(double *U, int64_t ld, int64_t n, int32_t *status, hipStream_t s);
+
+// ------------------------------------------------------------ Householder QR
+constexpr int QR_NB = 64;        // panel width
+constexpr int QR_ROWS_PER_WG = 256;
+
+struct QrWork {
+    double *A;        // column-major [lda x ncols], factor columns 0..n-1, apply to n..ncols-1
+    int64_t lda, m, n, ncols;
+    double *tau;      // [n]
+    double *refl;     // [2 * QR_NB] per-column reflector scale / beta (panel-local)
+    double *colpart;  // [max_col_wgs * (QR_NB + 1)] column-step partials
+    double *wpart;    // [max_chunks * QR_NB * (QR_NB + ncols)] split-K partials
+    double *T;        // [QR_NB * QR_NB]
+    double *W;        // [QR_NB * ncols] (T^T V^T C), row-major by panel column
+    unsigned *counters;  // [4] arrival counters (zero-initialised)
+    int64_t max_chunks;
+    int32_t *status;
+};
+int64_t qr_max_chunks();
+int64_t qr_max_col_wgs(int64_t m);
+hipError_t launch_geqrf(const QrWork &w, hipStream_t s);
+
+// -------------------------------------------------------- triangular solve
+// Solve R c = rhs for the n x n upper triangle of R (column-major, ld); rhs
+// [n] is overwritten (used as work), c [n] output.  tail/tail_n: optional
+// (tail != nullptr) sum of squares of tail[0..tail_n) into *tail_out.
+hipError_t launch_trsv_upper(const double *R, int64_t ld, int64_t n, double *rhs, double *c,
+                             int32_t *status, hipStream_t s);
+hipError_t launch_sumsq(const double *x, int64_t n, double *out, double *part, unsigned *counter,
+                        hipStream_t s);
+
+// ---------------------------------------------------------------- utilities
+// b = [y / sigma ; 0] into column `col` of the column-major A (lda rows).
+hipError_t launch_assemble_b(const double *y, const double *sigma, int64_t N, double *bcol,
+                             int64_t lda, hipStream_t s);
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
+// Zero rows [r0, r1) of columns [c0, c1) of a column-major matrix.
+hipError_t launch_zero_block(double *A, int64_t lda, int64_t r0, int64_t r1, int64_t c0, int64_t c1,
+                             hipStream_t s);
+hipError_t launch_check_finite(const double *x, int64_t n, int32_t *status, hipStream_t s);
+
+}  // namespace gap

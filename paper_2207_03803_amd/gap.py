@@ -1,0 +1,195 @@
+"""Thin ctypes binding of libgap.so (declared in include/gap.h).
+
+Argument marshalling only: every step of the fit runs in the library's HIP
+kernels.  PyTorch supplies device memory (tensor data pointers) and streams.
+The library must have been built (``python -m paper_2207_03803_amd.build``);
+loading fails loudly otherwise, and nothing here falls back to a CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgap.so")
+
+GAP_OK, GAP_EINVAL, GAP_ENOMEM, GAP_ENOTPD, GAP_ENONFINITE, GAP_ENOCONV, GAP_EDEVICE, GAP_ESTATE = range(8)
+GAP_FP64, GAP_MIXED_FP32 = 0, 1
+GAP_FLAG_TIMING = 1
+
+# Every entry point include/gap.h declares.
+EXPORTS = ["gap_create", "gap_workspace_bytes", "gap_bind_workspace", "gap_build_knm", "gap_solve",
+           "gap_predict", "gap_sync", "gap_layout", "gap_stage_times", "gap_status_string",
+           "gap_destroy"]
+
+STAGES = ["knm", "kmm", "cholesky", "assemble_b", "qr", "trsv", "refine", "reserved"]
+
+
+class GapParams(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("zeta", ctypes.c_int32), ("sigma_w", ctypes.c_double),
+                ("jitter", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("max_refine_iters", ctypes.c_int32), ("refine_tol", ctypes.c_double),
+                ("flags", ctypes.c_uint32)]
+
+
+class GapSolveInfo(ctypes.Structure):
+    _fields_ = [("device_status", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
+                ("residual_norm2", ctypes.c_double), ("grad_rel", ctypes.c_double),
+                ("est_err", ctypes.c_double)]
+
+
+class GapLayoutInfo(ctypes.Structure):
+    _fields_ = [("A_aug", ctypes.c_void_p), ("lda", ctypes.c_int64), ("ncols", ctypes.c_int64),
+                ("N", ctypes.c_int64), ("M", ctypes.c_int64), ("n_atoms", ctypes.c_int64),
+                ("tau", ctypes.c_void_p), ("device_status", ctypes.c_void_p)]
+
+
+class GapError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+_lib = None
+
+
+def lib():
+    """Load libgap.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2207_03803_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    L.gap_create.argtypes = [ctypes.POINTER(GapParams), P, ctypes.POINTER(P)]
+    L.gap_workspace_bytes.argtypes = [ctypes.POINTER(GapParams), I64, I64, I64]
+    L.gap_workspace_bytes.restype = ctypes.c_size_t
+    L.gap_bind_workspace.argtypes = [P, P, ctypes.c_size_t]
+    L.gap_build_knm.argtypes = [P, P, I64, P, I64, P, I64, P]
+    L.gap_solve.argtypes = [P, P, P, ctypes.POINTER(GapSolveInfo)]
+    L.gap_predict.argtypes = [P, P, I64, P, I64, P, P]
+    L.gap_sync.argtypes = [P, ctypes.POINTER(GapSolveInfo)]
+    L.gap_layout.argtypes = [P, ctypes.POINTER(GapLayoutInfo)]
+    L.gap_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_float), I32]
+    L.gap_status_string.argtypes = [I32]
+    L.gap_status_string.restype = ctypes.c_char_p
+    L.gap_destroy.argtypes = [P]
+    for n in ("gap_create", "gap_bind_workspace", "gap_build_knm", "gap_solve", "gap_predict", "gap_sync",
+              "gap_layout", "gap_stage_times", "gap_destroy"):
+        getattr(L, n).restype = I32
+    _lib = L
+    return L
+
+
+def status_string(s: int) -> str:
+    return lib().gap_status_string(int(s)).decode()
+
+
+def params(d, zeta, sigma_w=1.0, jitter=1e-8, precision=GAP_FP64, max_refine_iters=20,
+           refine_tol=1e-12, flags=0) -> GapParams:
+    return GapParams(d, zeta, sigma_w, jitter, precision, max_refine_iters, refine_tol, flags)
+
+
+def workspace_bytes(p: GapParams, n_configs: int, n_atoms: int, M: int) -> int:
+    return int(lib().gap_workspace_bytes(ctypes.byref(p), n_configs, n_atoms, M))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check(s, where):
+    if s != GAP_OK:
+        raise GapError(s, where)
+
+
+class Handle:
+    """One fit context: gap_create / gap_bind_workspace / gap_destroy.
+
+    Tensor arguments are torch CUDA tensors (float64 / int64, contiguous); the
+    stream defaults to torch's current stream at creation.
+    """
+
+    def __init__(self, p: GapParams, stream=None):
+        import torch
+
+        self.p = p
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(lib().gap_create(ctypes.byref(p), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+               "gap_create")
+        self.h = h
+        self.ws = None
+
+    def bind(self, ws):
+        self.ws = ws
+        _check(lib().gap_bind_workspace(self.h, _ptr(ws), ws.numel() * ws.element_size()),
+               "gap_bind_workspace")
+
+    def alloc_workspace(self, n_configs, n_atoms, M):
+        import torch
+
+        nbytes = workspace_bytes(self.p, n_configs, n_atoms, M)
+        if nbytes == 0:
+            raise GapError(GAP_EINVAL, "gap_workspace_bytes")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.bind(ws)
+        return ws
+
+    def build_knm(self, X, offsets, XM, sigma):
+        _check(lib().gap_build_knm(self.h, _ptr(X), X.shape[0], _ptr(offsets), offsets.numel() - 1,
+                                   _ptr(XM), XM.shape[0], _ptr(sigma)), "gap_build_knm")
+
+    def solve(self, y, c_out, info=True):
+        inf = GapSolveInfo() if info else None
+        s = lib().gap_solve(self.h, _ptr(y), _ptr(c_out), ctypes.byref(inf) if info else None)
+        _check(s, "gap_solve")
+        return inf
+
+    def predict(self, X, offsets, c, y_out):
+        _check(lib().gap_predict(self.h, _ptr(X), X.shape[0], _ptr(offsets), offsets.numel() - 1, _ptr(c),
+                                 _ptr(y_out)), "gap_predict")
+
+    def sync(self):
+        inf = GapSolveInfo()
+        s = lib().gap_sync(self.h, ctypes.byref(inf))
+        return s, inf
+
+    def layout(self) -> GapLayoutInfo:
+        out = GapLayoutInfo()
+        _check(lib().gap_layout(self.h, ctypes.byref(out)), "gap_layout")
+        return out
+
+    def stage_times(self):
+        arr = (ctypes.c_float * 8)()
+        _check(lib().gap_stage_times(self.h, arr, 8), "gap_stage_times")
+        return dict(zip(STAGES, [float(v) for v in arr]))
+
+    def A_view(self):
+        """The workspace's augmented matrix as a torch view [ncols, lda] (column-major)."""
+        import torch
+
+        lay = self.layout()
+        off = lay.A_aug - self.ws.data_ptr()
+        n = lay.lda * lay.ncols
+        flat = self.ws[off:off + 8 * n].view(torch.float64)
+        return flat.view(lay.ncols, lay.lda), lay
+
+    def tau_view(self):
+        import torch
+
+        lay = self.layout()
+        off = lay.tau - self.ws.data_ptr()
+        return self.ws[off:off + 8 * lay.M].view(torch.float64)
+
+    def close(self):
+        if self.h:
+            lib().gap_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

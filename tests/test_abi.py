@@ -1,0 +1,66 @@
+"""Host-side checks of the C ABI: the library loads and exports every symbol
+include/gap.h declares; pure host functions behave (no GPU needed)."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+from paper_2207_03803_amd import gap
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "gap.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*(gap_[a-z_]+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_binding_exports():
+    assert _declared() == sorted(gap.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = gap.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    for s in range(8):
+        assert gap.status_string(s)
+    assert gap.status_string(gap.GAP_ENOTPD).startswith("K_MM")
+
+
+def test_create_rejects_bad_params_without_a_gpu():
+    lib = gap.lib()
+    h = ctypes.c_void_p()
+    for p in (gap.params(0, 2), gap.params(8, 0), gap.params(8, 9), gap.params(8, 2, sigma_w=0.0),
+              gap.params(8, 2, jitter=-1.0), gap.params(8, 2, precision=7)):
+        assert lib.gap_create(ctypes.byref(p), None, ctypes.byref(h)) == gap.GAP_EINVAL
+
+
+def test_workspace_bytes_bad_inputs():
+    p = gap.params(64, 2)
+    assert gap.workspace_bytes(p, 0, 10, 10) == 0
+    assert gap.workspace_bytes(p, 10, 10, 0) == 0
+    assert gap.workspace_bytes(gap.params(64, 0), 10, 10, 10) == 0
+
+
+def test_workspace_holds_the_paper_sized_stacked_matrix():
+    """A of (N+M) x M in FP64 (the printed element counts) plus b, within the bound workspace."""
+    cases = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_shapes.json")))["cases"]
+    p = gap.params(400, 2)
+    for c in cases:
+        N, M = c["N"], c["M"]
+        nb = gap.workspace_bytes(p, N, 40 * N, M)
+        assert nb >= 8 * c["n_A"] + 8 * (N + M)
+        # overhead beyond [A | b] (padding, QR scratch, tile plan) stays small
+        assert nb <= 1.05 * 8 * (N + M + 64) * (M + 1)
+
+
+@pytest.mark.parametrize("N,M", [(200, 256), (100_000, 10_000)])
+def test_workspace_fits_one_mi355x(N, M):
+    nb = gap.workspace_bytes(gap.params(400, 4), N, 40 * N, M)
+    assert nb < 288e9 * 0.5

@@ -1,0 +1,167 @@
+"""GPU parity tests of the FP64 path (K_NM build, Cholesky, Householder QR,
+back-substitution, predict) against the CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_03803_amd import synth
+from tests.gpu_helpers import GpuFit, U, log, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL_C = 1e-10          # FP64 path: relative error of c versus the oracle
+TOL_K = 1e-13          # elementwise relative error of Sigma^-1/2 K_NM
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
+
+
+def _case(orc, n_configs, atoms, d, M, zeta, seed, sigma_per_atom=1e-3, jitter=1e-8):
+    inp = synth.make_fit_inputs(n_configs=n_configs, atoms=atoms, d=d, M=M, seed=seed,
+                                sigma_per_atom=sigma_per_atom)
+    y = oracle.targets(orc, inp, zeta)
+    ref = orc.fit(inp.X, inp.offsets, inp.XM, inp.sigma, y, zeta, jitter=jitter, keep=True)
+    assert ref.status == 0
+    return inp, y, ref
+
+
+def _compare_fit(orc, inp, y, ref, zeta, jitter=1e-8, check_blocks=True):
+    g = GpuFit(inp.X, inp.offsets, inp.XM, inp.sigma, y, zeta, jitter=jitter)
+    g.build()
+    if check_blocks:
+        top, low = g.A_top_and_lower()
+        expect_top = ref.Knm / inp.sigma[:, None]
+        relK = np.max(np.abs(top - expect_top) / np.abs(expect_top))
+        log(f"  K_NM/sigma max elementwise rel err {relK:.2e}")
+        assert relK <= TOL_K
+        Lt = ref.L.T
+        errL = np.linalg.norm(low - Lt) / np.linalg.norm(Lt)
+        log(f"  L^T rel err {errL:.2e}")
+        assert np.all(np.tril(low, -1) == 0.0)
+        assert errL <= 1e-12
+    c, info = g.solve()
+    assert info.device_status == 0
+    err = rel(c, ref.c)
+    pred_err = rel(ref.Knm @ c, ref.Knm @ ref.c)
+    loss_err = abs(info.residual_norm2 - ref.loss_tail) / ref.loss_tail
+    log(f"  c rel err {err:.2e}; prediction-space {pred_err:.2e}; loss {loss_err:.2e}")
+    assert err <= TOL_C
+    assert pred_err <= 1e-12
+    assert loss_err <= 1e-10
+    # |diag R| against the oracle (R is unique up to row signs)
+    Av, lay = g.h.A_view()
+    dR = np.abs(np.diag(Av[:g.M, :g.M].T.cpu().numpy()))
+    assert np.max(np.abs(dR - np.abs(ref.diagR)) / np.abs(ref.diagR)) <= 1e-9
+    return g, c
+
+
+@pytest.fixture(scope="module")
+def orc_m():
+    return oracle.Oracle()
+
+
+def test_tiny_workload_parity(orc_m):
+    w = synth.WORKLOADS["tiny_fp64"]
+    log("tiny_fp64: 200 configs, d=64, M=256, zeta=2")
+    inp, y, ref = _case(orc_m, 200, (8, 64), 64, 256, 2, seed=0)
+    _compare_fit(orc_m, inp, y, ref, 2, jitter=w["jitter"])
+
+
+@pytest.mark.parametrize("n_configs,atoms,d,M,zeta,seed", [
+    (37, (1, 5), 13, 45, 3, 1),      # tiny odd shapes: M < one QR panel, d not a tile multiple
+    (150, (8, 64), 64, 200, 2, 2),    # ragged M (3 panels + 8 columns)
+    (400, (16, 64), 96, 333, 4, 3),   # several K_NM tiles, ragged everything
+    (90, (1, 1), 32, 90, 2, 4),       # one atom per configuration, M = N
+])
+def test_ragged_shapes_parity(orc_m, n_configs, atoms, d, M, zeta, seed):
+    log(f"ragged: N={n_configs} atoms={atoms} d={d} M={M} zeta={zeta}")
+    inp, y, ref = _case(orc_m, n_configs, atoms, d, M, zeta, seed)
+    _compare_fit(orc_m, inp, y, ref, zeta)
+
+
+def test_large_and_empty_configurations(orc_m):
+    """Configurations larger than one 256-atom chunk, and empty ones."""
+    rng = np.random.default_rng(9)
+    counts = np.array([3, 0, 300, 17, 0, 0, 600, 64, 1, 257, 256, 5] * 3, dtype=np.int64)
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    d, M, zeta = 24, 70, 2
+    X = np.abs(rng.standard_normal((offsets[-1], d)))
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    XM = X[rng.choice(offsets[-1], M, replace=False)]
+    sigma = 1e-3 * np.maximum(counts, 1).astype(float)
+    y = orc_m.predict(X, offsets, XM, rng.standard_normal(M), zeta) + sigma * rng.standard_normal(len(counts))
+    log("large/empty configurations: counts up to 600 atoms, empty rows")
+    ref = orc_m.fit(X, offsets, XM, sigma, y, zeta, jitter=1e-8, keep=True)
+    assert ref.status == 0
+    g = GpuFit(X, offsets, XM, sigma, y, zeta)
+    g.build()
+    top, low = g.A_top_and_lower()
+    expect = ref.Knm / sigma[:, None]
+    nz = expect != 0
+    assert np.all(top[~nz] == 0.0)
+    assert np.max(np.abs(top[nz] - expect[nz]) / np.abs(expect[nz])) <= TOL_K
+    c, info = g.solve()
+    # empty configurations make zero rows: still a valid least-squares problem
+    assert rel(c, ref.c) <= TOL_C
+
+
+def test_mid_size_realistic_shape(orc_m):
+    """d=400, zeta=4 at a size the oracle finishes in seconds (several tiles, ragged M)."""
+    log("mid-size: N=2000 configs of 16..64 atoms, d=400, M=520, zeta=4")
+    inp, y, ref = _case(orc_m, 2000, (16, 64), 400, 520, 4, seed=5)
+    _compare_fit(orc_m, inp, y, ref, 4)
+
+
+def test_predict_parity(orc_m):
+    inp, y, ref = _case(orc_m, 150, (8, 64), 64, 200, 2, seed=6)
+    g = GpuFit(inp.X, inp.offsets, inp.XM, inp.sigma, y, 2)
+    c, info = g.run()
+    import torch
+
+    # new configurations, different sizes, including a 1-configuration batch
+    for n_cfg, seed in ((1, 20), (7, 21), (333, 22)):
+        q = synth.make_fit_inputs(n_configs=n_cfg, atoms=(8, 64), d=64, M=1, seed=seed)
+        expect = orc_m.predict(q.X, q.offsets, inp.XM, ref.c, 2)
+        out = torch.empty(n_cfg, dtype=torch.float64, device="cuda")
+        g.h.predict(to_dev(q.X), to_dev(q.offsets), to_dev(ref.c), out)
+        got = out.cpu().numpy()
+        e = np.max(np.abs(got - expect) / np.abs(expect))
+        log(f"  predict {n_cfg} configs: max rel err {e:.2e}")
+        assert e <= 1e-12
+    # on the training configurations, predict = K_NM c
+    out = torch.empty(inp.n_configs, dtype=torch.float64, device="cuda")
+    g.h.predict(g.X, g.offsets, g.c, out)
+    assert rel(out.cpu().numpy(), ref.Knm @ c) <= 1e-13
+
+
+def test_not_positive_definite_is_reported(orc_m):
+    inp, y, ref = _case(orc_m, 60, (8, 16), 16, 40, 2, seed=7)
+    XM = np.vstack([inp.XM[:39], inp.XM[:1]])  # duplicated sparse point, no jitter
+    g = GpuFit(inp.X, inp.offsets, XM, inp.sigma, y, 2, jitter=0.0)
+    g.build()
+    from paper_2207_03803_amd import gap
+
+    with pytest.raises(gap.GapError) as e:
+        g.solve()
+    assert e.value.status == gap.GAP_ENOTPD
+
+
+def test_bad_offsets_are_reported(orc_m):
+    inp, y, ref = _case(orc_m, 20, (8, 16), 16, 10, 2, seed=8)
+    offs = inp.offsets.copy()
+    offs[5], offs[6] = offs[6], offs[5]  # decreasing
+    g = GpuFit(inp.X, offs, inp.XM, inp.sigma, y, 2)
+    g.build()
+    s, info = g.h.sync()
+    from paper_2207_03803_amd import gap
+
+    assert s == gap.GAP_EINVAL
+
+
+def test_repeat_runs_are_bitwise_identical(orc_m):
+    inp, y, ref = _case(orc_m, 150, (8, 64), 64, 200, 2, seed=10)
+    g = GpuFit(inp.X, inp.offsets, inp.XM, inp.sigma, y, 2)
+    c1, _ = g.run()
+    c2, _ = g.run()
+    assert np.array_equal(c1, c2)
