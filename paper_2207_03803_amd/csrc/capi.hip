@@ -17,9 +17,11 @@ constexpr int N_STAGES = 8;
 enum State { ST_CREATED = 0, ST_BOUND = 1, ST_BUILT = 2, ST_SOLVED = 3 };
 
 struct Layout {
-    int64_t N = 0, M = 0, n_atoms = 0, m = 0, lda = 0, ncols = 0, max_tiles = 0, col_wgs = 0;
-    size_t off_A = 0, off_tau = 0, off_refl = 0, off_colpart = 0, off_wpart = 0, off_T = 0, off_W = 0,
-           off_rhs = 0, off_misc = 0, off_tiles = 0, off_counters = 0, off_status = 0, total = 0;
+    int64_t N = 0, M = 0, n_atoms = 0, m = 0, lda = 0, ncols = 0, max_tiles = 0;
+    TsqrTree tree;
+    size_t off_A = 0, off_tau = 0, off_wpart = 0, off_T = 0, off_U = 0, off_W = 0, off_ts_tiles = 0,
+           off_ts_X = 0, off_ts_tau = 0, off_rhs = 0, off_misc = 0, off_tiles = 0, off_counters = 0,
+           off_status = 0, total = 0;
 };
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -34,7 +36,7 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M)
     L.lda = (L.m + 63) / 64 * 64;
     L.ncols = M + 1;
     L.max_tiles = knm_max_tiles(N, n_atoms);
-    L.col_wgs = qr_max_col_wgs(L.m);
+    L.tree = tsqr_tree(L.m);
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
@@ -43,11 +45,13 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M)
     };
     L.off_A = take(sizeof(double) * (size_t)L.lda * (size_t)L.ncols);
     L.off_tau = take(sizeof(double) * (size_t)M);
-    L.off_refl = take(sizeof(double) * (2 * QR_NB + 2));
-    L.off_colpart = take(sizeof(double) * (size_t)L.col_wgs * (QR_NB + 1));
-    L.off_wpart = take(sizeof(double) * (size_t)qr_max_chunks() * QR_NB * (size_t)(QR_NB + L.ncols));
+    L.off_wpart = take(sizeof(double) * (size_t)qr_max_chunks() * QR_NB * (size_t)L.ncols);
     L.off_T = take(sizeof(double) * QR_NB * QR_NB);
+    L.off_U = take(sizeof(double) * QR_NB * QR_NB);
     L.off_W = take(sizeof(double) * QR_NB * (size_t)L.ncols);
+    L.off_ts_tiles = take(sizeof(double) * (size_t)L.tree.tiles_doubles);
+    L.off_ts_X = take(sizeof(double) * (size_t)L.tree.tiles_doubles);
+    L.off_ts_tau = take(sizeof(double) * (size_t)L.tree.tau_doubles);
     L.off_rhs = take(sizeof(double) * (size_t)M);
     L.off_misc = take(sizeof(double) * 512);
     L.off_tiles = take(sizeof(int32_t) * (size_t)(L.max_tiles + 2));
@@ -297,12 +301,14 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
     w.n = L.M;
     w.ncols = L.ncols;
     w.tau = h->at<double>(L.off_tau);
-    w.refl = h->at<double>(L.off_refl);
-    w.colpart = h->at<double>(L.off_colpart);
     w.wpart = h->at<double>(L.off_wpart);
     w.T = h->at<double>(L.off_T);
+    w.U = h->at<double>(L.off_U);
     w.W = h->at<double>(L.off_W);
-    w.counters = h->counters();
+    w.ts_tiles = h->at<double>(L.off_ts_tiles);
+    w.ts_X = h->at<double>(L.off_ts_X);
+    w.ts_tau = h->at<double>(L.off_ts_tau);
+    w.tree = L.tree;
     w.max_chunks = qr_max_chunks();
     w.status = h->status();
     h->mark(4, false);

@@ -51,23 +51,39 @@ hipError_t launch_potrf_upper(double *U, int64_t ld, int64_t n, int32_t *status,
 
 // ------------------------------------------------------------ Householder QR
 constexpr int QR_NB = 64;        // panel width
-constexpr int QR_ROWS_PER_WG = 256;
+constexpr int TS_ROWS = 256;     // rows of one TSQR tile
+constexpr int TS_FAN = 4;        // children per TSQR tree node
+constexpr int TS_MAX_LEVELS = 16;
+
+// TSQR tree storage for panels of up to m rows.  Level 0 has ceil(m/256)
+// nodes, level l+1 has ceil(n_l / 4).  Every node owns a 256 x 64 tile
+// (column-major inside the tile), 64 reflector weights and (levels >= 1) a
+// 256 x 64 block of the explicit Q.
+struct TsqrTree {
+    int levels = 0;
+    int64_t nodes[TS_MAX_LEVELS] = {};
+    int64_t tile_off[TS_MAX_LEVELS] = {};  // offsets in doubles into tiles / X
+    int64_t tau_off[TS_MAX_LEVELS] = {};   // offsets in doubles into tau
+    int64_t tiles_doubles = 0, tau_doubles = 0;
+};
+TsqrTree tsqr_tree(int64_t m);
 
 struct QrWork {
-    double *A;        // column-major [lda x ncols], factor columns 0..n-1, apply to n..ncols-1
+    double *A;        // column-major [lda x ncols]: factor columns 0..n-1, apply to n..ncols-1
     int64_t lda, m, n, ncols;
     double *tau;      // [n]
-    double *refl;     // [2 * QR_NB] per-column reflector scale / beta (panel-local)
-    double *colpart;  // [max_col_wgs * (QR_NB + 1)] column-step partials
-    double *wpart;    // [max_chunks * QR_NB * (QR_NB + ncols)] split-K partials
-    double *T;        // [QR_NB * QR_NB]
-    double *W;        // [QR_NB * ncols] (T^T V^T C), row-major by panel column
-    unsigned *counters;  // [4] arrival counters (zero-initialised)
+    double *wpart;    // [max_chunks * QR_NB * ncols] split-K partials of Y^T C
+    double *T;        // [QR_NB * QR_NB] compact-WY T of the current panel (row-major)
+    double *U;        // [QR_NB * QR_NB] LU factor of (Q - S) of the current panel
+    double *W;        // [QR_NB * ncols] T^T Y^T C, row-major by panel column
+    double *ts_tiles; // TsqrTree::tiles_doubles
+    double *ts_X;     // TsqrTree::tiles_doubles
+    double *ts_tau;   // TsqrTree::tau_doubles
+    TsqrTree tree;    // sized for m rows
     int64_t max_chunks;
     int32_t *status;
 };
 int64_t qr_max_chunks();
-int64_t qr_max_col_wgs(int64_t m);
 hipError_t launch_geqrf(const QrWork &w, hipStream_t s);
 
 // -------------------------------------------------------- triangular solve

@@ -111,15 +111,17 @@ __global__ __launch_bounds__(256) void chol_syrk_kernel(double *U, int64_t ld, i
     const int64_t ti = L - tj * (tj + 1) / 2;
     const int64_t r0 = k1 + ti * SS::BM, c0 = k1 + tj * SS::BN;
 
+    // The tile is computed transposed, acc(c, r), so that consecutive lanes
+    // update consecutive rows of the column-major matrix.
     d4 acc[SS::FM][SS::FN];
     zero_acc<SS>(acc);
     const double *P = U + k0;  // element (row x, p) = U[k0 + p][x] at x * ld + p
-    auto fa = [&](int m, int64_t p) -> double {
-        const int64_t x = r0 + m;
+    auto fa = [&](int mi, int64_t p) -> double {
+        const int64_t x = c0 + mi;
         return (x < n && p < kb) ? P[x * ld + p] : 0.0;
     };
-    auto fb = [&](int m, int64_t p) -> double {
-        const int64_t x = c0 + m;
+    auto fb = [&](int ni, int64_t p) -> double {
+        const int64_t x = r0 + ni;
         return (x < n && p < kb) ? P[x * ld + p] : 0.0;
     };
     gemm_tile<SS, true, true>(acc, lds, kb, fa, fb);
@@ -132,8 +134,8 @@ __global__ __launch_bounds__(256) void chol_syrk_kernel(double *U, int64_t ld, i
         for (int j = 0; j < SS::FN; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int64_t r = r0 + acc_row<SS>(wm, i, lane, e);
-                const int64_t c = c0 + acc_col<SS>(wn, j, lane);
+                const int64_t c = c0 + acc_row<SS>(wm, i, lane, e);
+                const int64_t r = r0 + acc_col<SS>(wn, j, lane);
                 if (r <= c && c < n)
                     U[c * ld + r] -= acc[i][j][e];
             }
