@@ -64,10 +64,18 @@ DEV double wave_sum(double v)
 //
 // A workgroup computes a BM x BN tile C = sum_k Aop(m, k) * Bop(n, k).  Both
 // operands are staged in LDS "K-major": As[k * LDA + m], Bs[k * LDB + n].  The
-// WM x WN waves each own a TM x TN sub-tile made of FM x FN blocks of the
-// 16x16x4 FP64 MFMA.  For v_mfma_f64_16x16x4f64, lane l supplies A(l%16, l/16)
-// and B(l/16, l%16); accumulator element e of lane l is C(4*e + l/16, l%16)
-// (measured on gfx950).
+// WM x WN waves each own a TM x TN sub-tile made of FM x FN blocks of 16x16.
+//
+// Each 16x16x4 block product is done with four v_mfma_f64_4x4x4_4b_f64
+// (measured on gfx950 at about twice the FP64 rate of v_mfma_f64_16x16x4_f64).
+// That instruction holds four independent 4x4x4 products in the lane groups
+// g = (l/4)%4: A(m, k) of block g at lane 16k + 4g + (m%4), B(k, n) at lane
+// 16k + 4g + (n%4), result (m, n) at lane 16(m%4) + 4g + (n%4).  With the A
+// register holding A(l%16, l/16) (rows 4g..4g+3 in group g) and the s-th B
+// register holding B(l/16, 4((g+s)%4) + l%4), instruction s computes the
+// 4x4 blocks (row group g, column group (g+s)%4); the four instructions
+// together cover the 16x16 block.  Accumulator element s of lane l is
+// C(4g + l/16, 4((g+s)%4) + l%4) with g = (l/4)%4 (layout measured on gfx950).
 // ---------------------------------------------------------------------------
 template <int BM_, int BN_, int BK_, int WM_, int WN_>
 struct TileShape {
@@ -75,11 +83,11 @@ struct TileShape {
     static constexpr int NT = WM * WN * 64;
     static constexpr int TM = BM / WM, TN = BN / WN;
     static constexpr int FM = TM / 16, FN = TN / 16;
-    static constexpr int PAD = 4;
+    static constexpr int PAD = 16;  // row offset of 32 banks between the k-rows read by one MFMA
     static constexpr int LDA = BM + PAD, LDB = BN + PAD;
     static constexpr int A_ELEMS = BK * LDA, B_ELEMS = BK * LDB;
     static constexpr int STAGE = A_ELEMS + B_ELEMS;
-    static_assert(TM % 16 == 0 && TN % 16 == 0, "wave tile must be whole MFMA blocks");
+    static_assert(TM % 16 == 0 && TN % 16 == 0, "wave tile must be whole 16x16 blocks");
     static_assert(BK % 4 == 0, "BK must be a multiple of the MFMA K (4)");
 };
 
@@ -93,6 +101,9 @@ DEV void zero_acc(d4 (&acc)[S::FM][S::FN])
             acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 }
 
+// Column (within a 16-wide block) that B register s of lane l carries.
+DEV int bcol16(int lane, int s) { return 4 * ((((lane >> 2) & 3) + s) & 3) + (lane & 3); }
+
 template <class S>
 DEV void mma_stage(const double *__restrict__ As, const double *__restrict__ Bs,
                    d4 (&acc)[S::FM][S::FN], int wm, int wn, int lane)
@@ -100,26 +111,34 @@ DEV void mma_stage(const double *__restrict__ As, const double *__restrict__ Bs,
 #pragma unroll
     for (int kk = 0; kk < S::BK; kk += 4) {
         const int kr = kk + (lane >> 4);
-        double a[S::FM], b[S::FN];
+        double a[S::FM];
 #pragma unroll
         for (int i = 0; i < S::FM; ++i)
             a[i] = As[kr * S::LDA + wm * S::TM + i * 16 + (lane & 15)];
 #pragma unroll
-        for (int j = 0; j < S::FN; ++j)
-            b[j] = Bs[kr * S::LDB + wn * S::TN + j * 16 + (lane & 15)];
+        for (int j = 0; j < S::FN; ++j) {
+            double b[4];
 #pragma unroll
-        for (int i = 0; i < S::FM; ++i)
+            for (int s = 0; s < 4; ++s)
+                b[s] = Bs[kr * S::LDB + wn * S::TN + j * 16 + bcol16(lane, s)];
 #pragma unroll
-            for (int j = 0; j < S::FN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+            for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    acc[i][j][s] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[i], b[s], acc[i][j][s], 0, 0, 0);
+        }
     }
 }
 
 // Row / column (within the workgroup tile) of accumulator element e.
 template <class S>
-DEV int acc_row(int wm, int i, int lane, int e) { return wm * S::TM + i * 16 + 4 * e + (lane >> 4); }
+DEV int acc_row(int wm, int i, int lane, int e)
+{
+    (void)e;
+    return wm * S::TM + i * 16 + 4 * ((lane >> 2) & 3) + (lane >> 4);
+}
 template <class S>
-DEV int acc_col(int wn, int j, int lane) { return wn * S::TN + j * 16 + (lane & 15); }
+DEV int acc_col(int wn, int j, int lane, int e) { return wn * S::TN + j * 16 + bcol16(lane, e); }
 
 // Integer power by repeated multiplication, p = g^zeta (zeta >= 1).
 DEV double ipow(double g, int zeta)

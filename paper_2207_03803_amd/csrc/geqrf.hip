@@ -25,7 +25,9 @@ namespace gap {
 constexpr int NB = QR_NB;
 constexpr int TR = TS_ROWS;
 constexpr int TILE = TR * NB;  // doubles per tile
-constexpr int SLOTS = TR / 4;  // rows held per thread (row = 4 * slot + part)
+constexpr int NPART = 8;           // threads per tile column
+constexpr int TS_NT = NB * NPART;  // threads of the TSQR kernels
+constexpr int SLOTS = TR / NPART;  // rows held per thread (row = NPART * slot + part)
 constexpr int64_t MAX_CHUNKS = 64;
 
 int64_t qr_max_chunks() { return MAX_CHUNKS; }
@@ -78,26 +80,27 @@ DEV void leaf_rows(int64_t i, int64_t n0, int64_t mk, int64_t &lo, int64_t &hi)
     hi = ((i + 1) * mk) / n0;
 }
 
-// Sum over the 4 consecutive lanes that hold one column (deterministic).
-DEV double quad_sum(double v)
+// Sum over the NPART consecutive lanes that hold one column (deterministic).
+DEV double col_sum(double v)
 {
     v += __shfl_xor(v, 1, 64);
     v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
     return v;
 }
 
 // ---------------------------------------------------------------------------
 // Householder QR of one 256 x pw tile held in registers.  Thread t owns
-// column q = t / 4 and the rows r = 4 * slot + (t % 4).  Level 0 reads rows
+// column q = t / 8 and the rows r = 8 * slot + (t % 8).  Level 0 reads rows
 // of the panel; level l >= 1 stacks the R factors of up to 4 children.  The
 // factored tile (R above the diagonal, v below) and tau go to the tree.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void tsqr_factor_kernel(QrWork w, int64_t j0, int pw, int level,
+__global__ __launch_bounds__(TS_NT) void tsqr_factor_kernel(QrWork w, int64_t j0, int pw, int level,
                                                           int64_t n_level, int64_t n_prev, int64_t mk)
 {
     __shared__ double vbuf[2][TR];
     __shared__ double taus[NB];
-    const int t = threadIdx.x, q = t >> 2, part = t & 3;
+    const int t = threadIdx.x, q = t / NPART, part = t % NPART;
     const int64_t node = blockIdx.x;
     double x[SLOTS];
     if (level == 0) {
@@ -107,7 +110,7 @@ __global__ __launch_bounds__(256) void tsqr_factor_kernel(QrWork w, int64_t j0, 
         const int64_t nr = hi - lo;
 #pragma unroll
         for (int i = 0; i < SLOTS; ++i) {
-            const int r = 4 * i + part;
+            const int r = NPART * i + part;
             x[i] = (q < pw && r < nr) ? col[r] : 0.0;
         }
     } else {
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(256) void tsqr_factor_kernel(QrWork w, int64_t j0, 
         const int64_t nc = (n_prev - c0) < TS_FAN ? (n_prev - c0) : TS_FAN;
 #pragma unroll
         for (int i = 0; i < SLOTS; ++i) {
-            const int r = 4 * i + part;
+            const int r = NPART * i + part;
             const int k = r / pw, rr = r % pw;
             x[i] = (q < pw && k < nc && rr <= q) ? prev[(c0 + k) * TILE + q * TR + rr] : 0.0;
         }
@@ -127,14 +130,14 @@ __global__ __launch_bounds__(256) void tsqr_factor_kernel(QrWork w, int64_t j0, 
             double s = 0.0, a = 0.0;
 #pragma unroll
             for (int i = 0; i < SLOTS; ++i) {
-                const int r = 4 * i + part;
+                const int r = NPART * i + part;
                 if (r > j)
                     s += x[i] * x[i];
                 if (r == j)
                     a = x[i];
             }
-            s = quad_sum(s);
-            a = quad_sum(a);  // one lane holds alpha, the others 0
+            s = col_sum(s);
+            a = col_sum(a);  // one lane holds alpha, the others 0
             double tau = 0.0, scale = 0.0, beta = a;
             if (s != 0.0) {
                 const double norm = sqrt(a * a + s);
@@ -144,7 +147,7 @@ __global__ __launch_bounds__(256) void tsqr_factor_kernel(QrWork w, int64_t j0, 
             }
 #pragma unroll
             for (int i = 0; i < SLOTS; ++i) {
-                const int r = 4 * i + part;
+                const int r = NPART * i + part;
                 if (r == j)
                     x[i] = beta;
                 else if (r > j)
@@ -160,17 +163,17 @@ __global__ __launch_bounds__(256) void tsqr_factor_kernel(QrWork w, int64_t j0, 
             double d = 0.0;
 #pragma unroll
             for (int i = 0; i < SLOTS; ++i)
-                d += v[4 * i + part] * x[i];
-            d = quad_sum(d) * tau;
+                d += v[NPART * i + part] * x[i];
+            d = col_sum(d) * tau;
 #pragma unroll
             for (int i = 0; i < SLOTS; ++i)
-                x[i] -= d * v[4 * i + part];
+                x[i] -= d * v[NPART * i + part];
         }
     }
     double *out = w.ts_tiles + w.tree.tile_off[level] + node * TILE + q * TR;
 #pragma unroll
     for (int i = 0; i < SLOTS; ++i)
-        out[4 * i + part] = x[i];
+        out[NPART * i + part] = x[i];
     if (part == 0)
         w.ts_tau[w.tree.tau_off[level] + node * NB + q] = (q < pw) ? taus[q] : 0.0;
 }
@@ -180,15 +183,15 @@ __global__ __launch_bounds__(256) void tsqr_factor_kernel(QrWork w, int64_t j0, 
 // node's pw x pw slice of its parent's X (the identity at the root).  Level 0
 // writes its X into the panel's rows of A.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void tsqr_formq_kernel(QrWork w, int64_t j0, int pw, int level,
+__global__ __launch_bounds__(TS_NT) void tsqr_formq_kernel(QrWork w, int64_t j0, int pw, int level,
                                                          int64_t n_level, int is_root, int64_t mk)
 {
     __shared__ double V[NB * (TR + 1)];
     __shared__ double taus[NB];
-    const int t = threadIdx.x, q = t >> 2, part = t & 3;
+    const int t = threadIdx.x, q = t / NPART, part = t % NPART;
     const int64_t node = blockIdx.x;
     const double *tile = w.ts_tiles + w.tree.tile_off[level] + node * TILE;
-    for (int idx = t; idx < TILE; idx += 256) {
+    for (int idx = t; idx < TILE; idx += TS_NT) {
         const int c = idx / TR, r = idx % TR;
         V[c * (TR + 1) + r] = tile[idx];
     }
@@ -198,7 +201,7 @@ __global__ __launch_bounds__(256) void tsqr_formq_kernel(QrWork w, int64_t j0, i
     if (is_root) {
 #pragma unroll
         for (int i = 0; i < SLOTS; ++i) {
-            const int r = 4 * i + part;
+            const int r = NPART * i + part;
             x[i] = (r == q && q < pw) ? 1.0 : 0.0;
         }
     } else {
@@ -206,7 +209,7 @@ __global__ __launch_bounds__(256) void tsqr_formq_kernel(QrWork w, int64_t j0, i
         const double *px = w.ts_X + w.tree.tile_off[level + 1] + parent * TILE + q * TR + pos * pw;
 #pragma unroll
         for (int i = 0; i < SLOTS; ++i) {
-            const int r = 4 * i + part;
+            const int r = NPART * i + part;
             x[i] = (q < pw && r < pw) ? px[r] : 0.0;
         }
     }
@@ -220,14 +223,14 @@ __global__ __launch_bounds__(256) void tsqr_formq_kernel(QrWork w, int64_t j0, i
             double d = 0.0;
 #pragma unroll
             for (int i = 0; i < SLOTS; ++i) {
-                const int r = 4 * i + part;
+                const int r = NPART * i + part;
                 const double vr = (r > j) ? vc[r] : (r == j ? 1.0 : 0.0);
                 d += vr * x[i];
             }
-            d = quad_sum(d) * tau;
+            d = col_sum(d) * tau;
 #pragma unroll
             for (int i = 0; i < SLOTS; ++i) {
-                const int r = 4 * i + part;
+                const int r = NPART * i + part;
                 const double vr = (r > j) ? vc[r] : (r == j ? 1.0 : 0.0);
                 x[i] -= d * vr;
             }
@@ -241,7 +244,7 @@ __global__ __launch_bounds__(256) void tsqr_formq_kernel(QrWork w, int64_t j0, i
             const int64_t nr = hi - lo;
 #pragma unroll
             for (int i = 0; i < SLOTS; ++i) {
-                const int r = 4 * i + part;
+                const int r = NPART * i + part;
                 if (r < nr)
                     col[r] = x[i];
             }
@@ -250,7 +253,7 @@ __global__ __launch_bounds__(256) void tsqr_formq_kernel(QrWork w, int64_t j0, i
         double *out = w.ts_X + w.tree.tile_off[level] + node * TILE + q * TR;
 #pragma unroll
         for (int i = 0; i < SLOTS; ++i)
-            out[4 * i + part] = x[i];
+            out[NPART * i + part] = x[i];
     }
 }
 
@@ -407,7 +410,7 @@ __global__ __launch_bounds__(256) void qr_wpart_kernel(QrWork w, int64_t j0, int
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int p = acc_row<WS>(wm, i, lane, e);
-                const int64_t q = q0 + acc_col<WS>(wn, jj, lane);
+                const int64_t q = q0 + acc_col<WS>(wn, jj, lane, e);
                 if (q < nt)
                     P[p * w.ncols + q] = acc[i][jj][e];
             }
@@ -469,7 +472,7 @@ __global__ __launch_bounds__(256) void qr_update_kernel(QrWork w, int64_t j0, in
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int64_t q = q0 + acc_row<US>(wm, i, lane, e);
-                const int64_t r = r0 + acc_col<US>(wn, jj, lane);
+                const int64_t r = r0 + acc_col<US>(wn, jj, lane, e);
                 if (r < m && q < nt)
                     C[q * lda + r] -= acc[i][jj][e];
             }
@@ -483,11 +486,11 @@ hipError_t launch_geqrf(const QrWork &w, hipStream_t s)
         const PanelTree pt = panel_tree(mk);
         // 1. TSQR up the tree
         for (int l = 0; l < pt.levels; ++l)
-            hipLaunchKernelGGL(tsqr_factor_kernel, dim3((unsigned)pt.nodes[l]), dim3(256), 0, s, w, j0, pw, l,
+            hipLaunchKernelGGL(tsqr_factor_kernel, dim3((unsigned)pt.nodes[l]), dim3(TS_NT), 0, s, w, j0, pw, l,
                                pt.nodes[l], l > 0 ? pt.nodes[l - 1] : 0, mk);
         // 2. explicit Q down the tree (level 0 lands in the panel)
         for (int l = pt.levels - 1; l >= 0; --l)
-            hipLaunchKernelGGL(tsqr_formq_kernel, dim3((unsigned)pt.nodes[l]), dim3(256), 0, s, w, j0, pw, l,
+            hipLaunchKernelGGL(tsqr_formq_kernel, dim3((unsigned)pt.nodes[l]), dim3(TS_NT), 0, s, w, j0, pw, l,
                                pt.nodes[l], l == pt.levels - 1 ? 1 : 0, mk);
         // 3. Householder vectors, T, R and tau from the explicit Q
         hipLaunchKernelGGL(tsqr_lu_kernel, dim3(1), dim3(256), 0, s, w, j0, pw, pt.levels - 1);

@@ -8,7 +8,7 @@ namespace gap {
 
 // ----------------------------------------------------------------- K_NM / K_MM
 constexpr int KNM_BM = 256;       // atoms per chunk (GEMM rows)
-constexpr int KNM_BN = 128;       // sparse points per tile (GEMM columns)
+constexpr int KNM_BN = 64;        // sparse points per tile (GEMM columns)
 constexpr int KNM_CAP = KNM_BM;   // atom capacity of a packed tile
 constexpr int KNM_MAX_SEG = 256;  // configurations per tile
 

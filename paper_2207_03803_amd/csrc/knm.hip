@@ -63,18 +63,21 @@ int64_t knm_max_tiles(int64_t N, int64_t n_atoms)
     return bound < N ? bound : N;
 }
 
-using KS = TileShape<KNM_BM, KNM_BN, 16, 4, 2>;  // 512 threads, 8 waves of 64x64
-static_assert(KS::NT == 512, "K_NM kernel assumes 512 threads");
-static_assert(KNM_BM == 256 && KNM_BN == 128, "loader mapping assumes a 256 x 128 tile");
+// 256 threads, 4 waves of 64 x 64, BK = 8: about 45 KB of LDS, so two or three
+// workgroups share a CU and cover each other's barriers.
+using KS = TileShape<KNM_BM, KNM_BN, 8, 4, 1>;
+static_assert(KS::NT == 256, "K_NM kernel assumes 256 threads");
+static_assert(KNM_BM == 256 && KNM_BN == 64, "loader mapping assumes a 256 x 64 tile");
 
-constexpr int EPC = 32;           // epilogue columns per pass
+constexpr int EPC = 16;           // epilogue columns per pass (one 16-column block)
 constexpr int EPLD = EPC + 1;     // padded LDS row of the epilogue buffer
 
-// Load one BK-slice of the atom tile (256 rows) and the sparse tile (128 rows)
-// into registers.  Rows past the valid range and k past d read as zero.
+// Load one BK-slice (8 descriptor components) of the atom tile (256 rows) and
+// the sparse tile (64 rows) into registers.  Rows past the valid range and k
+// past d read as zero.
 struct KnmLoads {
     double a[8];
-    double b[4];
+    double b[2];
 };
 
 DEV void knm_load(KnmLoads &r, const double *__restrict__ X, int64_t row0, int64_t row_end,
@@ -82,8 +85,8 @@ DEV void knm_load(KnmLoads &r, const double *__restrict__ X, int64_t row0, int64
 {
     const int tid = threadIdx.x;
     {
-        const int64_t row = row0 + (tid >> 1);
-        const int kb = k0 + (tid & 1) * 8;
+        const int64_t row = row0 + tid;
+        const int kb = k0;
         const bool rv = row < row_end;
         const double *p = X + row * (int64_t)d + kb;
         if (rv && kb + 8 <= d) {
@@ -98,16 +101,15 @@ DEV void knm_load(KnmLoads &r, const double *__restrict__ X, int64_t row0, int64
     }
     {
         const int64_t row = col0 + (tid >> 2);
-        const int kb = k0 + (tid & 3) * 4;
+        const int kb = k0 + (tid & 3) * 2;
         const bool rv = row < M;
         const double *p = XM + row * (int64_t)d + kb;
-        if (rv && kb + 4 <= d) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                r.b[e] = p[e];
+        if (rv && kb + 2 <= d) {
+            r.b[0] = p[0];
+            r.b[1] = p[1];
         } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
+            for (int e = 0; e < 2; ++e)
                 r.b[e] = (rv && kb + e < d) ? p[e] : 0.0;
         }
     }
@@ -117,25 +119,25 @@ DEV void knm_store(const KnmLoads &r, double *As, double *Bs)
 {
     const int tid = threadIdx.x;
     {
-        const int row = tid >> 1, kb = (tid & 1) * 8;
+        const int row = tid;
 #pragma unroll
         for (int e = 0; e < 8; ++e)
-            As[(kb + e) * KS::LDA + row] = r.a[e];
+            As[e * KS::LDA + row] = r.a[e];
     }
     {
-        const int row = tid >> 2, kb = (tid & 3) * 4;
+        const int row = tid >> 2, kb = (tid & 3) * 2;
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < 2; ++e)
             Bs[(kb + e) * KS::LDB + row] = r.b[e];
     }
 }
 
-// G = X[row0 : row0+256) . XM[col0 : col0+128)^T, accumulated in registers.
+// G = X[row0 : row0+256) . XM[col0 : col0+64)^T, accumulated in registers.
 DEV void knm_gemm(d4 (&acc)[KS::FM][KS::FN], double *lds, const double *__restrict__ X, int64_t row0,
                   int64_t row_end, const double *__restrict__ XM, int64_t col0, int64_t M, int d)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / KS::WN, wn = wave % KS::WN;
     zero_acc<KS>(acc);
     const int nk = (d + KS::BK - 1) / KS::BK;
     KnmLoads r;
@@ -158,18 +160,24 @@ DEV void knm_gemm(d4 (&acc)[KS::FM][KS::FN], double *lds, const double *__restri
 constexpr int KNM_LDS_DOUBLES =
     (2 * KS::STAGE > KNM_BM * EPLD) ? 2 * KS::STAGE : KNM_BM * EPLD;
 
-__global__ __launch_bounds__(512) void knm_kernel(KnmArgs a)
+__global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
 {
     __shared__ double lds[KNM_LDS_DOUBLES];
     __shared__ int32_t sstart[KNM_MAX_SEG + 1];
     __shared__ double carry[KNM_BN];
 
-    const int64_t lw = xcd_remap(blockIdx.x, a.total_pad);
-    const int64_t t = lw / a.n_ct, ct = lw % a.n_ct;
+    // The grid is sized for the largest possible tile count; the remap uses
+    // the actual count so that all eight XCDs get an equal share of the tiles.
     const bool unit = (a.offsets == nullptr);
     const int64_t n_tiles = unit ? (a.n_rows_unit + KNM_BM - 1) / KNM_BM : (int64_t)*a.n_tiles_dev;
-    if (t >= n_tiles)
+    const int64_t total = n_tiles * a.n_ct;
+    const int64_t total_pad = (total + 7) & ~int64_t(7);
+    if ((int64_t)blockIdx.x >= total_pad)
         return;
+    const int64_t lw = xcd_remap(blockIdx.x, total_pad);
+    if (lw >= total)
+        return;
+    const int64_t t = lw / a.n_ct, ct = lw % a.n_ct;
 
     int64_t seg_lo, seg_hi, atom_lo, atom_hi;
     if (unit) {
@@ -186,7 +194,7 @@ __global__ __launch_bounds__(512) void knm_kernel(KnmArgs a)
     const int n_seg = (int)(seg_hi - seg_lo);
     const int64_t col0 = ct * KNM_BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / KS::WN, wn = wave % KS::WN;
 
     // Segment boundaries relative to the tile's first atom.
     for (int s = tid; s <= n_seg; s += KS::NT)
@@ -234,19 +242,18 @@ __global__ __launch_bounds__(512) void knm_kernel(KnmArgs a)
 
         double *E = lds;  // [256][EPLD], reused after the GEMM
         for (int p = 0; p < KNM_BN / EPC; ++p) {
-            // waves owning columns [p*32, p*32+32) park their values in LDS
+            // waves owning columns [p*16, p*16+16) park their values in LDS
             if (wn == (p * EPC) / KS::TN) {
 #pragma unroll
                 for (int i = 0; i < KS::FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < KS::FN; ++j) {
-                        const int cl = acc_col<KS>(wn, j, lane) - p * EPC;
-                        if (cl >= 0 && cl < EPC) {
+                    for (int j = 0; j < KS::FN; ++j)
 #pragma unroll
-                            for (int e = 0; e < 4; ++e)
+                        for (int e = 0; e < 4; ++e) {
+                            const int cl = acc_col<KS>(wn, j, lane, e) - p * EPC;
+                            if (cl >= 0 && cl < EPC)
                                 E[acc_row<KS>(wm, i, lane, e) * EPLD + cl] = acc[i][j][e];
                         }
-                    }
             }
             __syncthreads();
             if (!multi) {
@@ -284,16 +291,16 @@ __global__ __launch_bounds__(512) void knm_kernel(KnmArgs a)
 // (the atom-by-sparse covariances stay in registers), then one thread per
 // configuration adds its atoms' energies in atom order.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(512) void predict_kernel(const double *__restrict__ X, const int64_t *offsets,
+__global__ __launch_bounds__(256, 2) void predict_kernel(const double *__restrict__ X, const int64_t *offsets,
                                                       int64_t N, const double *__restrict__ XM, int64_t M,
                                                       int d, int zeta, double sw2,
                                                       const double *__restrict__ c, double *y, int64_t C)
 {
     __shared__ double lds[2 * KS::STAGE];
     __shared__ double eps[KNM_BM];
-    __shared__ double part[2][KNM_BM];
+    __shared__ double part[KS::WN][KNM_BM];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / KS::WN, wn = wave % KS::WN;
     const int64_t cfg_lo = (int64_t)blockIdx.x * C;
     int64_t cfg_hi = cfg_lo + C;
     if (cfg_hi > N)
@@ -318,31 +325,36 @@ __global__ __launch_bounds__(512) void predict_kernel(const double *__restrict__
             const int64_t col0 = ct * KNM_BN;
             __syncthreads();
             knm_gemm(acc, lds, X, cs, atom_hi, XM, col0, M, d);
-            double cw[KS::FN];
+            double cw[KS::FN][4];
 #pragma unroll
-            for (int j = 0; j < KS::FN; ++j) {
-                const int64_t col = col0 + acc_col<KS>(wn, j, lane);
-                cw[j] = (col < M) ? c[col] : 0.0;
-            }
-#pragma unroll
-            for (int i = 0; i < KS::FM; ++i)
+            for (int j = 0; j < KS::FN; ++j)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int j = 0; j < KS::FN; ++j)
-                        s += cw[j] * (sw2 * ipow(acc[i][j][e], zeta));
-                    // sum over the 16 lanes that share this row
-                    s += __shfl_xor(s, 1, 64);
-                    s += __shfl_xor(s, 2, 64);
-                    s += __shfl_xor(s, 4, 64);
-                    s += __shfl_xor(s, 8, 64);
-                    if ((lane & 15) == 0)
-                        part[wn][acc_row<KS>(wm, i, lane, e)] = s;
+                    const int64_t col = col0 + acc_col<KS>(wn, j, lane, e);
+                    cw[j][e] = (col < M) ? c[col] : 0.0;
                 }
+#pragma unroll
+            for (int i = 0; i < KS::FM; ++i) {
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < KS::FN; ++j)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        s += cw[j][e] * (sw2 * ipow(acc[i][j][e], zeta));
+                // the 4 lanes that differ in l % 4 share this row
+                s += __shfl_xor(s, 1, 64);
+                s += __shfl_xor(s, 2, 64);
+                if ((lane & 3) == 0)
+                    part[wn][acc_row<KS>(wm, i, lane, 0)] = s;
+            }
             __syncthreads();
-            if (tid < KNM_BM)
-                eps[tid] += part[0][tid] + part[1][tid];
+            if (tid < KNM_BM) {
+                double add = 0.0;
+#pragma unroll
+                for (int q = 0; q < KS::WN; ++q)
+                    add += part[q][tid];
+                eps[tid] += add;
+            }
         }
         __syncthreads();
         if (tid < ncfg) {

@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void chol_syrk_kernel(double *U, int64_t ld, i
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int64_t c = c0 + acc_row<SS>(wm, i, lane, e);
-                const int64_t r = r0 + acc_col<SS>(wn, j, lane);
+                const int64_t r = r0 + acc_col<SS>(wn, j, lane, e);
                 if (r <= c && c < n)
                     U[c * ld + r] -= acc[i][j][e];
             }
