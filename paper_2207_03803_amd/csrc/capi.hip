@@ -19,7 +19,7 @@ enum State { ST_CREATED = 0, ST_BOUND = 1, ST_BUILT = 2, ST_SOLVED = 3 };
 struct Layout {
     int64_t N = 0, M = 0, n_atoms = 0, m = 0, lda = 0, ncols = 0, max_tiles = 0;
     TsqrTree tree;
-    size_t off_A = 0, off_tau = 0, off_wpart = 0, off_T = 0, off_U = 0, off_W = 0, off_ts_tiles = 0,
+    size_t off_A = 0, off_tau = 0, off_wpart = 0, off_T = 0, off_Tin = 0, off_U = 0, off_W = 0, off_ts_tiles = 0,
            off_ts_X = 0, off_ts_tau = 0, off_rhs = 0, off_misc = 0, off_tiles = 0, off_counters = 0,
            off_status = 0, total = 0;
 };
@@ -45,10 +45,11 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M)
     };
     L.off_A = take(sizeof(double) * (size_t)L.lda * (size_t)L.ncols);
     L.off_tau = take(sizeof(double) * (size_t)M);
-    L.off_wpart = take(sizeof(double) * (size_t)qr_max_chunks() * QR_NB * (size_t)L.ncols);
-    L.off_T = take(sizeof(double) * QR_NB * QR_NB);
+    L.off_wpart = take(sizeof(double) * (size_t)qr_max_chunks() * 2 * QR_NB * (size_t)L.ncols);
+    L.off_T = take(sizeof(double) * 4 * QR_NB * QR_NB);
+    L.off_Tin = take(sizeof(double) * 2 * QR_NB * QR_NB);
     L.off_U = take(sizeof(double) * QR_NB * QR_NB);
-    L.off_W = take(sizeof(double) * QR_NB * (size_t)L.ncols);
+    L.off_W = take(sizeof(double) * 2 * QR_NB * (size_t)L.ncols);
     L.off_ts_tiles = take(sizeof(double) * (size_t)L.tree.tiles_doubles);
     L.off_ts_X = take(sizeof(double) * (size_t)L.tree.tiles_doubles);
     L.off_ts_tau = take(sizeof(double) * (size_t)L.tree.tau_doubles);
@@ -303,6 +304,7 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
     w.tau = h->at<double>(L.off_tau);
     w.wpart = h->at<double>(L.off_wpart);
     w.T = h->at<double>(L.off_T);
+    w.Tin = h->at<double>(L.off_Tin);
     w.U = h->at<double>(L.off_U);
     w.W = h->at<double>(L.off_W);
     w.ts_tiles = h->at<double>(L.off_ts_tiles);

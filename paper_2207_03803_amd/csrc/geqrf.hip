@@ -263,7 +263,7 @@ __global__ __launch_bounds__(TS_NT) void tsqr_formq_kernel(QrWork w, int64_t j0,
 // T = -U S Y1^-T, R = S R_root; writes R above and Y1 below the diagonal of
 // the panel's top block, tau = diag(T), and U for the row solve below.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void tsqr_lu_kernel(QrWork w, int64_t j0, int pw, int root_level)
+__global__ __launch_bounds__(256) void tsqr_lu_kernel(QrWork w, int64_t j0, int pw, int root_level, double *Tout)
 {
     __shared__ double B[NB][NB + 1];
     __shared__ double Z[NB][NB + 1];
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(256) void tsqr_lu_kernel(QrWork w, int64_t j0, int 
             for (int p = r; p <= c; ++p)
                 tv -= B[r][p] * sg[p] * Z[p][c];
         }
-        w.T[idx] = tv;
+        Tout[idx] = tv;
         w.U[idx] = (r < pw && c < pw && r <= c) ? B[r][c] : 0.0;
         if (r < pw && c < pw) {
             double out;
@@ -358,7 +358,8 @@ __global__ __launch_bounds__(256) void tsqr_trsm_kernel(QrWork w, int64_t j0, in
             w.A[(j0 + c) * w.lda + r] = y[c];
 }
 
-// Householder vectors of the panel at (j0, j0): unit lower trapezoidal.
+// Householder vectors of the column block at (j0, j0), pw <= 2 * QR_NB wide:
+// unit lower trapezoidal.
 DEV double ypanel(const double *A, int64_t lda, int64_t m, int64_t j0, int pw, int64_t r, int p)
 {
     if (p >= pw || r >= m)
@@ -371,16 +372,21 @@ DEV double ypanel(const double *A, int64_t lda, int64_t m, int64_t j0, int pw, i
     return A[(j0 + p) * lda + r];
 }
 
-using WS = TileShape<NB, 128, 16, 1, 4>;   // P = Y^T C, split over row chunks
+constexpr int OB = 2 * NB;                 // outer block: two TSQR panels
+using WS = TileShape<OB, 64, 16, 2, 2>;    // P = Y^T C over a row chunk
 using US = TileShape<128, 128, 16, 2, 2>;  // C^T -= W^T Y^T (rows of C along the MFMA N axis)
 
-// P[ch][p][q] = sum over the chunk's rows r of Y[r][p] C[r][q], C = columns j0+pw..
-__global__ __launch_bounds__(256) void qr_wpart_kernel(QrWork w, int64_t j0, int pw, int64_t chunk, int64_t nt)
+// P[ch][p][q] = sum over the chunk's rows r of Y[r][p] C[r][q].  Y is the
+// block at (j0, j0) of width pw; C is either columns c0 .. c0+nt of A
+// (ymode = 0) or the unit lower trapezoidal block at (c0, c0) of width nt
+// (ymode = 1, used for Y_A^T Y_B).  Rows r0 .. m.
+__global__ __launch_bounds__(256, 2) void qr_wpart_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt,
+                                                          int ymode, int64_t r0, int64_t chunk)
 {
     __shared__ double lds[2 * WS::STAGE];
     const int64_t ch = blockIdx.y;
     const int64_t q0 = (int64_t)blockIdx.x * WS::BN;
-    const int64_t rlo = j0 + ch * chunk;
+    const int64_t rlo = r0 + ch * chunk;
     int64_t rhi = rlo + chunk;
     if (rhi > w.m)
         rhi = w.m;
@@ -390,19 +396,20 @@ __global__ __launch_bounds__(256) void qr_wpart_kernel(QrWork w, int64_t j0, int
     zero_acc<WS>(acc);
     const double *A = w.A;
     const int64_t lda = w.lda, m = w.m;
-    const double *C = A + (j0 + pw) * lda;
     auto fa = [&](int p, int64_t k) -> double {
         const int64_t r = rlo + k;
         return (r < rhi) ? ypanel(A, lda, m, j0, pw, r, p) : 0.0;
     };
     auto fb = [&](int qi, int64_t k) -> double {
         const int64_t r = rlo + k, q = q0 + qi;
-        return (r < rhi && q < nt) ? C[q * lda + r] : 0.0;
+        if (r >= rhi || q >= nt)
+            return 0.0;
+        return ymode ? ypanel(A, lda, m, c0, (int)nt, r, (int)q) : A[(c0 + q) * lda + r];
     };
     gemm_tile<WS, true, true>(acc, lds, rhi - rlo, fa, fb);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WS::WN, wn = wave % WS::WN;
-    double *P = w.wpart + ch * NB * w.ncols;
+    double *P = w.wpart + ch * OB * w.ncols;
 #pragma unroll
     for (int i = 0; i < WS::FM; ++i)
 #pragma unroll
@@ -411,42 +418,86 @@ __global__ __launch_bounds__(256) void qr_wpart_kernel(QrWork w, int64_t j0, int
             for (int e = 0; e < 4; ++e) {
                 const int p = acc_row<WS>(wm, i, lane, e);
                 const int64_t q = q0 + acc_col<WS>(wn, jj, lane, e);
-                if (q < nt)
+                if (p < pw && q < nt)
                     P[p * w.ncols + q] = acc[i][jj][e];
             }
 }
 
-// W[p][q] = sum_{s <= p} T[s][p] sum_ch P[ch][s][q]; 64 columns per workgroup,
-// thread (q, part) sums panel rows p = part, part + 4, ... over the chunks in order.
-__global__ __launch_bounds__(256) void qr_wred_kernel(QrWork w, int pw, int64_t nch, int64_t nt)
+// W[p][q] = sum_{s <= p} T[s][p] sum_ch P[ch][s][q] (T upper triangular,
+// row-major with leading dimension tld); 64 columns per workgroup, thread
+// (q, part) handles panel rows p = part, part + 4, ...; chunks summed in order.
+__global__ __launch_bounds__(256) void qr_wred_kernel(QrWork w, const double *__restrict__ T, int tld, int pw,
+                                                      int64_t nch, int64_t nt)
 {
-    __shared__ double T[NB][NB + 1];
-    __shared__ double Pm[NB][NB + 1];
-    for (int idx = threadIdx.x; idx < NB * NB; idx += 256)
-        T[idx / NB][idx % NB] = w.T[idx];
+    __shared__ double Pm[OB][64 + 1];
     const int ql = threadIdx.x & 63, part = threadIdx.x >> 6;
-    const int64_t q = (int64_t)blockIdx.x * NB + ql;
-    for (int p = part; p < NB; p += 4) {
+    const int64_t q = (int64_t)blockIdx.x * 64 + ql;
+    for (int p = part; p < pw; p += 4) {
         double s = 0.0;
-        if (p < pw && q < nt)
+        if (q < nt)
             for (int64_t ch = 0; ch < nch; ++ch)
-                s += w.wpart[(ch * NB + p) * w.ncols + q];
+                s += w.wpart[(ch * OB + p) * w.ncols + q];
         Pm[p][ql] = s;
     }
     __syncthreads();
     if (q >= nt)
         return;
-    for (int p = part; p < NB; p += 4) {
+    for (int p = part; p < pw; p += 4) {
         double s = 0.0;
         for (int r = 0; r <= p; ++r)
-            s += T[r][p] * Pm[r][ql];
-        w.W[p * w.ncols + q] = (p < pw) ? s : 0.0;
+            s += T[r * tld + p] * Pm[r][ql];
+        w.W[p * w.ncols + q] = s;
     }
 }
 
-// C[r][q] -= sum_p Y[r][p] W[p][q] for rows j0.. and columns j0+pw..; the tile
-// is computed transposed so that consecutive lanes write consecutive rows.
-__global__ __launch_bounds__(256) void qr_update_kernel(QrWork w, int64_t j0, int pw, int64_t nt)
+// Combined compact-WY factor of two consecutive panels A | B:
+// T = [[T_A, -T_A G T_B], [0, T_B]] with G = Y_A^T Y_B (chunk partials summed in order).
+__global__ __launch_bounds__(256) void qr_tcombine_kernel(QrWork w, int pwb, int64_t nch)
+{
+    __shared__ double TA[NB][NB + 1];
+    __shared__ double TB[NB][NB + 1];
+    __shared__ double G[NB][NB + 1];
+    __shared__ double X[NB][NB + 1];
+    const int t = threadIdx.x;
+    const double *Ta = w.Tin, *Tb = w.Tin + NB * NB;
+    for (int idx = t; idx < NB * NB; idx += 256) {
+        const int r = idx / NB, c = idx % NB;
+        TA[r][c] = Ta[idx];
+        TB[r][c] = Tb[idx];
+        double g = 0.0;
+        if (c < pwb)
+            for (int64_t ch = 0; ch < nch; ++ch)
+                g += w.wpart[(ch * OB + r) * w.ncols + c];
+        G[r][c] = g;
+    }
+    __syncthreads();
+    for (int idx = t; idx < NB * NB; idx += 256) {  // X = G T_B
+        const int r = idx / NB, c = idx % NB;
+        double v = 0.0;
+        for (int k = 0; k <= c; ++k)
+            v += G[r][k] * TB[k][c];
+        X[r][c] = v;
+    }
+    __syncthreads();
+    for (int idx = t; idx < OB * OB; idx += 256) {
+        const int r = idx / OB, c = idx % OB;
+        double v = 0.0;
+        if (r < NB && c < NB) {
+            v = TA[r][c];
+        } else if (r >= NB && c >= NB) {
+            v = TB[r - NB][c - NB];
+        } else if (r < NB && c >= NB) {  // -T_A X
+            const int cc = c - NB;
+            for (int k = r; k < NB; ++k)
+                v -= TA[r][k] * X[k][cc];
+        }
+        w.T[idx] = v;
+    }
+}
+
+// C[r][q] -= sum_p Y[r][p] W[p][q] for rows j0.. and columns c0 .. c0+nt; the
+// tile is computed transposed so that consecutive lanes write consecutive rows.
+__global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt)
 {
     __shared__ double lds[2 * US::STAGE];
     const int64_t q0 = (int64_t)blockIdx.y * US::BM;
@@ -464,7 +515,7 @@ __global__ __launch_bounds__(256) void qr_update_kernel(QrWork w, int64_t j0, in
     gemm_tile<US, false, false>(acc, lds, pw, fa, fb);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / US::WN, wn = wave % US::WN;
-    double *C = w.A + (j0 + pw) * lda;
+    double *C = w.A + c0 * lda;
 #pragma unroll
     for (int i = 0; i < US::FM; ++i)
 #pragma unroll
@@ -478,45 +529,79 @@ __global__ __launch_bounds__(256) void qr_update_kernel(QrWork w, int64_t j0, in
             }
 }
 
+// Split of rows [r0, m) into chunks for the split-K products.
+static void chunking(int64_t rows, int64_t ncb, int64_t &chunk, int64_t &nch)
+{
+    nch = (2048 + ncb - 1) / ncb;
+    if (nch > MAX_CHUNKS)
+        nch = MAX_CHUNKS;
+    chunk = (rows + nch - 1) / nch;
+    chunk = (chunk + 15) & ~int64_t(15);
+    if (chunk < 256)
+        chunk = 256;
+    nch = (rows + chunk - 1) / chunk;
+}
+
+// TSQR + reconstruction of the panel at (j0, j0) of width pw; its T goes to Tout.
+static void factor_panel(const QrWork &w, int64_t j0, int pw, double *Tout, hipStream_t s)
+{
+    const int64_t mk = w.m - j0;
+    const PanelTree pt = panel_tree(mk);
+    for (int l = 0; l < pt.levels; ++l)
+        hipLaunchKernelGGL(tsqr_factor_kernel, dim3((unsigned)pt.nodes[l]), dim3(TS_NT), 0, s, w, j0, pw, l,
+                           pt.nodes[l], l > 0 ? pt.nodes[l - 1] : 0, mk);
+    for (int l = pt.levels - 1; l >= 0; --l)
+        hipLaunchKernelGGL(tsqr_formq_kernel, dim3((unsigned)pt.nodes[l]), dim3(TS_NT), 0, s, w, j0, pw, l,
+                           pt.nodes[l], l == pt.levels - 1 ? 1 : 0, mk);
+    hipLaunchKernelGGL(tsqr_lu_kernel, dim3(1), dim3(256), 0, s, w, j0, pw, pt.levels - 1, Tout);
+    if (mk > pw)
+        hipLaunchKernelGGL(tsqr_trsm_kernel, dim3((unsigned)((mk - pw + 255) / 256)), dim3(256), 0, s, w, j0, pw);
+}
+
+// C := (I - Y T Y^T)^T C for the columns c0 .. c0+nt, Y the block at (j0, j0) of width pw.
+static void apply_block(const QrWork &w, int64_t j0, int pw, const double *T, int tld, int64_t c0, int64_t nt,
+                        hipStream_t s)
+{
+    if (nt <= 0)
+        return;
+    const int64_t rows = w.m - j0;
+    const int64_t ncb = (nt + WS::BN - 1) / WS::BN;
+    int64_t chunk, nch;
+    chunking(rows, ncb, chunk, nch);
+    hipLaunchKernelGGL(qr_wpart_kernel, dim3((unsigned)ncb, (unsigned)nch), dim3(256), 0, s, w, j0, pw, c0, nt, 0,
+                       j0, chunk);
+    hipLaunchKernelGGL(qr_wred_kernel, dim3((unsigned)((nt + 63) / 64)), dim3(256), 0, s, w, T, tld, pw, nch, nt);
+    hipLaunchKernelGGL(qr_update_kernel,
+                       dim3((unsigned)((rows + US::BN - 1) / US::BN), (unsigned)((nt + US::BM - 1) / US::BM)),
+                       dim3(256), 0, s, w, j0, pw, c0, nt);
+}
+
 hipError_t launch_geqrf(const QrWork &w, hipStream_t s)
 {
-    for (int64_t j0 = 0; j0 < w.n; j0 += NB) {
-        const int pw = (int)((w.n - j0) < NB ? (w.n - j0) : NB);
-        const int64_t mk = w.m - j0;
-        const PanelTree pt = panel_tree(mk);
-        // 1. TSQR up the tree
-        for (int l = 0; l < pt.levels; ++l)
-            hipLaunchKernelGGL(tsqr_factor_kernel, dim3((unsigned)pt.nodes[l]), dim3(TS_NT), 0, s, w, j0, pw, l,
-                               pt.nodes[l], l > 0 ? pt.nodes[l - 1] : 0, mk);
-        // 2. explicit Q down the tree (level 0 lands in the panel)
-        for (int l = pt.levels - 1; l >= 0; --l)
-            hipLaunchKernelGGL(tsqr_formq_kernel, dim3((unsigned)pt.nodes[l]), dim3(TS_NT), 0, s, w, j0, pw, l,
-                               pt.nodes[l], l == pt.levels - 1 ? 1 : 0, mk);
-        // 3. Householder vectors, T, R and tau from the explicit Q
-        hipLaunchKernelGGL(tsqr_lu_kernel, dim3(1), dim3(256), 0, s, w, j0, pw, pt.levels - 1);
-        if (mk > pw)
-            hipLaunchKernelGGL(tsqr_trsm_kernel, dim3((unsigned)((mk - pw + 255) / 256)), dim3(256), 0, s, w, j0,
-                               pw);
-        // 4. trailing update of the remaining columns (b included)
-        const int64_t nt = w.ncols - j0 - pw;
-        if (nt <= 0)
+    double *Ta = w.Tin, *Tb = w.Tin + NB * NB;
+    for (int64_t J = 0; J < w.n; J += OB) {
+        const int pwa = (int)((w.n - J) < NB ? (w.n - J) : NB);
+        factor_panel(w, J, pwa, Ta, s);
+        const int64_t jb = J + pwa;
+        const int pwb = (int)((w.n - jb) < NB ? (w.n - jb) : NB);
+        if (pwb <= 0) {
+            apply_block(w, J, pwa, Ta, NB, jb, w.ncols - jb, s);
             continue;
-        const int64_t ncb = (nt + WS::BN - 1) / WS::BN;
-        int64_t nch = (2048 + ncb - 1) / ncb;
-        if (nch > MAX_CHUNKS)
-            nch = MAX_CHUNKS;
-        int64_t chunk = (mk + nch - 1) / nch;
-        chunk = (chunk + 15) & ~int64_t(15);
-        if (chunk < 256)
-            chunk = 256;
-        nch = (mk + chunk - 1) / chunk;
-        hipLaunchKernelGGL(qr_wpart_kernel, dim3((unsigned)ncb, (unsigned)nch), dim3(256), 0, s, w, j0, pw,
-                           chunk, nt);
-        hipLaunchKernelGGL(qr_wred_kernel, dim3((unsigned)((nt + NB - 1) / NB)), dim3(256), 0, s, w, pw, nch,
-                           nt);
-        hipLaunchKernelGGL(qr_update_kernel,
-                           dim3((unsigned)((mk + US::BN - 1) / US::BN), (unsigned)((nt + US::BM - 1) / US::BM)),
-                           dim3(256), 0, s, w, j0, pw, nt);
+        }
+        // bring panel B up to date with panel A, factor it, then merge the two
+        // compact-WY factors and update everything to the right at once
+        apply_block(w, J, pwa, Ta, NB, jb, pwb, s);
+        factor_panel(w, jb, pwb, Tb, s);
+        {
+            const int64_t rows = w.m - jb;
+            int64_t chunk, nch;
+            chunking(rows, 1, chunk, nch);
+            hipLaunchKernelGGL(qr_wpart_kernel, dim3(1, (unsigned)nch), dim3(256), 0, s, w, J, pwa, jb,
+                               (int64_t)pwb, 1, jb, chunk);
+            hipLaunchKernelGGL(qr_tcombine_kernel, dim3(1), dim3(256), 0, s, w, pwb, nch);
+        }
+        const int64_t c0 = jb + pwb;
+        apply_block(w, J, pwa + pwb, w.T, OB, c0, w.ncols - c0, s);
     }
     return hipGetLastError();
 }
