@@ -49,7 +49,7 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M)
     L.off_T = take(sizeof(double) * 4 * QR_NB * QR_NB);
     L.off_Tin = take(sizeof(double) * 2 * QR_NB * QR_NB);
     L.off_U = take(sizeof(double) * QR_NB * QR_NB);
-    L.off_W = take(sizeof(double) * 2 * QR_NB * (size_t)L.ncols);
+    L.off_W = take(sizeof(double) * 2 * QR_NB * (size_t)((L.ncols + 63) / 64 * 64));
     L.off_ts_tiles = take(sizeof(double) * (size_t)L.tree.tiles_doubles);
     L.off_ts_X = take(sizeof(double) * (size_t)L.tree.tiles_doubles);
     L.off_ts_tau = take(sizeof(double) * (size_t)L.tree.tau_doubles);
@@ -301,6 +301,7 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
     w.m = L.m;
     w.n = L.M;
     w.ncols = L.ncols;
+    w.ldw = (L.ncols + 63) / 64 * 64;
     w.tau = h->at<double>(L.off_tau);
     w.wpart = h->at<double>(L.off_wpart);
     w.T = h->at<double>(L.off_T);

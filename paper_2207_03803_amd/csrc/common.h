@@ -250,3 +250,85 @@ DEV void gemm_tile(d4 (&acc)[S::FM][S::FN], double *lds, int64_t K, FA fa, FB fb
         __syncthreads();
     }
 }
+
+// ---------------------------------------------------------------------------
+// Same product with run loaders: fa(r, k, v) fills v[0..VA) with a run of
+// consecutive elements (along k when A_KC, else along the row index, starting
+// at the given (r, k)); likewise fb with VB.  Lets the caller issue vector
+// loads and keep bounds checks off the common path.
+// ---------------------------------------------------------------------------
+template <class S, bool A_KC, bool B_KC, class FA, class FB>
+DEV void gemm_tile_runs(d4 (&acc)[S::FM][S::FN], double *lds, int64_t K, FA fa, FB fb)
+{
+    constexpr int VA = S::BM * S::BK / S::NT;
+    constexpr int VB = S::BN * S::BK / S::NT;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave / S::WN, wn = wave % S::WN;
+    double ra[VA], rb[VB];
+    // per-thread run origin inside the tile
+    int ar, ak, br, bk;
+    if constexpr (A_KC) {
+        ar = t / (S::BK / VA);
+        ak = (t % (S::BK / VA)) * VA;
+    } else {
+        ak = t / (S::BM / VA);
+        ar = (t % (S::BM / VA)) * VA;
+    }
+    if constexpr (B_KC) {
+        br = t / (S::BK / VB);
+        bk = (t % (S::BK / VB)) * VB;
+    } else {
+        bk = t / (S::BN / VB);
+        br = (t % (S::BN / VB)) * VB;
+    }
+    auto store = [&](double *As, double *Bs) {
+#pragma unroll
+        for (int e = 0; e < VA; ++e) {
+            if constexpr (A_KC)
+                As[(ak + e) * S::LDA + ar] = ra[e];
+            else
+                As[ak * S::LDA + ar + e] = ra[e];
+        }
+#pragma unroll
+        for (int e = 0; e < VB; ++e) {
+            if constexpr (B_KC)
+                Bs[(bk + e) * S::LDB + br] = rb[e];
+            else
+                Bs[bk * S::LDB + br + e] = rb[e];
+        }
+    };
+    const int64_t nk = (K + S::BK - 1) / S::BK;
+    if (nk <= 0)
+        return;
+    fa(ar, (int64_t)ak, ra);
+    fb(br, (int64_t)bk, rb);
+    store(lds, lds + S::A_ELEMS);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        double *cur = lds + (kt & 1) * S::STAGE;
+        double *nxt = lds + ((kt + 1) & 1) * S::STAGE;
+        const bool more = kt + 1 < nk;
+        if (more) {
+            fa(ar, (kt + 1) * S::BK + ak, ra);
+            fb(br, (kt + 1) * S::BK + bk, rb);
+        }
+        mma_stage<S>(cur, cur + S::A_ELEMS, acc, wm, wn, lane);
+        if (more)
+            store(nxt, nxt + S::A_ELEMS);
+        __syncthreads();
+    }
+}
+
+// Load n consecutive doubles from p (16-byte aligned when aligned16).
+template <int N>
+DEV void load_run(const double *__restrict__ p, double (&v)[N])
+{
+    static_assert(N % 2 == 0, "runs of an even length");
+    const double2 *q = reinterpret_cast<const double2 *>(p);
+#pragma unroll
+    for (int e = 0; e < N / 2; ++e) {
+        const double2 x = q[e];
+        v[2 * e] = x.x;
+        v[2 * e + 1] = x.y;
+    }
+}

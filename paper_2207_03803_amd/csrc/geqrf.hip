@@ -396,17 +396,44 @@ __global__ __launch_bounds__(256, 2) void qr_wpart_kernel(QrWork w, int64_t j0, 
     zero_acc<WS>(acc);
     const double *A = w.A;
     const int64_t lda = w.lda, m = w.m;
-    auto fa = [&](int p, int64_t k) -> double {
+    const bool masked = rlo < j0 + pw;  // the chunk meets Y's unit upper triangle
+    constexpr int VA = WS::BM * WS::BK / WS::NT, VB = WS::BN * WS::BK / WS::NT;
+    auto fa = [&](int p, int64_t k, double (&v)[VA]) {
         const int64_t r = rlo + k;
-        return (r < rhi) ? ypanel(A, lda, m, j0, pw, r, p) : 0.0;
+        if (p >= pw) {
+#pragma unroll
+            for (int e = 0; e < VA; ++e)
+                v[e] = 0.0;
+        } else if (!masked && r + VA <= rhi) {
+            load_run(A + (j0 + p) * lda + r, v);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VA; ++e)
+                v[e] = (r + e < rhi) ? ypanel(A, lda, m, j0, pw, r + e, p) : 0.0;
+        }
     };
-    auto fb = [&](int qi, int64_t k) -> double {
+    auto fb = [&](int qi, int64_t k, double (&v)[VB]) {
         const int64_t r = rlo + k, q = q0 + qi;
-        if (r >= rhi || q >= nt)
-            return 0.0;
-        return ymode ? ypanel(A, lda, m, c0, (int)nt, r, (int)q) : A[(c0 + q) * lda + r];
+        if (q >= nt) {
+#pragma unroll
+            for (int e = 0; e < VB; ++e)
+                v[e] = 0.0;
+        } else if (ymode) {
+#pragma unroll
+            for (int e = 0; e < VB; ++e)
+                v[e] = (r + e < rhi) ? ypanel(A, lda, m, c0, (int)nt, r + e, (int)q) : 0.0;
+        } else {
+            const double *col = A + (c0 + q) * lda + r;
+            if (r + VB <= rhi) {
+                load_run(col, v);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VB; ++e)
+                    v[e] = (r + e < rhi) ? col[e] : 0.0;
+            }
+        }
     };
-    gemm_tile<WS, true, true>(acc, lds, rhi - rlo, fa, fb);
+    gemm_tile_runs<WS, true, true>(acc, lds, rhi - rlo, fa, fb);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WS::WN, wn = wave % WS::WN;
     double *P = w.wpart + ch * OB * w.ncols;
@@ -446,7 +473,7 @@ __global__ __launch_bounds__(256) void qr_wred_kernel(QrWork w, const double *__
         double s = 0.0;
         for (int r = 0; r <= p; ++r)
             s += T[r * tld + p] * Pm[r][ql];
-        w.W[p * w.ncols + q] = s;
+        w.W[p * w.ldw + q] = s;
     }
 }
 
@@ -503,16 +530,41 @@ __global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0,
     const int64_t q0 = (int64_t)blockIdx.y * US::BM;
     const int64_t r0 = j0 + (int64_t)blockIdx.x * US::BN;
     const double *A = w.A;
-    const int64_t lda = w.lda, m = w.m, ldW = w.ncols;
+    const int64_t lda = w.lda, m = w.m, ldW = w.ldw;
     const double *W = w.W;
     d4 acc[US::FM][US::FN];
     zero_acc<US>(acc);
-    auto fa = [&](int qi, int64_t p) -> double {
+    const bool masked = r0 < j0 + pw;  // the row block meets Y's unit upper triangle
+    constexpr int VA = US::BM * US::BK / US::NT, VB = US::BN * US::BK / US::NT;
+    auto fa = [&](int qi, int64_t p, double (&v)[VA]) {
         const int64_t q = q0 + qi;
-        return (q < nt && p < pw) ? W[p * ldW + q] : 0.0;
+        if (p >= pw) {
+#pragma unroll
+            for (int e = 0; e < VA; ++e)
+                v[e] = 0.0;
+        } else if (q + VA <= nt) {
+            load_run(W + p * ldW + q, v);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VA; ++e)
+                v[e] = (q + e < nt) ? W[p * ldW + q + e] : 0.0;
+        }
     };
-    auto fb = [&](int ri, int64_t p) -> double { return ypanel(A, lda, m, j0, pw, r0 + ri, (int)p); };
-    gemm_tile<US, false, false>(acc, lds, pw, fa, fb);
+    auto fb = [&](int ri, int64_t p, double (&v)[VB]) {
+        const int64_t r = r0 + ri;
+        if (p >= pw) {
+#pragma unroll
+            for (int e = 0; e < VB; ++e)
+                v[e] = 0.0;
+        } else if (!masked && r + VB <= m) {
+            load_run(A + (j0 + p) * lda + r, v);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VB; ++e)
+                v[e] = ypanel(A, lda, m, j0, pw, r + e, (int)p);
+        }
+    };
+    gemm_tile_runs<US, false, false>(acc, lds, pw, fa, fb);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / US::WN, wn = wave % US::WN;
     double *C = w.A + c0 * lda;

@@ -71,12 +71,13 @@ TsqrTree tsqr_tree(int64_t m);
 struct QrWork {
     double *A;        // column-major [lda x ncols]: factor columns 0..n-1, apply to n..ncols-1
     int64_t lda, m, n, ncols;
+    int64_t ldw;      // leading dimension of W (ncols rounded up to 64)
     double *tau;      // [n]
     double *wpart;    // [max_chunks * 2 QR_NB * ncols] split-K partials of Y^T C
     double *T;        // [2 QR_NB * 2 QR_NB] compact-WY T of the current two-panel block (row-major)
     double *Tin;      // [2 * QR_NB * QR_NB] T of the block's two panels (row-major, ld QR_NB)
     double *U;        // [QR_NB * QR_NB] LU factor of (Q - S) of the current panel
-    double *W;        // [2 QR_NB * ncols] T^T Y^T C, row-major by block column
+    double *W;        // [2 QR_NB * ldw] T^T Y^T C, row-major by block column
     double *ts_tiles; // TsqrTree::tiles_doubles
     double *ts_X;     // TsqrTree::tiles_doubles
     double *ts_tau;   // TsqrTree::tau_doubles

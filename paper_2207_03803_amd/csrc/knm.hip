@@ -11,39 +11,64 @@ namespace gap {
 // Tile plan: pack whole configurations, in order, into tiles of at most
 // KNM_CAP atoms and KNM_MAX_SEG configurations (greedy).  A configuration with
 // more than KNM_CAP atoms gets a tile of its own, processed in several atom
-// chunks.  Also validates the offsets.  One thread: the plan is a sequential
-// scan of n_configs + 1 offsets.
+// chunks.  Also validates the offsets.  The plan is a sequential scan of the
+// n_configs + 1 offsets by one thread; the workgroup stages them through LDS.
 // ---------------------------------------------------------------------------
-__global__ void plan_tiles_kernel(const int64_t *__restrict__ offsets, int64_t N, int64_t n_atoms,
-                                  int32_t *__restrict__ tile_cfg, int32_t *__restrict__ n_tiles,
-                                  int64_t max_tiles, int32_t *status)
+constexpr int PLAN_SEG = 4096;  // offsets staged in LDS per step of the scan
+
+__global__ __launch_bounds__(256) void plan_tiles_kernel(const int64_t *__restrict__ offsets, int64_t N,
+                                                         int64_t n_atoms, int32_t *__restrict__ tile_cfg,
+                                                         int32_t *__restrict__ n_tiles, int64_t max_tiles,
+                                                         int32_t *status)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0)
-        return;
-    int64_t t = 0, tile_atoms = 0, tile_n = 0;
-    int64_t prev = offsets[0];
-    bool bad = (prev != 0);
-    tile_cfg[0] = 0;
-    for (int64_t c = 0; c < N && !bad; ++c) {
-        const int64_t nx = offsets[c + 1];
-        const int64_t cnt = nx - prev;
-        if (cnt < 0) {
-            bad = true;
-            break;
-        }
-        if (tile_n > 0 && (tile_atoms + cnt > KNM_CAP || tile_n == KNM_MAX_SEG)) {
-            if (++t >= max_tiles) {
-                bad = true;
-                break;
-            }
-            tile_cfg[t] = (int32_t)c;
-            tile_atoms = 0;
-            tile_n = 0;
-        }
-        tile_atoms += cnt;
-        ++tile_n;
-        prev = nx;
+    __shared__ int64_t seg[PLAN_SEG + 1];
+    __shared__ int bad_s;
+    // scan state, owned by thread 0
+    int64_t t = 0, tile_atoms = 0, tile_n = 0, prev = 0;
+    bool bad = false;
+    if (threadIdx.x == 0) {
+        bad_s = 0;
+        tile_cfg[0] = 0;
     }
+    for (int64_t base = 0; base < N; base += PLAN_SEG) {
+        const int64_t cnt = (N - base) < PLAN_SEG ? (N - base) : PLAN_SEG;
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i <= cnt; i += 256)
+            seg[i] = offsets[base + i];
+        __syncthreads();
+        if (threadIdx.x == 0 && !bad) {
+            if (base == 0) {
+                prev = seg[0];
+                bad = (prev != 0);
+            }
+            for (int64_t i = 0; i < cnt && !bad; ++i) {
+                const int64_t nx = seg[i + 1];
+                const int64_t na = nx - prev;
+                if (na < 0) {
+                    bad = true;
+                    break;
+                }
+                if (tile_n > 0 && (tile_atoms + na > KNM_CAP || tile_n == KNM_MAX_SEG)) {
+                    if (++t >= max_tiles) {
+                        bad = true;
+                        break;
+                    }
+                    tile_cfg[t] = (int32_t)(base + i);
+                    tile_atoms = 0;
+                    tile_n = 0;
+                }
+                tile_atoms += na;
+                ++tile_n;
+                prev = nx;
+            }
+            bad_s = bad ? 1 : 0;
+        }
+        __syncthreads();
+        if (bad_s)
+            break;
+    }
+    if (threadIdx.x != 0)
+        return;
     if (prev != n_atoms)
         bad = true;
     if (bad) {
@@ -388,7 +413,7 @@ hipError_t launch_predict(const double *X, int64_t n_atoms, const int64_t *offse
 hipError_t launch_plan_tiles(const int64_t *offsets, int64_t N, int64_t n_atoms, int32_t *tile_cfg,
                              int32_t *n_tiles, int64_t max_tiles, int32_t *status, hipStream_t s)
 {
-    hipLaunchKernelGGL(plan_tiles_kernel, dim3(1), dim3(64), 0, s, offsets, N, n_atoms, tile_cfg,
+    hipLaunchKernelGGL(plan_tiles_kernel, dim3(1), dim3(256), 0, s, offsets, N, n_atoms, tile_cfg,
                        n_tiles, max_tiles, status);
     return hipGetLastError();
 }
