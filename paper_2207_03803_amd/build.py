@@ -42,8 +42,15 @@ def build(verbose: bool = True) -> str:
     tmp = OUT + ".tmp"
     subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], check=True)
     os.replace(tmp, OUT)
+    # the roofline microbenchmarks (a standalone program)
+    peaks = os.path.join(HERE, "gap_peaks")
+    r = subprocess.run([HIPCC, *FLAGS, os.path.join(CSRC, "peaks.hip"), "-o", peaks + ".tmp"],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on peaks.hip:\n{r.stderr}")
+    os.replace(peaks + ".tmp", peaks)
     if verbose:
-        print(f"built {OUT}")
+        print(f"built {OUT} and {peaks}")
     return OUT
 
 
