@@ -21,8 +21,10 @@
  *    gap_layout_info are host structs.
  *  - Work is enqueued asynchronously on the handle's HIP stream (a hipStream_t
  *    passed as void*; NULL = the default stream).  Inputs must stay valid and
- *    unmodified until that work completes; the sparse set given to
- *    gap_build_knm must stay valid for later gap_predict calls.
+ *    unmodified until that work completes; sigma given to gap_build_knm is
+ *    read again by gap_solve (b assembly) and must stay valid until gap_solve's
+ *    work completes; the sparse set given to gap_build_knm must stay valid for
+ *    later gap_predict calls.
  *  - Argument errors are detected synchronously, before anything is enqueued,
  *    and returned as GAP_EINVAL / GAP_ENOMEM / GAP_ESTATE.  Failures found on
  *    the device (Cholesky pivot not positive, non-finite values) are reported
@@ -32,7 +34,8 @@
  *    may run concurrently on different streams.
  *  - Call order: gap_create -> gap_bind_workspace -> gap_build_knm ->
  *    gap_solve -> gap_predict*; gap_build_knm may be called again to start a
- *    new fit in the same handle.
+ *    new fit in the same handle.  A predict-only handle: gap_create ->
+ *    gap_set_model -> gap_predict*.
  *  - Descriptors are used as given: the covariance assumes unit-L2 rows but
  *    does not renormalise them.
  */
@@ -71,7 +74,8 @@ typedef struct gap_params {
     double jitter;            /* added to K_MM's diagonal before the Cholesky (>= 0) */
     int32_t precision;        /* gap_precision */
     int32_t max_refine_iters; /* mixed precision only: refinement iteration cap */
-    double refine_tol;        /* mixed precision only: stop when ||dc||/||c|| <= refine_tol */
+    double refine_tol;        /* mixed precision only: stop when ||dc||/||c|| <= refine_tol, or when
+                                 ||dc|| stops halving at a level <= 1e-9 ||c|| (FP64 rounding floor) */
     uint32_t flags;           /* GAP_FLAG_* */
 } gap_params;
 
@@ -83,7 +87,8 @@ typedef struct gap_handle_s *gap_handle;
 typedef struct gap_solve_info {
     int32_t device_status;   /* gap_status found on the device (GAP_OK when none) */
     int32_t refine_iters;    /* mixed precision: refinement iterations done (0 in FP64) */
-    double residual_norm2;   /* ||(Q^T b)[M:]||^2 = min of the loss at the returned c */
+    double residual_norm2;   /* min of the loss at the returned c: ||(Q^T b)[M:]||^2 in FP64,
+                                ||b - A c||^2 against the FP64 A in mixed precision */
     double grad_rel;         /* mixed precision: last ||dc|| / ||c||; 0 in FP64 */
     double est_err;          /* reserved: 0 */
 } gap_solve_info;
@@ -93,7 +98,7 @@ typedef struct gap_solve_info {
  *   rows 0..N-1, cols 0..M-1      Sigma^-1/2 K_NM after gap_build_knm; R and reflectors after gap_solve
  *   rows N..N+M-1, cols 0..M-1    L^T (upper triangular) after gap_build_knm
  *   col M                          b = [Sigma^-1/2 y ; 0] during gap_solve, Q^T b after it
- *   rows m..lda-1 and cols M+1..ncols-1 are zero padding (they do not change the solution). */
+ *   rows N+M..lda-1 are unused padding (never read). */
 typedef struct gap_layout_info {
     double *A_aug;
     int64_t lda;          /* rows of A_aug in memory (>= N + M) */
@@ -101,6 +106,8 @@ typedef struct gap_layout_info {
     int64_t N, M, n_atoms;
     double *tau;          /* [M] Householder weights after gap_solve */
     int32_t *device_status;
+    float *A32;           /* mixed precision: FP32 copy of [A | b] (same lda), holding R,
+                             reflectors and Q^T b after gap_solve; NULL in FP64 */
 } gap_layout_info;
 
 /* Create a handle bound to the current HIP device and `stream` (hipStream_t or NULL).
@@ -154,6 +161,14 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
 gap_status gap_predict(gap_handle h, const double *x_atoms, int64_t n_atoms,
                        const int64_t *offsets, int64_t n_configs, const double *c, double *y_out);
 
+/* Bind a resident model's sparse set [M x d] (device FP64, caller-owned) for
+ * gap_predict without a fit or a workspace (e.g. a served model whose fit has
+ * finished and released its workspace).  GAP_EINVAL on NULL or M < 1. */
+gap_status gap_set_model(gap_handle h, const double *x_sparse, int64_t M);
+
+/* Move the handle to another HIP stream (hipStream_t or NULL) for later calls. */
+gap_status gap_set_stream(gap_handle h, void *stream);
+
 /* Wait for the handle's stream; fill info (nullable) and return the device status. */
 gap_status gap_sync(gap_handle h, gap_solve_info *info);
 
@@ -165,6 +180,18 @@ gap_status gap_layout(gap_handle h, gap_layout_info *out);
  * [4] Householder QR incl. Q^T b, [5] back-substitution, [6] refinement.
  * Waits for the stream.  n = number of floats in ms (up to 8). */
 gap_status gap_stage_times(gap_handle h, float *ms, int n);
+
+/* Launch-shape knobs an autotuner may set per handle (0 = library default).
+ *   qr_split_wgs  target number of workgroups of the QR's split-K products
+ *                 Y^T C (sets the row-chunk height); 256 .. 65536. */
+typedef struct gap_tuning {
+    int32_t qr_split_wgs;
+    int32_t reserved[7];
+} gap_tuning;
+
+/* Set the handle's launch-shape knobs (host-only; affects later calls).  GAP_EINVAL on
+ * out-of-range values. */
+gap_status gap_set_tuning(gap_handle h, const gap_tuning *t);
 
 /* Human-readable name of a status code (static string). */
 const char *gap_status_string(gap_status s);

@@ -22,13 +22,18 @@ struct Layout {
     size_t off_A = 0, off_tau = 0, off_wpart = 0, off_T = 0, off_Tin = 0, off_U = 0, off_W = 0, off_ts_tiles = 0,
            off_ts_X = 0, off_ts_tau = 0, off_rhs = 0, off_misc = 0, off_tiles = 0, off_counters = 0,
            off_status = 0, total = 0;
+    // mixed precision only
+    bool mixed = false;
+    size_t off_A32 = 0, off_W32 = 0, off_r = 0, off_s = 0, off_z = 0, off_dc = 0, off_part = 0,
+           off_rnorm = 0, off_flags = 0, off_stats = 0;
 };
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-Layout make_layout(int64_t N, int64_t n_atoms, int64_t M)
+Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, bool mixed)
 {
     Layout L;
+    L.mixed = mixed;
     L.N = N;
     L.M = M;
     L.n_atoms = n_atoms;
@@ -58,6 +63,19 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M)
     L.off_tiles = take(sizeof(int32_t) * (size_t)(L.max_tiles + 2));
     L.off_counters = take(sizeof(unsigned) * 16);
     L.off_status = take(sizeof(int32_t) * 4);
+    if (mixed) {
+        const int64_t ldw = (L.ncols + 63) / 64 * 64;
+        L.off_A32 = take(sizeof(float) * (size_t)L.lda * (size_t)L.ncols);
+        L.off_W32 = take(sizeof(float) * 2 * QR_NB * (size_t)ldw);
+        L.off_r = take(sizeof(double) * (size_t)L.m);
+        L.off_s = take(sizeof(double) * (size_t)M);
+        L.off_z = take(sizeof(double) * (size_t)M);
+        L.off_dc = take(sizeof(double) * (size_t)M);
+        L.off_part = take(sizeof(double) * 8 * (size_t)L.m);
+        L.off_rnorm = take(sizeof(double) * (size_t)((L.m + 255) / 256 + 1));
+        L.off_flags = take(sizeof(int32_t) * 4);
+        L.off_stats = take(sizeof(double) * 4);
+    }
     L.total = o;
     return L;
 }
@@ -74,9 +92,12 @@ struct gap_handle_s {
     Layout L;
     const double *x_sparse = nullptr;
     const double *sigma = nullptr;
+    int64_t model_M = 0;      // set by gap_set_model
+    bool model_only = false;  // predict-only handle (no workspace)
     hipEvent_t ev[2 * N_STAGES] = {};
     bool timed[N_STAGES] = {};
     bool timing = false;
+    gap_tuning tuning = {};
 
     template <class T>
     T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
@@ -114,7 +135,9 @@ bool valid_params(const gap_params *p)
 {
     return p && p->d >= 1 && p->zeta >= 1 && p->zeta <= 8 && p->sigma_w > 0.0 && isfinite(p->sigma_w) &&
            p->jitter >= 0.0 && isfinite(p->jitter) &&
-           (p->precision == GAP_FP64 || p->precision == GAP_MIXED_FP32);
+           (p->precision == GAP_FP64 || p->precision == GAP_MIXED_FP32) &&
+           (p->precision == GAP_FP64 || (p->max_refine_iters >= 0 && p->max_refine_iters <= 1000 &&
+                                          p->refine_tol >= 0.0));
 }
 
 gap_status dev(hipError_t e) { return e == hipSuccess ? GAP_OK : GAP_EDEVICE; }
@@ -149,7 +172,7 @@ size_t gap_workspace_bytes(const gap_params *p, int64_t n_configs, int64_t n_ato
 {
     if (!valid_params(p) || n_configs < 1 || n_atoms < 0 || M < 1)
         return 0;
-    return make_layout(n_configs, n_atoms, M).total;
+    return make_layout(n_configs, n_atoms, M, p->precision == GAP_MIXED_FP32).total;
 }
 
 gap_status gap_create(const gap_params *p, void *stream, gap_handle *out)
@@ -198,12 +221,13 @@ gap_status gap_build_knm(gap_handle h, const double *x_atoms, int64_t n_atoms, c
     if (!x_atoms || !config_offsets || !x_sparse || !sigma || n_atoms < 1 || n_configs < 1 || M < 1 ||
         n_configs > INT32_MAX - 1)
         return GAP_EINVAL;
-    const Layout L = make_layout(n_configs, n_atoms, M);
+    const Layout L = make_layout(n_configs, n_atoms, M, h->p.precision == GAP_MIXED_FP32);
     if (L.total > h->ws_bytes)
         return GAP_ENOMEM;
     h->L = L;
     h->x_sparse = x_sparse;
     h->sigma = sigma;
+    h->model_only = false;
     hipStream_t s = h->stream;
     const gap_params &p = h->p;
     const double sw2 = p.sigma_w * p.sigma_w;
@@ -278,6 +302,15 @@ gap_status gap_sync(gap_handle h, gap_solve_info *info)
         memset(info, 0, sizeof(*info));
         info->device_status = st;
         info->residual_norm2 = res;
+        if (h->ws && h->L.total && h->L.mixed) {
+            int32_t it = 0;
+            double st2[2] = {0.0, 0.0};
+            if (hipMemcpy(&it, h->at<int32_t>(h->L.off_flags) + 1, sizeof(it), hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(st2, h->at<double>(h->L.off_stats), sizeof(st2), hipMemcpyDeviceToHost) != hipSuccess)
+                return GAP_EDEVICE;
+            info->refine_iters = it;
+            info->grad_rel = st2[1];
+        }
     }
     return (gap_status)st;
 }
@@ -313,18 +346,57 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
     w.ts_tau = h->at<double>(L.off_ts_tau);
     w.tree = L.tree;
     w.max_chunks = qr_max_chunks();
+    w.split_wgs = h->tuning.qr_split_wgs;
     w.status = h->status();
-    h->mark(4, false);
-    GAP_TRY(dev(launch_geqrf(w, s)));
-    h->mark(4, true);
-
     double *rhs = h->at<double>(L.off_rhs);
-    const double *qtb = A + L.M * L.lda;
-    h->mark(5, false);
-    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((L.M + 255) / 256)), dim3(256), 0, s, qtb, rhs, L.M);
-    GAP_TRY(dev(launch_trsv_upper(A, L.lda, L.M, rhs, c_out, h->status(), s)));
-    h->mark(5, true);
-    GAP_TRY(dev(launch_sumsq(qtb + L.M, L.N, h->misc(), h->misc() + 1, h->counters() + 8, s)));
+    if (!L.mixed) {
+        h->mark(4, false);
+        GAP_TRY(dev(launch_geqrf(w, s)));
+        h->mark(4, true);
+        const double *qtb = A + L.M * L.lda;
+        h->mark(5, false);
+        hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((L.M + 255) / 256)), dim3(256), 0, s, qtb, rhs, L.M);
+        GAP_TRY(dev(launch_trsv_upper(A, L.lda, L.M, rhs, c_out, h->status(), s)));
+        h->mark(5, true);
+        GAP_TRY(dev(launch_sumsq(qtb + L.M, L.N, h->misc(), h->misc() + 1, h->counters() + 8, s)));
+    } else {
+        // FP32 copy of [A | b], FP32 Householder QR (FP64 reflector norms), then
+        // FP64 refinement against the untouched FP64 [A | b]
+        float *A32 = h->at<float>(L.off_A32);
+        w.A32 = A32;
+        w.W32 = h->at<float>(L.off_W32);
+        h->mark(4, false);
+        GAP_TRY(dev(launch_convert_f64_f32(A, A32, L.lda * L.ncols, s)));
+        GAP_TRY(dev(launch_geqrf(w, s)));
+        h->mark(4, true);
+        h->mark(5, false);
+        GAP_TRY(dev(launch_copy_f32_f64(A32 + L.M * L.lda, rhs, L.M, s)));
+        GAP_TRY(dev(launch_trsv_upper_f32(A32, L.lda, L.M, rhs, c_out, nullptr, s)));
+        h->mark(5, true);
+        RefineWork rw{};
+        rw.A = A;
+        rw.lda = L.lda;
+        rw.m = L.m;
+        rw.n = L.M;
+        rw.R32 = A32;
+        rw.c = c_out;
+        rw.r = h->at<double>(L.off_r);
+        rw.s = h->at<double>(L.off_s);
+        rw.z = h->at<double>(L.off_z);
+        rw.dc = h->at<double>(L.off_dc);
+        rw.part = h->at<double>(L.off_part);
+        rw.rnorm_part = h->at<double>(L.off_rnorm);
+        rw.done = h->at<int32_t>(L.off_flags);
+        rw.iters = h->at<int32_t>(L.off_flags) + 1;
+        rw.stats = h->at<double>(L.off_stats);
+        rw.tol = h->p.refine_tol;
+        rw.status = h->status();
+        h->mark(6, false);
+        GAP_TRY(dev(launch_refine(rw, h->p.max_refine_iters, s)));
+        h->mark(6, true);
+        GAP_TRY(dev(launch_check_finite(c_out, L.M, h->status(), s)));
+        hipLaunchKernelGGL(copy_kernel, dim3(1), dim3(256), 0, s, rw.stats, h->misc(), (int64_t)1);
+    }
     h->state = ST_SOLVED;
     if (info)
         return gap_sync(h, info);
@@ -336,11 +408,30 @@ gap_status gap_predict(gap_handle h, const double *x_atoms, int64_t n_atoms, con
 {
     if (!h || !x_atoms || !offsets || !c || !y_out || n_atoms < 0 || n_configs < 1)
         return GAP_EINVAL;
-    if (h->state < ST_BUILT || !h->x_sparse)
+    if ((h->state < ST_BUILT && !h->model_only) || !h->x_sparse)
         return GAP_ESTATE;
     const double sw2 = h->p.sigma_w * h->p.sigma_w;
-    return dev(launch_predict(x_atoms, n_atoms, offsets, n_configs, h->x_sparse, h->L.M, h->p.d, h->p.zeta,
-                              sw2, c, y_out, h->stream));
+    const int64_t M = h->model_only ? h->model_M : h->L.M;
+    return dev(launch_predict(x_atoms, n_atoms, offsets, n_configs, h->x_sparse, M, h->p.d, h->p.zeta, sw2, c,
+                              y_out, h->stream));
+}
+
+gap_status gap_set_model(gap_handle h, const double *x_sparse, int64_t M)
+{
+    if (!h || !x_sparse || M < 1)
+        return GAP_EINVAL;
+    h->x_sparse = x_sparse;
+    h->model_M = M;
+    h->model_only = true;
+    return GAP_OK;
+}
+
+gap_status gap_set_stream(gap_handle h, void *stream)
+{
+    if (!h)
+        return GAP_EINVAL;
+    h->stream = reinterpret_cast<hipStream_t>(stream);
+    return GAP_OK;
 }
 
 gap_status gap_layout(gap_handle h, gap_layout_info *out)
@@ -357,6 +448,7 @@ gap_status gap_layout(gap_handle h, gap_layout_info *out)
     out->n_atoms = h->L.n_atoms;
     out->tau = h->at<double>(h->L.off_tau);
     out->device_status = h->status();
+    out->A32 = h->L.mixed ? h->at<float>(h->L.off_A32) : nullptr;
     return GAP_OK;
 }
 
@@ -374,6 +466,16 @@ gap_status gap_stage_times(gap_handle h, float *ms, int n)
                 ms[i] = v;
         }
     }
+    return GAP_OK;
+}
+
+gap_status gap_set_tuning(gap_handle h, const gap_tuning *t)
+{
+    if (!h || !t)
+        return GAP_EINVAL;
+    if (t->qr_split_wgs != 0 && (t->qr_split_wgs < 256 || t->qr_split_wgs > 65536))
+        return GAP_EINVAL;
+    h->tuning = *t;
     return GAP_OK;
 }
 

@@ -332,3 +332,128 @@ DEV void load_run(const double *__restrict__ p, double (&v)[N])
         v[2 * e + 1] = x.y;
     }
 }
+
+// ---------------------------------------------------------------------------
+// FP32 MFMA tile machinery (v_mfma_f32_16x16x4_f32).  Operands are staged in
+// LDS K-major as for FP64; lane l supplies A(l%16, l/16) and B(l/16, l%16);
+// accumulator element e of lane l is C(4*(l/16) + e, l%16) (measured on
+// gfx950).
+// ---------------------------------------------------------------------------
+template <class S>
+DEV void zero_acc32(f4 (&acc)[S::FM][S::FN])
+{
+#pragma unroll
+    for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < S::FN; ++j)
+            acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+}
+
+template <class S>
+DEV void mma_stage32(const float *__restrict__ As, const float *__restrict__ Bs, f4 (&acc)[S::FM][S::FN],
+                     int wm, int wn, int lane)
+{
+#pragma unroll
+    for (int kk = 0; kk < S::BK; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        float a[S::FM], b[S::FN];
+#pragma unroll
+        for (int i = 0; i < S::FM; ++i)
+            a[i] = As[kr * S::LDA + wm * S::TM + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < S::FN; ++j)
+            b[j] = Bs[kr * S::LDB + wn * S::TN + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+            for (int j = 0; j < S::FN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+template <class S>
+DEV int acc32_row(int wm, int i, int lane, int e) { return wm * S::TM + i * 16 + 4 * (lane >> 4) + e; }
+template <class S>
+DEV int acc32_col(int wn, int j, int lane, int e)
+{
+    (void)e;
+    return wn * S::TN + j * 16 + (lane & 15);
+}
+
+// FP32 version of gemm_tile_runs (float LDS stages, same run-loader contract).
+template <class S, bool A_KC, bool B_KC, class FA, class FB>
+DEV void gemm_tile_runs32(f4 (&acc)[S::FM][S::FN], float *lds, int64_t K, FA fa, FB fb)
+{
+    constexpr int VA = S::BM * S::BK / S::NT;
+    constexpr int VB = S::BN * S::BK / S::NT;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave / S::WN, wn = wave % S::WN;
+    float ra[VA], rb[VB];
+    int ar, ak, br, bk;
+    if constexpr (A_KC) {
+        ar = t / (S::BK / VA);
+        ak = (t % (S::BK / VA)) * VA;
+    } else {
+        ak = t / (S::BM / VA);
+        ar = (t % (S::BM / VA)) * VA;
+    }
+    if constexpr (B_KC) {
+        br = t / (S::BK / VB);
+        bk = (t % (S::BK / VB)) * VB;
+    } else {
+        bk = t / (S::BN / VB);
+        br = (t % (S::BN / VB)) * VB;
+    }
+    auto store = [&](float *As, float *Bs) {
+#pragma unroll
+        for (int e = 0; e < VA; ++e) {
+            if constexpr (A_KC)
+                As[(ak + e) * S::LDA + ar] = ra[e];
+            else
+                As[ak * S::LDA + ar + e] = ra[e];
+        }
+#pragma unroll
+        for (int e = 0; e < VB; ++e) {
+            if constexpr (B_KC)
+                Bs[(bk + e) * S::LDB + br] = rb[e];
+            else
+                Bs[bk * S::LDB + br + e] = rb[e];
+        }
+    };
+    const int64_t nk = (K + S::BK - 1) / S::BK;
+    if (nk <= 0)
+        return;
+    fa(ar, (int64_t)ak, ra);
+    fb(br, (int64_t)bk, rb);
+    store(lds, lds + S::A_ELEMS);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        float *cur = lds + (kt & 1) * S::STAGE;
+        float *nxt = lds + ((kt + 1) & 1) * S::STAGE;
+        const bool more = kt + 1 < nk;
+        if (more) {
+            fa(ar, (kt + 1) * S::BK + ak, ra);
+            fb(br, (kt + 1) * S::BK + bk, rb);
+        }
+        mma_stage32<S>(cur, cur + S::A_ELEMS, acc, wm, wn, lane);
+        if (more)
+            store(nxt, nxt + S::A_ELEMS);
+        __syncthreads();
+    }
+}
+
+// Load n consecutive floats (16-byte aligned).
+template <int N>
+DEV void load_run(const float *__restrict__ p, float (&v)[N])
+{
+    static_assert(N % 4 == 0, "runs of a multiple of 4 floats");
+    const float4 *q = reinterpret_cast<const float4 *>(p);
+#pragma unroll
+    for (int e = 0; e < N / 4; ++e) {
+        const float4 x = q[e];
+        v[4 * e] = x.x;
+        v[4 * e + 1] = x.y;
+        v[4 * e + 2] = x.z;
+        v[4 * e + 3] = x.w;
+    }
+}

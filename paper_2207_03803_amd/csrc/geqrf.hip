@@ -80,6 +80,14 @@ DEV void leaf_rows(int64_t i, int64_t n0, int64_t mk, int64_t &lo, int64_t &hi)
     hi = ((i + 1) * mk) / n0;
 }
 
+// The matrix being factored: FP64 storage (w.A) or FP32 storage (w.A32).
+template <class T>
+DEV T *qmat(const QrWork &w);
+template <>
+DEV double *qmat<double>(const QrWork &w) { return w.A; }
+template <>
+DEV float *qmat<float>(const QrWork &w) { return w.A32; }
+
 // Sum over the NPART consecutive lanes that hold one column (deterministic).
 DEV double col_sum(double v)
 {
@@ -95,6 +103,7 @@ DEV double col_sum(double v)
 // of the panel; level l >= 1 stacks the R factors of up to 4 children.  The
 // factored tile (R above the diagonal, v below) and tau go to the tree.
 // ---------------------------------------------------------------------------
+template <class T>
 __global__ __launch_bounds__(TS_NT) void tsqr_factor_kernel(QrWork w, int64_t j0, int pw, int level,
                                                           int64_t n_level, int64_t n_prev, int64_t mk)
 {
@@ -106,12 +115,12 @@ __global__ __launch_bounds__(TS_NT) void tsqr_factor_kernel(QrWork w, int64_t j0
     if (level == 0) {
         int64_t lo, hi;
         leaf_rows(node, n_level, mk, lo, hi);
-        const double *col = w.A + (j0 + q) * w.lda + j0 + lo;
+        const T *col = qmat<T>(w) + (j0 + q) * w.lda + j0 + lo;
         const int64_t nr = hi - lo;
 #pragma unroll
         for (int i = 0; i < SLOTS; ++i) {
             const int r = NPART * i + part;
-            x[i] = (q < pw && r < nr) ? col[r] : 0.0;
+            x[i] = (q < pw && r < nr) ? (double)col[r] : 0.0;
         }
     } else {
         const double *prev = w.ts_tiles + w.tree.tile_off[level - 1];
@@ -183,6 +192,7 @@ __global__ __launch_bounds__(TS_NT) void tsqr_factor_kernel(QrWork w, int64_t j0
 // node's pw x pw slice of its parent's X (the identity at the root).  Level 0
 // writes its X into the panel's rows of A.
 // ---------------------------------------------------------------------------
+template <class T>
 __global__ __launch_bounds__(TS_NT) void tsqr_formq_kernel(QrWork w, int64_t j0, int pw, int level,
                                                          int64_t n_level, int is_root, int64_t mk)
 {
@@ -240,13 +250,13 @@ __global__ __launch_bounds__(TS_NT) void tsqr_formq_kernel(QrWork w, int64_t j0,
         int64_t lo, hi;
         leaf_rows(node, n_level, mk, lo, hi);
         if (q < pw) {
-            double *col = w.A + (j0 + q) * w.lda + j0 + lo;
+            T *col = qmat<T>(w) + (j0 + q) * w.lda + j0 + lo;
             const int64_t nr = hi - lo;
 #pragma unroll
             for (int i = 0; i < SLOTS; ++i) {
                 const int r = NPART * i + part;
                 if (r < nr)
-                    col[r] = x[i];
+                    col[r] = (T)x[i];
             }
         }
     } else {
@@ -263,6 +273,7 @@ __global__ __launch_bounds__(TS_NT) void tsqr_formq_kernel(QrWork w, int64_t j0,
 // T = -U S Y1^-T, R = S R_root; writes R above and Y1 below the diagonal of
 // the panel's top block, tau = diag(T), and U for the row solve below.
 // ---------------------------------------------------------------------------
+template <class T>
 __global__ __launch_bounds__(256) void tsqr_lu_kernel(QrWork w, int64_t j0, int pw, int root_level, double *Tout)
 {
     __shared__ double B[NB][NB + 1];
@@ -271,7 +282,7 @@ __global__ __launch_bounds__(256) void tsqr_lu_kernel(QrWork w, int64_t j0, int 
     const int t = threadIdx.x;
     for (int idx = t; idx < pw * pw; idx += 256) {
         const int r = idx % pw, c = idx / pw;
-        B[r][c] = w.A[(j0 + c) * w.lda + j0 + r];
+        B[r][c] = (double)qmat<T>(w)[(j0 + c) * w.lda + j0 + r];
     }
     __syncthreads();
     for (int k = 0; k < pw; ++k) {
@@ -321,7 +332,7 @@ __global__ __launch_bounds__(256) void tsqr_lu_kernel(QrWork w, int64_t j0, int 
                 out = sg[r] * root[c * TR + r];
             else
                 out = B[r][c];
-            w.A[(j0 + c) * w.lda + j0 + r] = out;
+            qmat<T>(w)[(j0 + c) * w.lda + j0 + r] = (T)out;
         }
         if (r == c && r < pw)
             w.tau[j0 + r] = tv;
@@ -329,6 +340,7 @@ __global__ __launch_bounds__(256) void tsqr_lu_kernel(QrWork w, int64_t j0, int 
 }
 
 // Rows below the top block: Y = Q U^-1 (one row per thread).
+template <class T>
 __global__ __launch_bounds__(256) void tsqr_trsm_kernel(QrWork w, int64_t j0, int pw)
 {
     __shared__ double U[NB][NB + 1];
@@ -341,7 +353,7 @@ __global__ __launch_bounds__(256) void tsqr_trsm_kernel(QrWork w, int64_t j0, in
     double y[NB];
 #pragma unroll
     for (int c = 0; c < NB; ++c)
-        y[c] = (c < pw) ? w.A[(j0 + c) * w.lda + r] : 0.0;
+        y[c] = (c < pw) ? (double)qmat<T>(w)[(j0 + c) * w.lda + r] : 0.0;
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
         if (c < pw) {
@@ -355,20 +367,21 @@ __global__ __launch_bounds__(256) void tsqr_trsm_kernel(QrWork w, int64_t j0, in
 #pragma unroll
     for (int c = 0; c < NB; ++c)
         if (c < pw)
-            w.A[(j0 + c) * w.lda + r] = y[c];
+            qmat<T>(w)[(j0 + c) * w.lda + r] = (T)y[c];
 }
 
 // Householder vectors of the column block at (j0, j0), pw <= 2 * QR_NB wide:
 // unit lower trapezoidal.
-DEV double ypanel(const double *A, int64_t lda, int64_t m, int64_t j0, int pw, int64_t r, int p)
+template <class T>
+DEV T ypanel(const T *A, int64_t lda, int64_t m, int64_t j0, int pw, int64_t r, int p)
 {
     if (p >= pw || r >= m)
-        return 0.0;
+        return T(0);
     const int64_t d = r - (j0 + p);
     if (d < 0)
-        return 0.0;
+        return T(0);
     if (d == 0)
-        return 1.0;
+        return T(1);
     return A[(j0 + p) * lda + r];
 }
 
@@ -453,8 +466,9 @@ __global__ __launch_bounds__(256, 2) void qr_wpart_kernel(QrWork w, int64_t j0, 
 // W[p][q] = sum_{s <= p} T[s][p] sum_ch P[ch][s][q] (T upper triangular,
 // row-major with leading dimension tld); 64 columns per workgroup, thread
 // (q, part) handles panel rows p = part, part + 4, ...; chunks summed in order.
+template <class TW>
 __global__ __launch_bounds__(256) void qr_wred_kernel(QrWork w, const double *__restrict__ T, int tld, int pw,
-                                                      int64_t nch, int64_t nt)
+                                                      int64_t nch, int64_t nt, TW *__restrict__ Wout)
 {
     __shared__ double Pm[OB][64 + 1];
     const int ql = threadIdx.x & 63, part = threadIdx.x >> 6;
@@ -473,7 +487,7 @@ __global__ __launch_bounds__(256) void qr_wred_kernel(QrWork w, const double *__
         double s = 0.0;
         for (int r = 0; r <= p; ++r)
             s += T[r * tld + p] * Pm[r][ql];
-        w.W[p * w.ldw + q] = s;
+        Wout[p * w.ldw + q] = (TW)s;
     }
 }
 
@@ -581,10 +595,141 @@ __global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0,
             }
 }
 
-// Split of rows [r0, m) into chunks for the split-K products.
-static void chunking(int64_t rows, int64_t ncb, int64_t &chunk, int64_t &nch)
+using WS32 = TileShape<OB, 64, 32, 2, 2>;    // FP32 P = Y^T C
+using US32 = TileShape<128, 128, 32, 2, 2>;  // FP32 C^T -= W^T Y^T
+
+// FP32-storage versions of qr_wpart_kernel / qr_update_kernel on FP32 MFMA.
+__global__ __launch_bounds__(256, 2) void qr_wpart32_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt,
+                                                            int ymode, int64_t r0, int64_t chunk)
 {
-    nch = (2048 + ncb - 1) / ncb;
+    __shared__ float lds[2 * WS32::STAGE];
+    const int64_t ch = blockIdx.y;
+    const int64_t q0 = (int64_t)blockIdx.x * WS32::BN;
+    const int64_t rlo = r0 + ch * chunk;
+    int64_t rhi = rlo + chunk;
+    if (rhi > w.m)
+        rhi = w.m;
+    if (rlo >= rhi)
+        return;
+    f4 acc[WS32::FM][WS32::FN];
+    zero_acc32<WS32>(acc);
+    const float *A = w.A32;
+    const int64_t lda = w.lda, m = w.m;
+    const bool masked = rlo < j0 + pw;
+    constexpr int VA = WS32::BM * WS32::BK / WS32::NT, VB = WS32::BN * WS32::BK / WS32::NT;
+    auto fa = [&](int p, int64_t k, float (&v)[VA]) {
+        const int64_t r = rlo + k;
+        if (p >= pw) {
+#pragma unroll
+            for (int e = 0; e < VA; ++e)
+                v[e] = 0.0f;
+        } else if (!masked && r + VA <= rhi) {
+            load_run(A + (j0 + p) * lda + r, v);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VA; ++e)
+                v[e] = (r + e < rhi) ? ypanel(A, lda, m, j0, pw, r + e, p) : 0.0f;
+        }
+    };
+    auto fb = [&](int qi, int64_t k, float (&v)[VB]) {
+        const int64_t r = rlo + k, q = q0 + qi;
+        if (q >= nt) {
+#pragma unroll
+            for (int e = 0; e < VB; ++e)
+                v[e] = 0.0f;
+        } else if (ymode) {
+#pragma unroll
+            for (int e = 0; e < VB; ++e)
+                v[e] = (r + e < rhi) ? ypanel(A, lda, m, c0, (int)nt, r + e, (int)q) : 0.0f;
+        } else {
+            const float *col = A + (c0 + q) * lda + r;
+            if (r + VB <= rhi) {
+                load_run(col, v);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VB; ++e)
+                    v[e] = (r + e < rhi) ? col[e] : 0.0f;
+            }
+        }
+    };
+    gemm_tile_runs32<WS32, true, true>(acc, lds, rhi - rlo, fa, fb);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave / WS32::WN, wn = wave % WS32::WN;
+    double *P = w.wpart + ch * OB * w.ncols;
+#pragma unroll
+    for (int i = 0; i < WS32::FM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < WS32::FN; ++jj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int p = acc32_row<WS32>(wm, i, lane, e);
+                const int64_t q = q0 + acc32_col<WS32>(wn, jj, lane, e);
+                if (p < pw && q < nt)
+                    P[p * w.ncols + q] = (double)acc[i][jj][e];
+            }
+}
+
+__global__ __launch_bounds__(256, 2) void qr_update32_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt)
+{
+    __shared__ float lds[2 * US32::STAGE];
+    const int64_t q0 = (int64_t)blockIdx.y * US32::BM;
+    const int64_t r0 = j0 + (int64_t)blockIdx.x * US32::BN;
+    const float *A = w.A32;
+    const int64_t lda = w.lda, m = w.m, ldW = w.ldw;
+    const float *W = w.W32;
+    f4 acc[US32::FM][US32::FN];
+    zero_acc32<US32>(acc);
+    const bool masked = r0 < j0 + pw;
+    constexpr int VA = US32::BM * US32::BK / US32::NT, VB = US32::BN * US32::BK / US32::NT;
+    auto fa = [&](int qi, int64_t p, float (&v)[VA]) {
+        const int64_t q = q0 + qi;
+        if (p >= pw) {
+#pragma unroll
+            for (int e = 0; e < VA; ++e)
+                v[e] = 0.0f;
+        } else if (q + VA <= nt) {
+            load_run(W + p * ldW + q, v);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VA; ++e)
+                v[e] = (q + e < nt) ? W[p * ldW + q + e] : 0.0f;
+        }
+    };
+    auto fb = [&](int ri, int64_t p, float (&v)[VB]) {
+        const int64_t r = r0 + ri;
+        if (p >= pw) {
+#pragma unroll
+            for (int e = 0; e < VB; ++e)
+                v[e] = 0.0f;
+        } else if (!masked && r + VB <= m) {
+            load_run(A + (j0 + p) * lda + r, v);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VB; ++e)
+                v[e] = ypanel(A, lda, m, j0, pw, r + e, (int)p);
+        }
+    };
+    gemm_tile_runs32<US32, false, false>(acc, lds, pw, fa, fb);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave / US32::WN, wn = wave % US32::WN;
+    float *C = w.A32 + c0 * lda;
+#pragma unroll
+    for (int i = 0; i < US32::FM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < US32::FN; ++jj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t q = q0 + acc32_row<US32>(wm, i, lane, e);
+                const int64_t r = r0 + acc32_col<US32>(wn, jj, lane, e);
+                if (r < m && q < nt)
+                    C[q * lda + r] -= acc[i][jj][e];
+            }
+}
+
+// Split of rows [r0, m) into chunks for the split-K products.
+static void chunking(int64_t rows, int64_t ncb, int64_t &chunk, int64_t &nch, int64_t target = 2048)
+{
+    nch = (target + ncb - 1) / ncb;
     if (nch > MAX_CHUNKS)
         nch = MAX_CHUNKS;
     chunk = (rows + nch - 1) / nch;
@@ -595,23 +740,39 @@ static void chunking(int64_t rows, int64_t ncb, int64_t &chunk, int64_t &nch)
 }
 
 // TSQR + reconstruction of the panel at (j0, j0) of width pw; its T goes to Tout.
+template <class T>
 static void factor_panel(const QrWork &w, int64_t j0, int pw, double *Tout, hipStream_t s)
 {
     const int64_t mk = w.m - j0;
     const PanelTree pt = panel_tree(mk);
     for (int l = 0; l < pt.levels; ++l)
-        hipLaunchKernelGGL(tsqr_factor_kernel, dim3((unsigned)pt.nodes[l]), dim3(TS_NT), 0, s, w, j0, pw, l,
+        hipLaunchKernelGGL(tsqr_factor_kernel<T>, dim3((unsigned)pt.nodes[l]), dim3(TS_NT), 0, s, w, j0, pw, l,
                            pt.nodes[l], l > 0 ? pt.nodes[l - 1] : 0, mk);
     for (int l = pt.levels - 1; l >= 0; --l)
-        hipLaunchKernelGGL(tsqr_formq_kernel, dim3((unsigned)pt.nodes[l]), dim3(TS_NT), 0, s, w, j0, pw, l,
+        hipLaunchKernelGGL(tsqr_formq_kernel<T>, dim3((unsigned)pt.nodes[l]), dim3(TS_NT), 0, s, w, j0, pw, l,
                            pt.nodes[l], l == pt.levels - 1 ? 1 : 0, mk);
-    hipLaunchKernelGGL(tsqr_lu_kernel, dim3(1), dim3(256), 0, s, w, j0, pw, pt.levels - 1, Tout);
+    hipLaunchKernelGGL(tsqr_lu_kernel<T>, dim3(1), dim3(256), 0, s, w, j0, pw, pt.levels - 1, Tout);
     if (mk > pw)
-        hipLaunchKernelGGL(tsqr_trsm_kernel, dim3((unsigned)((mk - pw + 255) / 256)), dim3(256), 0, s, w, j0, pw);
+        hipLaunchKernelGGL(tsqr_trsm_kernel<T>, dim3((unsigned)((mk - pw + 255) / 256)), dim3(256), 0, s, w, j0,
+                           pw);
+}
+
+// P = Y^T C (split over row chunks) for the block at (j0, j0) of width pw.
+template <class T>
+static void launch_wpart(const QrWork &w, int64_t j0, int pw, int64_t c0, int64_t nt, int ymode, int64_t r0,
+                         int64_t chunk, int64_t ncb, int64_t nch, hipStream_t s)
+{
+    if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL(qr_wpart_kernel, dim3((unsigned)ncb, (unsigned)nch), dim3(256), 0, s, w, j0, pw, c0,
+                           nt, ymode, r0, chunk);
+    else
+        hipLaunchKernelGGL(qr_wpart32_kernel, dim3((unsigned)ncb, (unsigned)nch), dim3(256), 0, s, w, j0, pw,
+                           c0, nt, ymode, r0, chunk);
 }
 
 // C := (I - Y T Y^T)^T C for the columns c0 .. c0+nt, Y the block at (j0, j0) of width pw.
-static void apply_block(const QrWork &w, int64_t j0, int pw, const double *T, int tld, int64_t c0, int64_t nt,
+template <class T>
+static void apply_block(const QrWork &w, int64_t j0, int pw, const double *Tm, int tld, int64_t c0, int64_t nt,
                         hipStream_t s)
 {
     if (nt <= 0)
@@ -619,42 +780,59 @@ static void apply_block(const QrWork &w, int64_t j0, int pw, const double *T, in
     const int64_t rows = w.m - j0;
     const int64_t ncb = (nt + WS::BN - 1) / WS::BN;
     int64_t chunk, nch;
-    chunking(rows, ncb, chunk, nch);
-    hipLaunchKernelGGL(qr_wpart_kernel, dim3((unsigned)ncb, (unsigned)nch), dim3(256), 0, s, w, j0, pw, c0, nt, 0,
-                       j0, chunk);
-    hipLaunchKernelGGL(qr_wred_kernel, dim3((unsigned)((nt + 63) / 64)), dim3(256), 0, s, w, T, tld, pw, nch, nt);
-    hipLaunchKernelGGL(qr_update_kernel,
-                       dim3((unsigned)((rows + US::BN - 1) / US::BN), (unsigned)((nt + US::BM - 1) / US::BM)),
-                       dim3(256), 0, s, w, j0, pw, c0, nt);
+    chunking(rows, ncb, chunk, nch, w.split_wgs > 0 ? w.split_wgs : 2048);
+    launch_wpart<T>(w, j0, pw, c0, nt, 0, j0, chunk, ncb, nch, s);
+    if constexpr (sizeof(T) == 8) {
+        hipLaunchKernelGGL(qr_wred_kernel<double>, dim3((unsigned)((nt + 63) / 64)), dim3(256), 0, s, w, Tm, tld,
+                           pw, nch, nt, w.W);
+        hipLaunchKernelGGL(qr_update_kernel,
+                           dim3((unsigned)((rows + US::BN - 1) / US::BN), (unsigned)((nt + US::BM - 1) / US::BM)),
+                           dim3(256), 0, s, w, j0, pw, c0, nt);
+    } else {
+        hipLaunchKernelGGL(qr_wred_kernel<float>, dim3((unsigned)((nt + 63) / 64)), dim3(256), 0, s, w, Tm, tld,
+                           pw, nch, nt, w.W32);
+        hipLaunchKernelGGL(qr_update32_kernel,
+                           dim3((unsigned)((rows + US32::BN - 1) / US32::BN),
+                                (unsigned)((nt + US32::BM - 1) / US32::BM)),
+                           dim3(256), 0, s, w, j0, pw, c0, nt);
+    }
 }
 
-hipError_t launch_geqrf(const QrWork &w, hipStream_t s)
+template <class T>
+static void geqrf(const QrWork &w, hipStream_t s)
 {
     double *Ta = w.Tin, *Tb = w.Tin + NB * NB;
     for (int64_t J = 0; J < w.n; J += OB) {
         const int pwa = (int)((w.n - J) < NB ? (w.n - J) : NB);
-        factor_panel(w, J, pwa, Ta, s);
+        factor_panel<T>(w, J, pwa, Ta, s);
         const int64_t jb = J + pwa;
         const int pwb = (int)((w.n - jb) < NB ? (w.n - jb) : NB);
         if (pwb <= 0) {
-            apply_block(w, J, pwa, Ta, NB, jb, w.ncols - jb, s);
+            apply_block<T>(w, J, pwa, Ta, NB, jb, w.ncols - jb, s);
             continue;
         }
         // bring panel B up to date with panel A, factor it, then merge the two
         // compact-WY factors and update everything to the right at once
-        apply_block(w, J, pwa, Ta, NB, jb, pwb, s);
-        factor_panel(w, jb, pwb, Tb, s);
+        apply_block<T>(w, J, pwa, Ta, NB, jb, pwb, s);
+        factor_panel<T>(w, jb, pwb, Tb, s);
         {
             const int64_t rows = w.m - jb;
             int64_t chunk, nch;
             chunking(rows, 1, chunk, nch);
-            hipLaunchKernelGGL(qr_wpart_kernel, dim3(1, (unsigned)nch), dim3(256), 0, s, w, J, pwa, jb,
-                               (int64_t)pwb, 1, jb, chunk);
+            launch_wpart<T>(w, J, pwa, jb, (int64_t)pwb, 1, jb, chunk, 1, nch, s);
             hipLaunchKernelGGL(qr_tcombine_kernel, dim3(1), dim3(256), 0, s, w, pwb, nch);
         }
         const int64_t c0 = jb + pwb;
-        apply_block(w, J, pwa + pwb, w.T, OB, c0, w.ncols - c0, s);
+        apply_block<T>(w, J, pwa + pwb, w.T, OB, c0, w.ncols - c0, s);
     }
+}
+
+hipError_t launch_geqrf(const QrWork &w, hipStream_t s)
+{
+    if (w.A32)
+        geqrf<float>(w, s);
+    else
+        geqrf<double>(w, s);
     return hipGetLastError();
 }
 

@@ -70,6 +70,7 @@ TsqrTree tsqr_tree(int64_t m);
 
 struct QrWork {
     double *A;        // column-major [lda x ncols]: factor columns 0..n-1, apply to n..ncols-1
+    float *A32;       // when non-null: factor this FP32 copy instead (same layout); A is not touched
     int64_t lda, m, n, ncols;
     int64_t ldw;      // leading dimension of W (ncols rounded up to 64)
     double *tau;      // [n]
@@ -78,11 +79,13 @@ struct QrWork {
     double *Tin;      // [2 * QR_NB * QR_NB] T of the block's two panels (row-major, ld QR_NB)
     double *U;        // [QR_NB * QR_NB] LU factor of (Q - S) of the current panel
     double *W;        // [2 QR_NB * ldw] T^T Y^T C, row-major by block column
+    float *W32;       // same for the FP32 factorisation
     double *ts_tiles; // TsqrTree::tiles_doubles
     double *ts_X;     // TsqrTree::tiles_doubles
     double *ts_tau;   // TsqrTree::tau_doubles
     TsqrTree tree;    // sized for m rows
     int64_t max_chunks;
+    int32_t split_wgs;  // target workgroups of the split-K products (0 = default)
     int32_t *status;
 };
 int64_t qr_max_chunks();
@@ -94,8 +97,33 @@ hipError_t launch_geqrf(const QrWork &w, hipStream_t s);
 // (tail != nullptr) sum of squares of tail[0..tail_n) into *tail_out.
 hipError_t launch_trsv_upper(const double *R, int64_t ld, int64_t n, double *rhs, double *c,
                              int32_t *status, hipStream_t s);
+hipError_t launch_trsv_upper_f32(const float *R, int64_t ld, int64_t n, double *rhs, double *x,
+                                 const int32_t *skip, hipStream_t s);
+// Solve R^T x = rhs (forward substitution) for the FP32-stored upper R.
+hipError_t launch_trsv_upper_t_f32(const float *R, int64_t ld, int64_t n, double *rhs, double *x,
+                                   const int32_t *skip, hipStream_t s);
+hipError_t launch_copy_f32_f64(const float *src, double *dst, int64_t n, hipStream_t s);
 hipError_t launch_sumsq(const double *x, int64_t n, double *out, double *part, unsigned *counter,
                         hipStream_t s);
+
+// ------------------------------------------------------ mixed-precision refinement
+struct RefineWork {
+    const double *A;     // FP64 [A | b], column-major lda; b is column n
+    int64_t lda, m, n;
+    const float *R32;    // FP32 factor (upper triangle of the first n rows), same lda
+    double *c;           // [n] solution, refined in place
+    double *r;           // [m] residual
+    double *s, *z, *dc;  // [n] work
+    double *part;        // [8 * m] column-chunk partials of A c
+    double *rnorm_part;  // [ceil(m / 256)] partial ||r||^2
+    int32_t *done;       // convergence flag
+    int32_t *iters;      // iterations done
+    double *stats;       // [0] ||r||^2, [1] last ||dc|| / ||c||
+    double tol;
+    int32_t *status;
+};
+hipError_t launch_convert_f64_f32(const double *a, float *b, int64_t n, hipStream_t s);
+hipError_t launch_refine(const RefineWork &w, int max_iters, hipStream_t s);
 
 // ---------------------------------------------------------------- utilities
 // b = [y / sigma ; 0] into column `col` of the column-major A (lda rows).

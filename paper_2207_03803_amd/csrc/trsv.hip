@@ -6,60 +6,158 @@ namespace gap {
 
 constexpr int TB = 64;
 
-// Solve the bw x bw diagonal block at (b0, b0) with one wave; rhs is updated
-// in place, c[b0 .. b0+bw) written.
-__global__ __launch_bounds__(64) void trsv_diag_kernel(const double *R, int64_t ld, int64_t b0, int bw,
-                                                       double *rhs, double *c)
+// Back-substitution R x = rhs for the n x n upper triangle of R (column-major,
+// ld), blocks of 64 from the bottom: one wave solves a diagonal block, then a
+// GEMV removes the block's contribution from the rows above.  rhs is used as
+// work.  R may be stored in FP32 (TR = float); the arithmetic is FP64.  When
+// skip is non-null and *skip != 0 the kernels return at once.
+
+// Solve the bw x bw diagonal block at (b0, b0) with one wave.
+template <class TR>
+__global__ __launch_bounds__(64) void trsv_diag_kernel(const TR *R, int64_t ld, int64_t b0, int bw, double *rhs,
+                                                       double *x, const int32_t *skip)
 {
     __shared__ double S[TB][TB + 1];
-    __shared__ double x[TB];
+    __shared__ double xs[TB];
+    if (skip && *skip)
+        return;
     const int l = threadIdx.x;
     for (int cc = 0; cc < bw; ++cc)
         if (l < bw)
-            S[l][cc] = R[(b0 + cc) * ld + b0 + l];
+            S[l][cc] = (double)R[(b0 + cc) * ld + b0 + l];
     double r = (l < bw) ? rhs[b0 + l] : 0.0;
     __syncthreads();
     for (int i = bw - 1; i >= 0; --i) {
         if (l == i)
-            x[i] = r / S[i][i];
+            xs[i] = r / S[i][i];
         __syncthreads();
         if (l < i)
-            r -= S[l][i] * x[i];
+            r -= S[l][i] * xs[i];
     }
     if (l < bw)
-        c[b0 + l] = x[l];
+        x[b0 + l] = xs[l];
 }
 
-// rhs[r] -= sum_i R[r][b0+i] c[b0+i] for r < b0.
-__global__ __launch_bounds__(256) void trsv_gemv_kernel(const double *R, int64_t ld, int64_t b0, int bw,
-                                                        double *rhs, const double *c)
+// rhs[r] -= sum_i R[r][b0+i] x[b0+i] for r < b0.
+template <class TR>
+__global__ __launch_bounds__(256) void trsv_gemv_kernel(const TR *R, int64_t ld, int64_t b0, int bw, double *rhs,
+                                                        const double *x, const int32_t *skip)
 {
-    __shared__ double x[TB];
+    __shared__ double xs[TB];
+    if (skip && *skip)
+        return;
     if (threadIdx.x < bw)
-        x[threadIdx.x] = c[b0 + threadIdx.x];
+        xs[threadIdx.x] = x[b0 + threadIdx.x];
     __syncthreads();
     const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (r >= b0)
         return;
     double s = 0.0;
     for (int i = 0; i < bw; ++i)
-        s += R[(b0 + i) * ld + r] * x[i];
+        s += (double)R[(b0 + i) * ld + r] * xs[i];
     rhs[r] -= s;
 }
 
-hipError_t launch_trsv_upper(const double *R, int64_t ld, int64_t n, double *rhs, double *c,
-                             int32_t *status, hipStream_t s)
+// Forward substitution R^T x = rhs (R upper, so R^T is lower), blocks from the
+// top: one wave per diagonal block, then rhs[i] -= sum_j R[j][i] x[j] for the
+// rows below (column i of R holds the R[j][i], contiguous in j).
+template <class TR>
+__global__ __launch_bounds__(64) void trsv_t_diag_kernel(const TR *R, int64_t ld, int64_t b0, int bw, double *rhs,
+                                                         double *x, const int32_t *skip)
+{
+    __shared__ double S[TB][TB + 1];
+    __shared__ double xs[TB];
+    if (skip && *skip)
+        return;
+    const int l = threadIdx.x;
+    for (int cc = 0; cc < bw; ++cc)
+        if (l < bw)
+            S[l][cc] = (double)R[(b0 + cc) * ld + b0 + l];  // S[j][i] = R[b0+j][b0+i]
+    double r = (l < bw) ? rhs[b0 + l] : 0.0;
+    __syncthreads();
+    for (int i = 0; i < bw; ++i) {
+        if (l == i)
+            xs[i] = r / S[i][i];
+        __syncthreads();
+        if (l > i && l < bw)
+            r -= S[i][l] * xs[i];
+    }
+    if (l < bw)
+        x[b0 + l] = xs[l];
+}
+
+template <class TR>
+__global__ __launch_bounds__(256) void trsv_t_gemv_kernel(const TR *R, int64_t ld, int64_t n, int64_t b0, int bw,
+                                                          double *rhs, const double *x, const int32_t *skip)
+{
+    __shared__ double xs[TB];
+    if (skip && *skip)
+        return;
+    if (threadIdx.x < bw)
+        xs[threadIdx.x] = x[b0 + threadIdx.x];
+    __syncthreads();
+    const int64_t i = b0 + bw + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n)
+        return;
+    const TR *col = R + i * ld + b0;
+    double s = 0.0;
+    for (int j = 0; j < bw; ++j)
+        s += (double)col[j] * xs[j];
+    rhs[i] -= s;
+}
+
+template <class TR>
+static hipError_t trsv_upper(const TR *R, int64_t ld, int64_t n, double *rhs, double *x, const int32_t *skip,
+                             hipStream_t s)
 {
     const int64_t nb = (n + TB - 1) / TB;
     for (int64_t b = nb - 1; b >= 0; --b) {
         const int64_t b0 = b * TB;
         const int bw = (int)((n - b0) < TB ? (n - b0) : TB);
-        hipLaunchKernelGGL(trsv_diag_kernel, dim3(1), dim3(64), 0, s, R, ld, b0, bw, rhs, c);
+        hipLaunchKernelGGL(trsv_diag_kernel<TR>, dim3(1), dim3(64), 0, s, R, ld, b0, bw, rhs, x, skip);
         if (b0 > 0)
-            hipLaunchKernelGGL(trsv_gemv_kernel, dim3((unsigned)((b0 + 255) / 256)), dim3(256), 0, s, R,
-                               ld, b0, bw, rhs, (const double *)c);
+            hipLaunchKernelGGL(trsv_gemv_kernel<TR>, dim3((unsigned)((b0 + 255) / 256)), dim3(256), 0, s, R, ld,
+                               b0, bw, rhs, (const double *)x, skip);
     }
+    return hipGetLastError();
+}
+
+template <class TR>
+static hipError_t trsv_upper_t(const TR *R, int64_t ld, int64_t n, double *rhs, double *x, const int32_t *skip,
+                               hipStream_t s)
+{
+    const int64_t nb = (n + TB - 1) / TB;
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t b0 = b * TB;
+        const int bw = (int)((n - b0) < TB ? (n - b0) : TB);
+        hipLaunchKernelGGL(trsv_t_diag_kernel<TR>, dim3(1), dim3(64), 0, s, R, ld, b0, bw, rhs, x, skip);
+        const int64_t rest = n - b0 - bw;
+        if (rest > 0)
+            hipLaunchKernelGGL(trsv_t_gemv_kernel<TR>, dim3((unsigned)((rest + 255) / 256)), dim3(256), 0, s, R, ld,
+                               n, b0, bw, rhs, (const double *)x, skip);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_trsv_upper(const double *R, int64_t ld, int64_t n, double *rhs, double *c, int32_t *status,
+                             hipStream_t s)
+{
+    hipError_t e = trsv_upper<double>(R, ld, n, rhs, c, nullptr, s);
+    if (e != hipSuccess)
+        return e;
     return launch_check_finite(c, n, status, s);
+}
+
+hipError_t launch_trsv_upper_f32(const float *R, int64_t ld, int64_t n, double *rhs, double *x, const int32_t *skip,
+                                 hipStream_t s)
+{
+    return trsv_upper<float>(R, ld, n, rhs, x, skip, s);
+}
+
+hipError_t launch_trsv_upper_t_f32(const float *R, int64_t ld, int64_t n, double *rhs, double *x,
+                                   const int32_t *skip, hipStream_t s)
+{
+    return trsv_upper_t<float>(R, ld, n, rhs, x, skip, s);
 }
 
 __global__ __launch_bounds__(256) void sumsq_kernel(const double *x, int64_t n, double *out, double *part,
@@ -114,6 +212,21 @@ hipError_t launch_assemble_b(const double *y, const double *sigma, int64_t N, do
 {
     hipLaunchKernelGGL(assemble_b_kernel, dim3((unsigned)((lda + 255) / 256)), dim3(256), 0, s, y, sigma,
                        N, bcol, lda);
+    return hipGetLastError();
+}
+
+__global__ void copy_f32_f64_kernel(const float *src, double *dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n)
+        dst[i] = (double)src[i];
+}
+
+hipError_t launch_copy_f32_f64(const float *src, double *dst, int64_t n, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(copy_f32_f64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
     return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ GAP_FLAG_TIMING = 1
 # Every entry point include/gap.h declares.
 EXPORTS = ["gap_create", "gap_workspace_bytes", "gap_bind_workspace", "gap_build_knm", "gap_solve",
            "gap_predict", "gap_sync", "gap_layout", "gap_stage_times", "gap_status_string",
-           "gap_destroy"]
+           "gap_set_tuning", "gap_set_model", "gap_set_stream", "gap_destroy"]
 
 STAGES = ["knm", "kmm", "cholesky", "assemble_b", "qr", "trsv", "refine", "reserved"]
 
@@ -38,10 +38,14 @@ class GapSolveInfo(ctypes.Structure):
                 ("est_err", ctypes.c_double)]
 
 
+class GapTuning(ctypes.Structure):
+    _fields_ = [("qr_split_wgs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
 class GapLayoutInfo(ctypes.Structure):
     _fields_ = [("A_aug", ctypes.c_void_p), ("lda", ctypes.c_int64), ("ncols", ctypes.c_int64),
                 ("N", ctypes.c_int64), ("M", ctypes.c_int64), ("n_atoms", ctypes.c_int64),
-                ("tau", ctypes.c_void_p), ("device_status", ctypes.c_void_p)]
+                ("tau", ctypes.c_void_p), ("device_status", ctypes.c_void_p), ("A32", ctypes.c_void_p)]
 
 
 class GapError(RuntimeError):
@@ -75,8 +79,12 @@ def lib():
     L.gap_status_string.argtypes = [I32]
     L.gap_status_string.restype = ctypes.c_char_p
     L.gap_destroy.argtypes = [P]
+    L.gap_set_tuning.argtypes = [P, ctypes.POINTER(GapTuning)]
+    L.gap_set_model.argtypes = [P, P, I64]
+    L.gap_set_stream.argtypes = [P, P]
     for n in ("gap_create", "gap_bind_workspace", "gap_build_knm", "gap_solve", "gap_predict", "gap_sync",
-              "gap_layout", "gap_stage_times", "gap_destroy"):
+              "gap_layout", "gap_stage_times", "gap_set_tuning", "gap_set_model", "gap_set_stream",
+              "gap_destroy"):
         getattr(L, n).restype = I32
     _lib = L
     return L
@@ -138,6 +146,9 @@ class Handle:
         return ws
 
     def build_knm(self, X, offsets, XM, sigma):
+        # the library keeps these pointers (sigma for gap_solve, XM for gap_predict):
+        # hold the tensors until the next build
+        self._inputs = (X, offsets, XM, sigma)
         _check(lib().gap_build_knm(self.h, _ptr(X), X.shape[0], _ptr(offsets), offsets.numel() - 1,
                                    _ptr(XM), XM.shape[0], _ptr(sigma)), "gap_build_knm")
 
@@ -176,12 +187,37 @@ class Handle:
         flat = self.ws[off:off + 8 * n].view(torch.float64)
         return flat.view(lay.ncols, lay.lda), lay
 
+    def A32_view(self):
+        """Mixed precision: the FP32 copy of [A | b] as a torch view [ncols, lda]."""
+        import torch
+
+        lay = self.layout()
+        if not lay.A32:
+            return None
+        off = lay.A32 - self.ws.data_ptr()
+        n = lay.lda * lay.ncols
+        return self.ws[off:off + 4 * n].view(torch.float32).view(lay.ncols, lay.lda)
+
     def tau_view(self):
         import torch
 
         lay = self.layout()
         off = lay.tau - self.ws.data_ptr()
         return self.ws[off:off + 8 * lay.M].view(torch.float64)
+
+    def set_tuning(self, qr_split_wgs=0):
+        t = GapTuning()
+        t.qr_split_wgs = int(qr_split_wgs)
+        _check(lib().gap_set_tuning(self.h, ctypes.byref(t)), "gap_set_tuning")
+
+    def set_model(self, XM):
+        """Predict-only use: bind a resident sparse set (keep XM alive)."""
+        self.model_XM = XM
+        _check(lib().gap_set_model(self.h, _ptr(XM), XM.shape[0]), "gap_set_model")
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(lib().gap_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)), "gap_set_stream")
 
     def close(self):
         if self.h:

@@ -1,0 +1,256 @@
+"""Batched hyperparameter sweep: many independent GAP fits replayed as one HIP graph.
+
+A sweep is a list of fits of different sizes and hyperparameters over shared
+descriptor pools (one pool per descriptor length d; a fit with N_c
+configurations takes the pool's first N_c, and draws its own sparse set from
+their atoms).  The fits are spread over S streams by longest-processing-time
+order on their flop counts, every fit's `gap_build_knm` + `gap_solve` is
+captured once into a single graph (fork/join over the streams), and the graph
+is replayed.  Each fit keeps its own handle and workspace; the library's
+kernels are deterministic, so a fit's weights are bitwise the same alone, in a
+replay, or on any stream.
+
+The autotuner times whole-sweep replays over a small grid of launch shapes
+(stream count, split-K workgroup target of the QR) and keeps a table keyed by
+the sweep's shape bucket.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import gap
+
+TUNING_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+
+# The sweep recipe: N_c ~ U[2000, 30000] configurations of U[8, 64] atoms,
+# d in {128, 256, 400}, M ~ U[500, 4000], zeta in {2, 3, 4}, sigma_E in
+# {1e-4, 1e-3, 1e-2} per atom; pools of 30000 configurations per d.
+SWEEP_RECIPE = dict(n_fits=64, n_configs=(2000, 30000), atoms=(8, 64), ds=(128, 256, 400),
+                    M=(500, 4000), zetas=(2, 3, 4), sigmas=(1e-4, 1e-3, 1e-2), pool_configs=30000)
+
+
+@dataclass
+class FitSpec:
+    idx: int
+    d: int
+    n_configs: int
+    M: int
+    zeta: int
+    sigma_per_atom: float
+    seed: int
+
+    def flops(self, atoms_mean=36.0):
+        n_atoms = self.n_configs * atoms_mean
+        m, n = self.n_configs + self.M, self.M
+        return 2 * n_atoms * self.M * self.d + 2 * m * n * n
+
+
+def make_sweep(seed=0, n_fits=None, scale=1.0, recipe=SWEEP_RECIPE):
+    """Draw the sweep's fit specifications (sizes scaled by `scale` for tests)."""
+    rng = np.random.default_rng(seed)
+    n_fits = n_fits or recipe["n_fits"]
+    lo_n, hi_n = recipe["n_configs"]
+    lo_m, hi_m = recipe["M"]
+    specs = []
+    for i in range(n_fits):
+        N = int(rng.integers(lo_n, hi_n + 1) * scale)
+        M = int(rng.integers(lo_m, hi_m + 1) * scale)
+        specs.append(FitSpec(i, int(rng.choice(recipe["ds"])), max(N, 8), max(M, 8), int(rng.choice(recipe["zetas"])),
+                             float(rng.choice(recipe["sigmas"])), int(seed * 1000 + i)))
+    return specs
+
+
+@dataclass
+class Pool:
+    d: int
+    offsets: np.ndarray     # int64 [n_configs + 1]
+    X: object               # torch [n_atoms, d] float64 (cuda)
+
+
+def make_pools(specs, seed=0, atoms=(8, 64), device="cuda"):
+    """One descriptor pool per d, as large as the largest fit that uses it."""
+    from . import synth
+
+    pools = {}
+    for d in sorted({s.d for s in specs}):
+        n = max(s.n_configs for s in specs if s.d == d)
+        inp = synth.make_fit_inputs_torch(n_configs=n, atoms=atoms, d=d, M=1, seed=seed + d, device=device)
+        pools[d] = Pool(d, inp.offsets, inp.X)
+    return pools
+
+
+@dataclass
+class Fit:
+    spec: FitSpec
+    handle: object = None
+    ws: object = None
+    offsets: object = None
+    XM: object = None
+    sigma: object = None
+    y: object = None
+    c: object = None
+    X: object = None
+    host: dict = field(default_factory=dict)
+
+
+class Sweep:
+    """The fits of one sweep with their inputs resident on the device."""
+
+    def __init__(self, specs, pools, precision=gap.GAP_MIXED_FP32, streams=8, split_wgs=0,
+                 max_refine_iters=20, refine_tol=1e-12):
+        import torch
+
+        self.specs = specs
+        self.pools = pools
+        self.precision = precision
+        self.n_streams = streams
+        self.streams = [torch.cuda.Stream() for _ in range(streams)]
+        self.root = torch.cuda.Stream()
+        self.fits = []
+        order = sorted(specs, key=lambda s: -s.flops())
+        loads = [0.0] * streams
+        self.assign = [[] for _ in range(streams)]
+        for s in order:  # longest processing time first, onto the least-loaded stream
+            k = int(np.argmin(loads))
+            loads[k] += s.flops()
+            self.assign[k].append(s.idx)
+        stream_of = {i: k for k, lst in enumerate(self.assign) for i in lst}
+        for s in specs:
+            pool = pools[s.d]
+            n_atoms = int(pool.offsets[s.n_configs])
+            rng = np.random.default_rng(s.seed)
+            sparse_idx = np.sort(rng.choice(n_atoms, size=s.M, replace=False))
+            counts = np.diff(pool.offsets[:s.n_configs + 1])
+            sigma = s.sigma_per_atom * counts.astype(np.float64)
+            f = Fit(s)
+            f.X = pool.X[:n_atoms]
+            f.offsets = torch.from_numpy(np.ascontiguousarray(pool.offsets[:s.n_configs + 1])).cuda()
+            f.XM = pool.X[torch.from_numpy(sparse_idx).cuda()].contiguous()
+            f.sigma = torch.from_numpy(sigma).cuda()
+            f.host = dict(c_true=rng.standard_normal(s.M), noise=rng.standard_normal(s.n_configs),
+                          sparse_idx=sparse_idx, sigma=sigma)
+            p = gap.params(s.d, s.zeta, 1.0, 1e-8, precision=precision, max_refine_iters=max_refine_iters,
+                           refine_tol=refine_tol)
+            f.handle = gap.Handle(p, stream=self.streams[stream_of[s.idx]])
+            if split_wgs:
+                f.handle.set_tuning(qr_split_wgs=split_wgs)
+            f.ws = f.handle.alloc_workspace(s.n_configs, n_atoms, s.M)
+            f.c = torch.empty(s.M, dtype=torch.float64, device="cuda")
+            self.fits.append(f)
+        self._targets()
+        self.graph = None
+
+    def _targets(self):
+        """y = prediction with c_true plus sigma * noise, through the library."""
+        import torch
+
+        for f in self.fits:
+            with torch.cuda.stream(f.handle.stream):
+                f.handle.build_knm(f.X, f.offsets, f.XM, f.sigma)
+                y = torch.empty(f.spec.n_configs, dtype=torch.float64, device="cuda")
+                f.handle.predict(f.X, f.offsets, torch.from_numpy(f.host["c_true"]).cuda(), y)
+                y += f.sigma * torch.from_numpy(f.host["noise"]).cuda()
+                f.y = y
+        torch.cuda.synchronize()
+
+    def enqueue(self):
+        """Every fit's build + solve on its stream (no host synchronisation)."""
+        for k, lst in enumerate(self.assign):
+            for i in lst:
+                f = self.fits[i]
+                f.handle.build_knm(f.X, f.offsets, f.XM, f.sigma)
+                f.handle.solve(f.y, f.c, info=False)
+
+    def run_eager(self):
+        import torch
+
+        torch.cuda.synchronize()
+        for st in self.streams:
+            st.wait_stream(torch.cuda.current_stream())
+        self.enqueue()
+        for st in self.streams:
+            torch.cuda.current_stream().wait_stream(st)
+        torch.cuda.synchronize()
+
+    def capture(self):
+        """Capture the whole sweep once: the root stream forks to the S streams and joins them."""
+        import torch
+
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(self.root):
+            g.capture_begin()
+            for st in self.streams:
+                st.wait_stream(self.root)
+            self.enqueue()
+            for st in self.streams:
+                self.root.wait_stream(st)
+            g.capture_end()
+        torch.cuda.synchronize()
+        self.graph = g
+        return g
+
+    def replay(self, n=1):
+        import torch
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            self.graph.replay()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    def statuses(self):
+        return [f.handle.sync()[0] for f in self.fits]
+
+    def weights(self):
+        return [f.c.cpu().numpy() for f in self.fits]
+
+    def close(self):
+        for f in self.fits:
+            f.handle.close()
+
+
+def bucket(specs):
+    """Shape bucket of a sweep for the tuning table."""
+    n = len(specs)
+    mm = int(np.median([s.M for s in specs]))
+    nn = int(np.median([s.n_configs for s in specs]))
+    return f"fits{n}_M{1 << max(0, mm.bit_length() - 1)}_N{1 << max(0, nn.bit_length() - 1)}"
+
+
+def load_table(path=TUNING_TABLE):
+    if os.path.exists(path):
+        return json.load(open(path))
+    return {}
+
+
+def autotune(specs, pools, precision=gap.GAP_MIXED_FP32, candidates=None, replays=1, path=TUNING_TABLE,
+             log=print):
+    """Time whole-sweep graph replays for each candidate launch shape and keep the best.
+
+    Returns (best, results); stores {bucket: best} in the table at `path`.
+    """
+    candidates = candidates or [dict(streams=s, split_wgs=w) for s in (4, 8, 16) for w in (1024, 2048, 4096)]
+    results = []
+    for cand in candidates:
+        sw = Sweep(specs, pools, precision=precision, streams=cand["streams"], split_wgs=cand["split_wgs"])
+        sw.capture()
+        sw.replay(1)
+        t = sw.replay(replays)
+        results.append(dict(cand, seconds=t))
+        log(f"[autotune] {cand} -> {t * 1e3:.1f} ms per sweep")
+        sw.close()
+        del sw
+    best = min(results, key=lambda r: r["seconds"])
+    table = load_table(path)
+    table[bucket(specs)] = dict(streams=best["streams"], split_wgs=best["split_wgs"],
+                                seconds=best["seconds"], precision=int(precision))
+    with open(path, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    return best, results

@@ -22,7 +22,7 @@ class GpuFit:
     """Build + solve one fit on the GPU; keeps the handle and the A copy."""
 
     def __init__(self, X, offsets, XM, sigma, y, zeta, sigma_w=1.0, jitter=1e-8, keep_A=False,
-                 timing=False, precision=0):
+                 timing=False, precision=0, max_refine_iters=20, refine_tol=1e-12):
         import torch
 
         from paper_2207_03803_amd import gap
@@ -37,7 +37,8 @@ class GpuFit:
         self.N = self.offsets.numel() - 1
         self.M = self.XM.shape[0]
         d = self.X.shape[1]
-        self.h = gap.Handle(gap.params(d, zeta, sigma_w, jitter, precision=precision, flags=flags))
+        self.h = gap.Handle(gap.params(d, zeta, sigma_w, jitter, precision=precision, flags=flags,
+                                       max_refine_iters=max_refine_iters, refine_tol=refine_tol))
         self.h.alloc_workspace(self.N, self.X.shape[0], self.M)
         self.c = torch.empty(self.M, dtype=torch.float64, device="cuda")
 

@@ -116,3 +116,37 @@ def test_predict_equals_knm_c_at_full_size(full_fit):
     err = np.linalg.norm(got - expect) / np.linalg.norm(expect)
     log(f"  predict vs K_NM c rel err {err:.2e}")
     assert err <= 1e-12
+
+
+def test_mixed_precision_at_full_size(full_fit):
+    """FP32 QR + FP64 refinement at full size: the refined c satisfies the FP64
+    normal equations as tightly as the FP64 path, and matches its loss."""
+    import torch
+
+    from paper_2207_03803_amd import gap
+
+    f = full_fit
+    inp, w, A = f["inp"], f["w"], f["A"]
+    N, M = inp.n_configs, w["M"]
+    h = gap.Handle(gap.params(w["d"], w["zeta"], w["sigma_w"], w["jitter"], precision=gap.GAP_MIXED_FP32,
+                              max_refine_iters=30, refine_tol=1e-12))
+    h.alloc_workspace(N, inp.n_atoms, M)
+    sigma = torch.from_numpy(inp.sigma).cuda()  # read again by gap_solve: keep it alive
+    h.build_knm(inp.X, f["offsets"], inp.XM, sigma)
+    c = torch.empty(M, dtype=torch.float64, device="cuda")
+    y = torch.from_numpy(f["y"]).cuda()
+    info = h.solve(y, c)
+    assert info.device_status == gap.GAP_OK
+    cm = c.cpu().numpy()
+    Amat = A[:M, :N + M].T
+    b = np.zeros(N + M)
+    b[:N] = f["y"] / inp.sigma
+    r = b - Amat @ cm
+    nA = np.linalg.norm(Amat)
+    eta = np.linalg.norm(Amat.T @ r) / (nA * (nA * np.linalg.norm(cm) + np.linalg.norm(b)))
+    loss = float(r @ r)
+    log(f"  mixed: {info.refine_iters} refinement steps (last |dc|/|c| {info.grad_rel:.1e}), eta {eta:.2e}, "
+        f"loss rel diff vs FP64 path {abs(loss - f['info'].residual_norm2) / loss:.2e}")
+    assert eta <= 1e-12
+    assert abs(loss - f["info"].residual_norm2) <= 1e-8 * loss
+    h.close()

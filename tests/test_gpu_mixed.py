@@ -1,0 +1,76 @@
+"""Mixed precision (FP32 Householder QR with FP64 reflector norms, FP64
+refinement against the FP64 stacked matrix): c within 1e-8 of the FP64 oracle,
+with the error reported per refinement step."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_03803_amd import synth
+from tests.gpu_helpers import GpuFit, log
+
+pytestmark = pytest.mark.gpu
+
+TOL_MIXED = 1e-8
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
+
+
+def _case(orc, n_configs, atoms, d, M, zeta, seed):
+    inp = synth.make_fit_inputs(n_configs=n_configs, atoms=atoms, d=d, M=M, seed=seed)
+    y = oracle.targets(orc, inp, zeta)
+    ref = orc.fit(inp.X, inp.offsets, inp.XM, inp.sigma, y, zeta, jitter=1e-8, keep=True)
+    assert ref.status == 0
+    return inp, y, ref
+
+
+def _mixed(inp, y, zeta, iters, tol=1e-14):
+    from paper_2207_03803_amd import gap
+
+    g = GpuFit(inp.X, inp.offsets, inp.XM, inp.sigma, y, zeta, precision=gap.GAP_MIXED_FP32,
+               max_refine_iters=iters, refine_tol=tol)
+    g.build()
+    g.h.solve(g.y, g.c, info=False)  # a capped run may end in GAP_ENOCONV: read it with sync()
+    s, info = g.h.sync()
+    return g, (s, info)
+
+
+@pytest.fixture(scope="module")
+def orc_m():
+    return oracle.Oracle()
+
+
+@pytest.mark.parametrize("name,args", [
+    ("tiny", (200, (8, 64), 64, 256, 2, 0)),
+    ("ragged", (400, (16, 64), 96, 333, 4, 3)),
+    ("mid-size d=400 zeta=4", (2000, (16, 64), 400, 520, 4, 5)),
+])
+def test_mixed_refines_to_fp64_accuracy(orc_m, name, args):
+    from paper_2207_03803_amd import gap
+
+    inp, y, ref = _case(orc_m, *args)
+    zeta = args[4]
+    errs = []
+    for k in (1, 2, 3, 5):
+        g, _ = _mixed(inp, y, zeta, k, tol=0.0)  # tol 0: run exactly k steps
+        errs.append(rel(g.c.cpu().numpy(), ref.c))
+    g, (s, info) = _mixed(inp, y, zeta, 20, tol=1e-14)
+    assert s == gap.GAP_OK
+    c = g.c.cpu().numpy()
+    err = rel(c, ref.c)
+    log(f"  {name}: c rel err after 1,2,3,5 steps {['%.1e' % e for e in errs]}; "
+        f"converged in {info.refine_iters} steps to {err:.2e} (last |dc|/|c| {info.grad_rel:.1e})")
+    assert info.device_status == gap.GAP_OK
+    assert err <= TOL_MIXED
+    assert abs(info.residual_norm2 - ref.loss_tail) <= 1e-8 * ref.loss_tail
+
+
+def test_mixed_reports_no_convergence(orc_m):
+    """An unattainable tolerance within one step: GAP_ENOCONV, c still improved."""
+    from paper_2207_03803_amd import gap
+
+    inp, y, ref = _case(orc_m, 200, (8, 64), 64, 256, 2, 0)
+    g, (s, info) = _mixed(inp, y, 2, 1, tol=0.0)
+    assert s == gap.GAP_ENOCONV
+    assert info.refine_iters == 1

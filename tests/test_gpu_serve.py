@@ -1,0 +1,87 @@
+"""Serving loop: fits and predicts arriving over time on several streams.  Every
+request's result is bitwise the same as the same request run alone, fitted
+weights match the oracle, and the latency report is well formed."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpu_helpers import log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def served():
+    import torch
+
+    from paper_2207_03803_amd import gap, serve, sweep, synth
+
+    reqs = serve.make_requests(24, rate=400.0, seed=5, mix=(0.6, 0.0, 0.4), small_scale=0.04)
+    specs = [r.spec for r in reqs if r.kind == "fit"]
+    # every fit serves predicts of d=400 descriptors only if it has d=400; force the sweep's d mix
+    pools = sweep.make_pools(specs, seed=5)
+    pp = synth.make_fit_inputs_torch(n_configs=5000, atoms=(8, 64), d=400, M=1, seed=77)
+    if 400 not in pools:
+        pools[400] = sweep.Pool(400, pp.offsets, pp.X)
+    srv = serve.Server(pools, slots=4, hbm_budget=8 << 30, predict_pool=(pp.offsets, pp.X))
+    for r in reqs:
+        srv.prepare(r)
+    torch.cuda.synchronize()
+    srv.run(reqs)
+    torch.cuda.synchronize()
+    yield srv, reqs
+
+
+def test_every_request_served(served):
+    from paper_2207_03803_amd import gap, serve
+
+    srv, reqs = served
+    fits = [r for r in reqs if r.kind == "fit"]
+    preds = [r for r in reqs if r.kind == "predict"]
+    assert all(r.done >= r.admitted >= r.arrival for r in fits)
+    assert all(r.meta["status"] == gap.GAP_OK for r in fits)
+    # predicts that arrived before any d=400 model existed may wait; all must be served by the end
+    assert all(r.done >= 0 for r in preds if r.model >= 0)
+    rep = serve.latency_report(reqs)
+    log(f"  latency report: {rep}")
+    assert rep["fit"]["p99_ms"] >= rep["fit"]["p50_ms"] > 0
+
+
+def test_served_results_match_alone_and_oracle(served):
+    import torch
+
+    from paper_2207_03803_amd import gap
+
+    srv, reqs = served
+    orc = oracle.Oracle()
+    checked = 0
+    for r in reqs:
+        m = r.meta
+        if r.kind == "fit":
+            p = gap.params(r.spec.d, r.spec.zeta, 1.0, 1e-8)
+            h = gap.Handle(p)
+            h.alloc_workspace(r.spec.n_configs, m["X"].shape[0], r.spec.M)
+            h.build_knm(m["X"], m["offsets"], m["XM"], m["sigma"])
+            c = torch.empty(r.spec.M, dtype=torch.float64, device="cuda")
+            h.solve(m["y"], c)
+            h.close()
+            assert np.array_equal(c.cpu().numpy(), r.result), r.rid
+            if checked < 3:
+                ref = orc.fit(m["X"].cpu().numpy(), m["offsets"].cpu().numpy(), m["XM"].cpu().numpy(),
+                              m["sigma"].cpu().numpy(), m["y"].cpu().numpy(), r.spec.zeta, jitter=1e-8)
+                err = float(np.linalg.norm(r.result - ref.c) / np.linalg.norm(ref.c))
+                log(f"  served fit {r.rid}: N={r.spec.n_configs} M={r.spec.M} d={r.spec.d}: c rel err {err:.2e}")
+                assert err <= 1e-8
+                checked += 1
+        elif r.model >= 0:
+            XM, c, zeta, d, _ = srv.models[r.model] if r.model in srv.models else (None,) * 5
+            if XM is None:
+                continue
+            p = gap.params(d, zeta, 1.0, 1e-8)
+            h = gap.Handle(p)
+            h.set_model(XM)
+            out = torch.empty(m["n"], dtype=torch.float64, device="cuda")
+            h.predict(m["X"], m["offsets"], c, out)
+            torch.cuda.synchronize()
+            h.close()
+            assert np.array_equal(out.cpu().numpy(), r.result), r.rid
