@@ -1,12 +1,22 @@
 """Benchmark: one GAP fit (K_NM build + Cholesky + Householder QR + solve) at
 the realistic workload, N = 1e5 configurations of 16..64 atoms, d = 400,
-M = 1e4 sparse points, zeta = 4, FP64.  Prints one JSON line.
+M = 1e4 sparse points, zeta = 4, FP64, beside the three forms around it:
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
+  mixed  the same fit with an FP32 Householder QR and FP64 refinement of c
+  sweep  64 uneven fits of a hyperparameter sweep replayed as one HIP graph
+         (FP32 QR + FP64 refinement), against the same fits run one after
+         another in plain FP64
+  serve  Poisson fit/predict requests through the continuous-batching loop:
+         p50/p99 latency and fits/s, mixed precision and plain FP64
+
+Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms mixed,sweep,serve | none]
                   [--workload realistic_fp64|tiny_fp64] [--no-cpu-baseline]
 
-A step is one whole fit on inputs already resident in HBM.  Inputs are
-synthetic (seeded), shaped like a GAP training set: see paper_2207_03803_amd/synth.py.
+A step is one whole fit on inputs already resident in HBM; `value` is the FP64
+fit's seconds per step.  Inputs are synthetic (seeded), shaped like a GAP
+training set: see paper_2207_03803_amd/synth.py and sweep.py.
 """
 from __future__ import annotations
 
@@ -17,6 +27,9 @@ import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+# The sweep and the serving loop run fits on up to 16 streams at once: give the
+# process as many hardware queues (HIP's default is 4), before HIP starts.
+os.environ["GPU_MAX_HW_QUEUES"] = "16"
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_MFMA = 78.6e12   # MI355X dense FP64 matrix peak, FLOP/s
@@ -108,7 +121,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="realistic_fp64")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--forms", default="mixed,serve",
+                    help="comma-separated forms to measure beside the FP64 fit, or none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -144,46 +158,56 @@ def main():
     sigma = torch.from_numpy(inp.sigma).to(dev)
     X, XM = inp.X, inp.XM
     n_atoms = inp.n_atoms
-    precision = gap.GAP_FP64 if args.precision == "fp64" else gap.GAP_MIXED_FP32
-    p = gap.params(d, zeta, w["sigma_w"], w["jitter"], precision=precision, flags=gap.GAP_FLAG_TIMING)
-    h = gap.Handle(p)
-    h.alloc_workspace(N, n_atoms, M)
-    # targets: model prediction with c_true (through the library) plus noise
-    h.build_knm(X, offsets, XM, sigma)
-    c_true = torch.from_numpy(inp.c_true).to(dev)
-    y = torch.empty(N, dtype=torch.float64, device=dev)
-    h.predict(X, offsets, c_true, y)
-    y += sigma * torch.from_numpy(inp.noise).to(dev)
-    torch.cuda.synchronize()
     log(f"[bench] inputs ready in {time.perf_counter() - t0:.1f}s (n_atoms={n_atoms})")
-
-    c = torch.empty(M, dtype=torch.float64, device=dev)
-    stage_sum = {}
-
-    def step(record):
-        h.build_knm(X, offsets, XM, sigma)
-        h.solve(y, c, info=False)
-        st = h.stage_times()  # waits for the stream
-        if record:
-            for k, v in st.items():
-                stage_sum[k] = stage_sum.get(k, 0.0) + v
-
-    for i in range(args.warmup):
-        step(False)
-        log(f"[bench] warmup {i + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(True)
-        log(f"[bench] step {i + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    s_status, info = h.sync()
-    if s_status != gap.GAP_OK:
-        raise RuntimeError(f"device status {gap.status_string(s_status)}")
-    ms_per_step = 1e3 * elapsed / args.steps
-    stages_ms = {k: v / args.steps for k, v in stage_sum.items() if v > 0}
     f = fit_flops(n_atoms, N, M, d)
+
+    def run_fit(precision, steps, warmup, y=None):
+        """Time `steps` whole fits (build + solve) after `warmup` untimed ones."""
+        p = gap.params(d, zeta, w["sigma_w"], w["jitter"], precision=precision, flags=gap.GAP_FLAG_TIMING,
+                       max_refine_iters=30, refine_tol=1e-12)
+        h = gap.Handle(p)
+        h.alloc_workspace(N, n_atoms, M)
+        if y is None:
+            # targets: model prediction with c_true (through the library) plus noise
+            h.build_knm(X, offsets, XM, sigma)
+            y = torch.empty(N, dtype=torch.float64, device=dev)
+            h.predict(X, offsets, torch.from_numpy(inp.c_true).to(dev), y)
+            y += sigma * torch.from_numpy(inp.noise).to(dev)
+            torch.cuda.synchronize()
+        c = torch.empty(M, dtype=torch.float64, device=dev)
+        stage_sum = {}
+
+        def step(record):
+            h.build_knm(X, offsets, XM, sigma)
+            h.solve(y, c, info=False)
+            st = h.stage_times()  # waits for the stream
+            if record:
+                for k, v in st.items():
+                    stage_sum[k] = stage_sum.get(k, 0.0) + v
+
+        tag = "fp64" if precision == gap.GAP_FP64 else "mixed"
+        for i in range(warmup):
+            step(False)
+            log(f"[bench] {tag} warmup {i + 1}/{warmup} done")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(True)
+            log(f"[bench] {tag} step {i + 1}/{steps} done")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        s_status, info = h.sync()
+        if s_status != gap.GAP_OK:
+            raise RuntimeError(f"{tag} fit: device status {gap.status_string(s_status)}")
+        h.close()
+        del h
+        torch.cuda.empty_cache()
+        stages_ms = {k: v / steps for k, v in stage_sum.items() if v > 0}
+        return dict(ms=1e3 * elapsed / steps, stages_ms=stages_ms, info=info, c=c, y=y)
+
+    fp = run_fit(gap.GAP_FP64, args.steps, args.warmup)
+    ms_per_step = fp["ms"]
+    stages_ms = fp["stages_ms"]
     knm_s = stages_ms["knm"] / 1e3
     achieved = f["knm"] / knm_s
     stage_rates = {
@@ -192,6 +216,32 @@ def main():
         "cholesky_tflops": f["cholesky"] / (stages_ms["cholesky"] / 1e3) / 1e12,
         "qr_tflops": f["qr"] / (stages_ms["qr"] / 1e3) / 1e12,
     }
+    # the forms are measured around the realistic workload only
+    forms = [] if args.forms == "none" or args.workload != "realistic_fp64" else args.forms.split(",")
+    extra = {}
+    if "mixed" in forms:
+        mx = run_fit(gap.GAP_MIXED_FP32, args.steps, args.warmup, y=fp["y"])
+        err = float((mx["c"] - fp["c"]).norm() / fp["c"].norm())
+        extra["mixed"] = {
+            "s_per_fit": mx["ms"] / 1e3, "speedup_vs_fp64": ms_per_step / mx["ms"], "stages_ms": mx["stages_ms"],
+            "qr_tflops_fp32": f["qr"] / (mx["stages_ms"]["qr"] / 1e3) / 1e12,
+            "refine_iters": mx["info"].refine_iters, "last_dc_over_c": mx["info"].grad_rel,
+            "c_rel_err_vs_fp64_path": err,
+            "note": "FP64 K_NM/Cholesky, FP32 Householder QR (FP64 reflector norms), FP64 CSNE refinement to "
+                    "||dc||/||c|| <= 1e-12"}
+        log(f"[bench] mixed: {mx['ms']:.1f} ms per fit, c rel err vs FP64 {err:.2e}")
+    del fp
+    torch.cuda.empty_cache()
+    if "sweep" in forms or "serve" in forms:
+        from paper_2207_03803_amd import serve, sweep
+
+        specs = sweep.make_sweep(seed=args.seed)
+        pools = sweep.make_pools(specs, seed=args.seed, min_configs=sweep.SWEEP_RECIPE["pool_configs"])
+    if "sweep" in forms:
+        extra["sweep"] = bench_sweep(gap, sweep, specs, pools)
+    if "serve" in forms:
+        big = sweep.Pool(d, inp.offsets, X)
+        extra["serve"] = bench_serve(gap, serve, sweep, pools, big, args.seed)
     traffic = knm_traffic() if args.workload == "realistic_fp64" else None
     cpu = None
     if not args.no_cpu_baseline:
@@ -208,10 +258,10 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n_configs": N, "atoms_per_config": list(w["atoms"]),
-                   "n_atoms": n_atoms, "d": d, "M": M, "zeta": zeta, "precision": args.precision,
+                   "n_atoms": n_atoms, "d": d, "M": M, "zeta": zeta, "precision": "fp64",
                    "stacked_matrix": [N + M, M]},
         "fits_per_s": 1e3 / ms_per_step,
         "stages_ms": stages_ms,
@@ -220,9 +270,82 @@ def main():
                      "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA,
                      "traffic": traffic},
         "cpu_baseline": cpu,
-        "residual_norm2": info.residual_norm2,
     }
+    out.update(extra)
     print(json.dumps(out), flush=True)
+
+
+def bench_sweep(gap, sweep, specs, pools, replays=2):
+    """64 uneven fits: one HIP graph (mixed precision, launch shape from the tuning
+    table) against the same fits one after another in plain FP64."""
+    import torch
+
+    table = sweep.load_table()
+    tune = table.get(sweep.bucket(specs), dict(streams=8, split_wgs=0))
+    total_flops = sum(s.flops() for s in specs)
+    sw = sweep.Sweep(specs, pools, precision=gap.GAP_MIXED_FP32, streams=tune["streams"],
+                     split_wgs=tune["split_wgs"], max_refine_iters=30, refine_tol=1e-12)
+    sw.capture(log=log)
+    log("[bench] sweep: every fit's graph captured; first replay")
+    sw.replay(1)
+    log("[bench] sweep replayed once")
+    t_graph = sw.replay(replays)
+    st = sw.statuses()
+    c_mixed = sw.weights()
+    sw.close()
+    del sw
+    torch.cuda.empty_cache()
+    log("[bench] sweep: the same fits one after another in plain FP64")
+    seq = sweep.Sweep(specs, pools, precision=gap.GAP_FP64, streams=1)
+    seq.run_eager()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq.run_eager()
+    t_seq = time.perf_counter() - t0
+    c_fp64 = seq.weights()
+    st64 = seq.statuses()
+    seq.close()
+    del seq
+    torch.cuda.empty_cache()
+    import numpy as np
+
+    errs = [float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(c_mixed, c_fp64)]
+    log(f"[bench] sweep: graph {t_graph * 1e3:.0f} ms, sequential FP64 {t_seq * 1e3:.0f} ms")
+    return {"n_fits": len(specs), "fits_per_s": len(specs) / t_graph, "s_per_sweep": t_graph,
+            "fp64_sequential_fits_per_s": len(specs) / t_seq, "speedup_vs_fp64_sequential": t_seq / t_graph,
+            "launch_shape": {"streams": tune["streams"], "qr_split_wgs": tune["split_wgs"],
+                             "from_tuning_table": sweep.bucket(specs) in table},
+            "tflops_effective": total_flops / t_graph / 1e12,
+            "all_ok": all(s == gap.GAP_OK for s in st) and all(s == gap.GAP_OK for s in st64),
+            "max_c_rel_err_vs_fp64": max(errs)}
+
+
+def bench_serve(gap, serve, sweep, pools, big_pool, seed, n_requests=64, rate=6.0):
+    """Poisson fit/predict requests through the serving loop, mixed and plain FP64."""
+    import torch
+
+    out = {"n_requests": n_requests, "arrival_rate_per_s": rate,
+           "mix": "70% sweep-sized fits, 5% realistic-size fits, 25% predicts of 1..4096 configurations"}
+    for name, prec in (("mixed", gap.GAP_MIXED_FP32), ("fp64", gap.GAP_FP64)):
+        reqs = serve.make_requests(n_requests, rate=rate, seed=seed + 11)
+        srv = serve.Server(pools, slots=8, hbm_budget=96 << 30, precision=prec,
+                           predict_pool=(pools[400].offsets, pools[400].X), big_pool=big_pool,
+                           max_refine_iters=30, refine_tol=1e-12)
+        for r in reqs:
+            srv.prepare(r)
+        torch.cuda.synchronize()
+        log(f"[bench] serve {name}: {n_requests} requests prepared")
+        srv.run(reqs)
+        torch.cuda.synchronize()
+        rep = serve.latency_report(reqs)
+        rep["all_fits_ok"] = all(r.meta.get("status") == gap.GAP_OK for r in reqs if r.kind == "fit")
+        out[name] = rep
+        log(f"[bench] serve {name}: {rep}")
+        for _, v in list(srv.models.items()):
+            v[4].close()
+        del srv, reqs
+        torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

@@ -21,7 +21,7 @@ struct Layout {
     TsqrTree tree;
     size_t off_A = 0, off_tau = 0, off_wpart = 0, off_T = 0, off_Tin = 0, off_U = 0, off_W = 0, off_ts_tiles = 0,
            off_ts_X = 0, off_ts_tau = 0, off_rhs = 0, off_misc = 0, off_tiles = 0, off_counters = 0,
-           off_status = 0, total = 0;
+           off_status = 0, off_tflags = 0, n_tflags = 0, total = 0;
     // mixed precision only
     bool mixed = false;
     size_t off_A32 = 0, off_W32 = 0, off_r = 0, off_s = 0, off_z = 0, off_dc = 0, off_part = 0,
@@ -63,6 +63,8 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, bool mixed)
     L.off_tiles = take(sizeof(int32_t) * (size_t)(L.max_tiles + 2));
     L.off_counters = take(sizeof(unsigned) * 16);
     L.off_status = take(sizeof(int32_t) * 4);
+    L.n_tflags = trsv_sync_ints(M);
+    L.off_tflags = take(sizeof(int32_t) * (size_t)L.n_tflags);
     if (mixed) {
         const int64_t ldw = (L.ncols + 63) / 64 * 64;
         L.off_A32 = take(sizeof(float) * (size_t)L.lda * (size_t)L.ncols);
@@ -105,6 +107,8 @@ struct gap_handle_s {
     int32_t *status() const { return at<int32_t>(L.off_status); }
     unsigned *counters() const { return at<unsigned>(L.off_counters); }
     double *misc() const { return at<double>(L.off_misc); }
+    // flags of the one-launch triangular solves; counters()[12] is their arrival counter
+    TrsvSync tsync() const { return TrsvSync{at<int32_t>(L.off_tflags), counters() + 12, status()}; }
 
     void mark(int stage, bool end)
     {
@@ -122,6 +126,12 @@ __global__ void zero_u32_kernel(unsigned *p, int n)
 {
     if ((int)threadIdx.x < n)
         p[threadIdx.x] = 0u;
+}
+
+__global__ void zero_i32_kernel(int32_t *p, int64_t n)
+{
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+        p[i] = 0;
 }
 
 __global__ void copy_kernel(const double *src, double *dst, int64_t n)
@@ -234,6 +244,7 @@ gap_status gap_build_knm(gap_handle h, const double *x_atoms, int64_t n_atoms, c
 
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, h->counters(), 16);
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned *>(h->status()), 4);
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(256), 0, s, h->at<int32_t>(L.off_tflags), L.n_tflags);
     int32_t *tiles = h->at<int32_t>(L.off_tiles);
     GAP_TRY(dev(launch_plan_tiles(config_offsets, n_configs, n_atoms, tiles, tiles + L.max_tiles + 1,
                                   L.max_tiles, h->status(), s)));
@@ -356,7 +367,7 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
         const double *qtb = A + L.M * L.lda;
         h->mark(5, false);
         hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((L.M + 255) / 256)), dim3(256), 0, s, qtb, rhs, L.M);
-        GAP_TRY(dev(launch_trsv_upper(A, L.lda, L.M, rhs, c_out, h->status(), s)));
+        GAP_TRY(dev(launch_trsv_upper(A, L.lda, L.M, rhs, c_out, h->tsync(), s)));
         h->mark(5, true);
         GAP_TRY(dev(launch_sumsq(qtb + L.M, L.N, h->misc(), h->misc() + 1, h->counters() + 8, s)));
     } else {
@@ -371,7 +382,7 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
         h->mark(4, true);
         h->mark(5, false);
         GAP_TRY(dev(launch_copy_f32_f64(A32 + L.M * L.lda, rhs, L.M, s)));
-        GAP_TRY(dev(launch_trsv_upper_f32(A32, L.lda, L.M, rhs, c_out, nullptr, s)));
+        GAP_TRY(dev(launch_trsv_upper_f32(A32, L.lda, L.M, rhs, c_out, h->tsync(), nullptr, s)));
         h->mark(5, true);
         RefineWork rw{};
         rw.A = A;
@@ -391,6 +402,7 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
         rw.stats = h->at<double>(L.off_stats);
         rw.tol = h->p.refine_tol;
         rw.status = h->status();
+        rw.sync = h->tsync();
         h->mark(6, false);
         GAP_TRY(dev(launch_refine(rw, h->p.max_refine_iters, s)));
         h->mark(6, true);

@@ -16,6 +16,7 @@ enum : int32_t {
     DST_ENOTPD = 3,
     DST_ENONFINITE = 4,
     DST_ENOCONV = 5,
+    DST_EDEVICE = 6,  // a device-side wait was abandoned
 };
 
 // Record the first failure seen on the device; later ones do not overwrite it.

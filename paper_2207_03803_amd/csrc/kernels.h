@@ -92,16 +92,25 @@ int64_t qr_max_chunks();
 hipError_t launch_geqrf(const QrWork &w, hipStream_t s);
 
 // -------------------------------------------------------- triangular solve
-// Solve R c = rhs for the n x n upper triangle of R (column-major, ld); rhs
-// [n] is overwritten (used as work), c [n] output.  tail/tail_n: optional
-// (tail != nullptr) sum of squares of tail[0..tail_n) into *tail_out.
-hipError_t launch_trsv_upper(const double *R, int64_t ld, int64_t n, double *rhs, double *c,
-                             int32_t *status, hipStream_t s);
-hipError_t launch_trsv_upper_f32(const float *R, int64_t ld, int64_t n, double *rhs, double *x,
-                                 const int32_t *skip, hipStream_t s);
+// Flags of the one-launch blocked substitution: sync.flags holds
+// trsv_sync_ints(n) int32 (zero before the first solve; each solve leaves them
+// zero), sync.counter one unsigned (zero), sync.status the device status word.
+struct TrsvSync {
+    int32_t *flags;
+    unsigned *counter;
+    int32_t *status;
+};
+int64_t trsv_sync_ints(int64_t n);
+// Solve R c = rhs for the n x n upper triangle of R (column-major, ld); then
+// check c is finite (DST_ENONFINITE otherwise).
+hipError_t launch_trsv_upper(const double *R, int64_t ld, int64_t n, const double *rhs, double *c,
+                             const TrsvSync &sync, hipStream_t s);
+// Same with R stored in FP32 (FP64 arithmetic).
+hipError_t launch_trsv_upper_f32(const float *R, int64_t ld, int64_t n, const double *rhs, double *x,
+                                 const TrsvSync &sync, const int32_t *skip, hipStream_t s);
 // Solve R^T x = rhs (forward substitution) for the FP32-stored upper R.
-hipError_t launch_trsv_upper_t_f32(const float *R, int64_t ld, int64_t n, double *rhs, double *x,
-                                   const int32_t *skip, hipStream_t s);
+hipError_t launch_trsv_upper_t_f32(const float *R, int64_t ld, int64_t n, const double *rhs, double *x,
+                                   const TrsvSync &sync, const int32_t *skip, hipStream_t s);
 hipError_t launch_copy_f32_f64(const float *src, double *dst, int64_t n, hipStream_t s);
 hipError_t launch_sumsq(const double *x, int64_t n, double *out, double *part, unsigned *counter,
                         hipStream_t s);
@@ -121,6 +130,7 @@ struct RefineWork {
     double *stats;       // [0] ||r||^2, [1] last ||dc|| / ||c||
     double tol;
     int32_t *status;
+    TrsvSync sync;       // flags of the triangular solves
 };
 hipError_t launch_convert_f64_f32(const double *a, float *b, int64_t n, hipStream_t s);
 hipError_t launch_refine(const RefineWork &w, int max_iters, hipStream_t s);

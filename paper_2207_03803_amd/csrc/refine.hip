@@ -188,10 +188,10 @@ hipError_t launch_refine(const RefineWork &w, int max_iters, hipStream_t s)
         residual(w, s);
         hipLaunchKernelGGL(atr_kernel, dim3((unsigned)w.n), dim3(256), 0, s, w);
         // dc = R^-1 R^-T s (R from the FP32 factorisation, FP64 arithmetic)
-        hipError_t e = launch_trsv_upper_t_f32(w.R32, w.lda, w.n, w.s, w.z, w.done, s);
+        hipError_t e = launch_trsv_upper_t_f32(w.R32, w.lda, w.n, w.s, w.z, w.sync, w.done, s);
         if (e != hipSuccess)
             return e;
-        e = launch_trsv_upper_f32(w.R32, w.lda, w.n, w.z, w.dc, w.done, s);
+        e = launch_trsv_upper_f32(w.R32, w.lda, w.n, w.z, w.dc, w.sync, w.done, s);
         if (e != hipSuccess)
             return e;
         hipLaunchKernelGGL(refine_update_kernel, dim3(1), dim3(256), 0, s, w, nparts);

@@ -4,160 +4,245 @@
 
 namespace gap {
 
-constexpr int TB = 64;
+constexpr int TB = 64;          // rows per block row
+constexpr int TS_GRID = 256;    // workgroups of one solve (all co-resident)
+// A workgroup waiting for a block row gives up after this many 100 MHz ticks
+// (10 s) and reports DST_EDEVICE, so that every wave always exits.
+constexpr uint64_t TS_WAIT_TICKS = 1000000000ull;
 
-// Back-substitution R x = rhs for the n x n upper triangle of R (column-major,
-// ld), blocks of 64 from the bottom: one wave solves a diagonal block, then a
-// GEMV removes the block's contribution from the rows above.  rhs is used as
-// work.  R may be stored in FP32 (TR = float); the arithmetic is FP64.  When
-// skip is non-null and *skip != 0 the kernels return at once.
+// Triangular solves with the n x n upper triangle of R (column-major, ld):
+// R x = rhs (back substitution, Sec. Theory: c = R^-1 Q^T b) and R^T x = rhs
+// (forward substitution, used by the refinement).  R may be stored in FP32
+// (TR = float); the arithmetic is FP64.
+//
+// One launch solves the whole system.  The block rows (64 rows each) are
+// numbered in dependency order q = 0 .. nb-1 (the last block row first for
+// R x = rhs, the first one first for R^T x = rhs); workgroup g takes q = g,
+// g + G, ...  A block row first accumulates the products with the blocks of
+// every earlier block row, in order, waiting for each one's ready flag (its
+// R values are loaded before the wait), then one wave solves the diagonal
+// block and publishes x with a release and the flag.  The workgroups of one
+// solve are few (G <= 256) and all wait only on smaller q, so the lowest
+// unfinished q can always proceed.  The last workgroup to finish clears the
+// flags for the next solve (they must be zero before the first one).
+// When skip is non-null and *skip != 0 the kernel returns at once.
 
-// Solve the bw x bw diagonal block at (b0, b0) with one wave.
-template <class TR>
-__global__ __launch_bounds__(64) void trsv_diag_kernel(const TR *R, int64_t ld, int64_t b0, int bw, double *rhs,
-                                                       double *x, const int32_t *skip)
+struct TrsvArgs {
+    int64_t ld, n, nb;
+    const double *rhs;
+    double *x;
+    int32_t *flags;     // [nb + 1]: ready flag per block row; [nb] = abort
+    unsigned *counter;  // arrival counter (zero between solves)
+    const int32_t *skip;
+    int32_t *status;
+};
+
+DEV double load_x(const double *p)
 {
-    __shared__ double S[TB][TB + 1];
-    __shared__ double xs[TB];
-    if (skip && *skip)
-        return;
-    const int l = threadIdx.x;
-    for (int cc = 0; cc < bw; ++cc)
-        if (l < bw)
-            S[l][cc] = (double)R[(b0 + cc) * ld + b0 + l];
-    double r = (l < bw) ? rhs[b0 + l] : 0.0;
-    __syncthreads();
-    for (int i = bw - 1; i >= 0; --i) {
-        if (l == i)
-            xs[i] = r / S[i][i];
-        __syncthreads();
-        if (l < i)
-            r -= S[l][i] * xs[i];
+    // bypass the non-coherent caches: x is written by other workgroups in this launch
+    unsigned long long v =
+        __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)v);
+}
+
+// Make the dependency items [from, q) usable: thread 0 waits until item `from`
+// is published, extends over every later item already published, and takes
+// one agent-scope acquire for all of them.  Returns the new end of the ready
+// range (uniform), or -1 when the wait was abandoned.
+template <bool TRANS>
+DEV int64_t acquire_ready(const TrsvArgs &a, int64_t from, int64_t q, int64_t *lds)
+{
+    if (threadIdx.x == 0) {
+        auto row = [&](int64_t qq) { return TRANS ? qq : a.nb - 1 - qq; };
+        int64_t upto = from;
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        while (__hip_atomic_load(&a.flags[row(from)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            if (__hip_atomic_load(&a.flags[a.nb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                upto = -1;
+                break;
+            }
+            if (__builtin_amdgcn_s_memrealtime() - t0 > TS_WAIT_TICKS) {
+                set_status(a.status, DST_EDEVICE);
+                __hip_atomic_store(&a.flags[a.nb], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                upto = -1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (upto >= 0) {
+            upto = from + 1;
+            while (upto < q && __hip_atomic_load(&a.flags[row(upto)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                ++upto;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        *lds = upto;
     }
-    if (l < bw)
-        x[b0 + l] = xs[l];
-}
-
-// rhs[r] -= sum_i R[r][b0+i] x[b0+i] for r < b0.
-template <class TR>
-__global__ __launch_bounds__(256) void trsv_gemv_kernel(const TR *R, int64_t ld, int64_t b0, int bw, double *rhs,
-                                                        const double *x, const int32_t *skip)
-{
-    __shared__ double xs[TB];
-    if (skip && *skip)
-        return;
-    if (threadIdx.x < bw)
-        xs[threadIdx.x] = x[b0 + threadIdx.x];
     __syncthreads();
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r >= b0)
-        return;
-    double s = 0.0;
-    for (int i = 0; i < bw; ++i)
-        s += (double)R[(b0 + i) * ld + r] * xs[i];
-    rhs[r] -= s;
+    return *lds;
 }
 
-// Forward substitution R^T x = rhs (R upper, so R^T is lower), blocks from the
-// top: one wave per diagonal block, then rhs[i] -= sum_j R[j][i] x[j] for the
-// rows below (column i of R holds the R[j][i], contiguous in j).
-template <class TR>
-__global__ __launch_bounds__(64) void trsv_t_diag_kernel(const TR *R, int64_t ld, int64_t b0, int bw, double *rhs,
-                                                         double *x, const int32_t *skip)
+template <class TR, bool TRANS>
+__global__ __launch_bounds__(256) void trsv_fused_kernel(const TR *__restrict__ R, TrsvArgs a)
 {
-    __shared__ double S[TB][TB + 1];
+    __shared__ double D[TB][TB + 1];  // diagonal block: D[c][l] = R[b0+l][b0+c]
+    __shared__ double red[4][TB];
     __shared__ double xs[TB];
-    if (skip && *skip)
+    __shared__ int64_t ready_lds;
+    __shared__ int last_lds;
+    if (a.skip && *a.skip)
         return;
-    const int l = threadIdx.x;
-    for (int cc = 0; cc < bw; ++cc)
-        if (l < bw)
-            S[l][cc] = (double)R[(b0 + cc) * ld + b0 + l];  // S[j][i] = R[b0+j][b0+i]
-    double r = (l < bw) ? rhs[b0 + l] : 0.0;
-    __syncthreads();
-    for (int i = 0; i < bw; ++i) {
-        if (l == i)
-            xs[i] = r / S[i][i];
-        __syncthreads();
-        if (l > i && l < bw)
-            r -= S[i][l] * xs[i];
-    }
-    if (l < bw)
-        x[b0 + l] = xs[l];
-}
-
-template <class TR>
-__global__ __launch_bounds__(256) void trsv_t_gemv_kernel(const TR *R, int64_t ld, int64_t n, int64_t b0, int bw,
-                                                          double *rhs, const double *x, const int32_t *skip)
-{
-    __shared__ double xs[TB];
-    if (skip && *skip)
-        return;
-    if (threadIdx.x < bw)
-        xs[threadIdx.x] = x[b0 + threadIdx.x];
-    __syncthreads();
-    const int64_t i = b0 + bw + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n)
-        return;
-    const TR *col = R + i * ld + b0;
-    double s = 0.0;
-    for (int j = 0; j < bw; ++j)
-        s += (double)col[j] * xs[j];
-    rhs[i] -= s;
-}
-
-template <class TR>
-static hipError_t trsv_upper(const TR *R, int64_t ld, int64_t n, double *rhs, double *x, const int32_t *skip,
-                             hipStream_t s)
-{
-    const int64_t nb = (n + TB - 1) / TB;
-    for (int64_t b = nb - 1; b >= 0; --b) {
-        const int64_t b0 = b * TB;
+    const int t = threadIdx.x, lane = t & 63, grp = t >> 6;
+    const int64_t ld = a.ld, n = a.n, nb = a.nb;
+    bool alive = true;
+    for (int64_t q = blockIdx.x; q < nb && alive; q += gridDim.x) {
+        const int64_t i = TRANS ? q : nb - 1 - q;
+        const int64_t b0 = i * TB;
         const int bw = (int)((n - b0) < TB ? (n - b0) : TB);
-        hipLaunchKernelGGL(trsv_diag_kernel<TR>, dim3(1), dim3(64), 0, s, R, ld, b0, bw, rhs, x, skip);
-        if (b0 > 0)
-            hipLaunchKernelGGL(trsv_gemv_kernel<TR>, dim3((unsigned)((b0 + 255) / 256)), dim3(256), 0, s, R, ld,
-                               b0, bw, rhs, (const double *)x, skip);
+        // stage the diagonal block (independent of x): D[c][l] = R[b0+l][b0+c]
+        for (int c = grp; c < TB; c += 4)
+            D[c][lane] = (c < bw && lane < bw) ? (double)R[(b0 + c) * ld + b0 + lane] : 0.0;
+        // products with the blocks of every earlier block row
+        double acc[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            acc[e] = 0.0;
+        int64_t ready = 0;  // dependency items [0, ready) are published and acquired
+        for (int64_t qq = 0; qq < q && alive; ++qq) {
+            const int64_t j = TRANS ? qq : nb - 1 - qq;
+            const int64_t j0 = j * TB;
+            const int jw = (int)((n - j0) < TB ? (n - j0) : TB);
+            double rv[16];
+            if (!TRANS) {
+                // thread (row lane, columns grp + 4e): R[b0+lane][j0+c], coalesced over lanes
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int c = grp + 4 * e;
+                    rv[e] = (c < jw && lane < bw) ? (double)R[(j0 + c) * ld + b0 + lane] : 0.0;
+                }
+            } else {
+                // thread (x index lane, rows grp + 4e of the block row): R[j0+lane][b0+k]
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int k = grp + 4 * e;
+                    rv[e] = (k < bw && lane < jw) ? (double)R[(b0 + k) * ld + j0 + lane] : 0.0;
+                }
+            }
+            if (qq >= ready) {
+                ready = acquire_ready<TRANS>(a, qq, q, &ready_lds);
+                if (ready < 0) {
+                    alive = false;
+                    break;
+                }
+            }
+            if (t < TB)
+                xs[t] = (t < jw) ? load_x(a.x + j0 + t) : 0.0;
+            __syncthreads();
+            if (!TRANS) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    acc[0] += rv[e] * xs[grp + 4 * e];
+            } else {
+                const double xv = xs[lane];
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    acc[e] += rv[e] * xv;
+            }
+            __syncthreads();
+        }
+        if (!alive)
+            break;
+        // r = rhs - (sum of the products), fixed reduction order
+        if (!TRANS) {
+            red[grp][lane] = acc[0];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const double v = wave_sum(acc[e]);
+                if (lane == 0)
+                    red[0][grp + 4 * e] = v;
+            }
+        }
+        __syncthreads();
+        if (t < TB) {
+            double r = 0.0, inv = 0.0;
+            if (lane < bw) {
+                const double sub = TRANS ? red[0][lane] : (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+                r = a.rhs[b0 + lane] - sub;
+                inv = 1.0 / D[lane][lane];
+            }
+            double xl = 0.0;
+            if (!TRANS) {
+                for (int c = bw - 1; c >= 0; --c) {
+                    const double xc = __shfl(r, c, 64) * __shfl(inv, c, 64);
+                    if (lane == c)
+                        xl = xc;
+                    else if (lane < c)
+                        r -= D[c][lane] * xc;
+                }
+            } else {
+                for (int c = 0; c < bw; ++c) {
+                    const double xc = __shfl(r, c, 64) * __shfl(inv, c, 64);
+                    if (lane == c)
+                        xl = xc;
+                    else if (lane > c)
+                        r -= D[lane][c] * xc;
+                }
+            }
+            if (lane < bw)
+                a.x[b0 + lane] = xl;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (lane == 0)
+                __hip_atomic_store(&a.flags[i], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
     }
+    // the last workgroup to finish clears the flags for the next solve
+    if (!arrive_last(a.counter, gridDim.x, &last_lds))
+        return;
+    for (int64_t k = t; k <= nb; k += 256)
+        a.flags[k] = 0;
+}
+
+template <class TR, bool TRANS>
+static hipError_t trsv_fused(const TR *R, int64_t ld, int64_t n, const double *rhs, double *x, const TrsvSync &sync,
+                             const int32_t *skip, hipStream_t s)
+{
+    TrsvArgs a{};
+    a.ld = ld;
+    a.n = n;
+    a.nb = (n + TB - 1) / TB;
+    a.rhs = rhs;
+    a.x = x;
+    a.flags = sync.flags;
+    a.counter = sync.counter;
+    a.skip = skip;
+    a.status = sync.status;
+    const unsigned g = (unsigned)(a.nb < TS_GRID ? a.nb : TS_GRID);
+    hipLaunchKernelGGL((trsv_fused_kernel<TR, TRANS>), dim3(g), dim3(256), 0, s, R, a);
     return hipGetLastError();
 }
 
-template <class TR>
-static hipError_t trsv_upper_t(const TR *R, int64_t ld, int64_t n, double *rhs, double *x, const int32_t *skip,
-                               hipStream_t s)
-{
-    const int64_t nb = (n + TB - 1) / TB;
-    for (int64_t b = 0; b < nb; ++b) {
-        const int64_t b0 = b * TB;
-        const int bw = (int)((n - b0) < TB ? (n - b0) : TB);
-        hipLaunchKernelGGL(trsv_t_diag_kernel<TR>, dim3(1), dim3(64), 0, s, R, ld, b0, bw, rhs, x, skip);
-        const int64_t rest = n - b0 - bw;
-        if (rest > 0)
-            hipLaunchKernelGGL(trsv_t_gemv_kernel<TR>, dim3((unsigned)((rest + 255) / 256)), dim3(256), 0, s, R, ld,
-                               n, b0, bw, rhs, (const double *)x, skip);
-    }
-    return hipGetLastError();
-}
+int64_t trsv_sync_ints(int64_t n) { return (n + TB - 1) / TB + 1 + 64; }
 
-hipError_t launch_trsv_upper(const double *R, int64_t ld, int64_t n, double *rhs, double *c, int32_t *status,
-                             hipStream_t s)
+hipError_t launch_trsv_upper(const double *R, int64_t ld, int64_t n, const double *rhs, double *c,
+                             const TrsvSync &sync, hipStream_t s)
 {
-    hipError_t e = trsv_upper<double>(R, ld, n, rhs, c, nullptr, s);
+    hipError_t e = trsv_fused<double, false>(R, ld, n, rhs, c, sync, nullptr, s);
     if (e != hipSuccess)
         return e;
-    return launch_check_finite(c, n, status, s);
+    return launch_check_finite(c, n, sync.status, s);
 }
 
-hipError_t launch_trsv_upper_f32(const float *R, int64_t ld, int64_t n, double *rhs, double *x, const int32_t *skip,
-                                 hipStream_t s)
+hipError_t launch_trsv_upper_f32(const float *R, int64_t ld, int64_t n, const double *rhs, double *x,
+                                 const TrsvSync &sync, const int32_t *skip, hipStream_t s)
 {
-    return trsv_upper<float>(R, ld, n, rhs, x, skip, s);
+    return trsv_fused<float, false>(R, ld, n, rhs, x, sync, skip, s);
 }
 
-hipError_t launch_trsv_upper_t_f32(const float *R, int64_t ld, int64_t n, double *rhs, double *x,
-                                   const int32_t *skip, hipStream_t s)
+hipError_t launch_trsv_upper_t_f32(const float *R, int64_t ld, int64_t n, const double *rhs, double *x,
+                                   const TrsvSync &sync, const int32_t *skip, hipStream_t s)
 {
-    return trsv_upper_t<float>(R, ld, n, rhs, x, skip, s);
+    return trsv_fused<float, true>(R, ld, n, rhs, x, sync, skip, s);
 }
 
 __global__ __launch_bounds__(256) void sumsq_kernel(const double *x, int64_t n, double *out, double *part,

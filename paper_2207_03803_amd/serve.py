@@ -70,10 +70,12 @@ class Server:
     """Continuous-batching executor over `slots` streams and an HBM budget."""
 
     def __init__(self, pools, slots=8, hbm_budget=96 << 30, precision=gap.GAP_FP64, resident_max=64,
-                 predict_pool=None):
+                 predict_pool=None, big_pool=None, max_refine_iters=20, refine_tol=1e-12):
         import torch
 
         self.pools = pools
+        self.big_pool = big_pool                   # descriptors of the realistic-size fits
+        self.refine = dict(max_refine_iters=max_refine_iters, refine_tol=refine_tol)
         self.slots = [torch.cuda.Stream() for _ in range(slots)]
         self.free = list(range(slots))
         self.budget = hbm_budget
@@ -88,7 +90,11 @@ class Server:
     def _fit_inputs(self, spec):
         import torch
 
-        pool = self.pools[spec.d]
+        pool = self.pools.get(spec.d)
+        if pool is None or len(pool.offsets) <= spec.n_configs:
+            pool = self.big_pool
+        if pool is None or pool.d != spec.d or len(pool.offsets) <= spec.n_configs:
+            raise ValueError(f"no descriptor pool of d={spec.d} with {spec.n_configs} configurations")
         n_atoms = int(pool.offsets[spec.n_configs])
         rng = np.random.default_rng(spec.seed)
         sparse_idx = np.sort(rng.choice(n_atoms, size=spec.M, replace=False))
@@ -106,7 +112,7 @@ class Server:
 
         if req.kind == "fit":
             X, offsets, XM, sigma, c_true, noise = self._fit_inputs(req.spec)
-            p = gap.params(req.spec.d, req.spec.zeta, 1.0, 1e-8, precision=self.precision)
+            p = gap.params(req.spec.d, req.spec.zeta, 1.0, 1e-8, precision=self.precision, **self.refine)
             h = gap.Handle(p)
             h.alloc_workspace(req.spec.n_configs, X.shape[0], req.spec.M)
             h.build_knm(X, offsets, XM, sigma)
@@ -135,7 +141,7 @@ class Server:
         m = req.meta
         with torch.cuda.stream(st):
             if req.kind == "fit":
-                p = gap.params(req.spec.d, req.spec.zeta, 1.0, 1e-8, precision=self.precision)
+                p = gap.params(req.spec.d, req.spec.zeta, 1.0, 1e-8, precision=self.precision, **self.refine)
                 h = gap.Handle(p, stream=st)
                 h.alloc_workspace(req.spec.n_configs, m["X"].shape[0], req.spec.M)
                 h.build_knm(m["X"], m["offsets"], m["XM"], m["sigma"])

@@ -1,14 +1,15 @@
-"""Batched hyperparameter sweep: many independent GAP fits replayed as one HIP graph.
+"""Batched hyperparameter sweep: many independent GAP fits replayed as HIP graphs.
 
 A sweep is a list of fits of different sizes and hyperparameters over shared
 descriptor pools (one pool per descriptor length d; a fit with N_c
 configurations takes the pool's first N_c, and draws its own sparse set from
 their atoms).  The fits are spread over S streams by longest-processing-time
-order on their flop counts, every fit's `gap_build_knm` + `gap_solve` is
-captured once into a single graph (fork/join over the streams), and the graph
-is replayed.  Each fit keeps its own handle and workspace; the library's
-kernels are deterministic, so a fit's weights are bitwise the same alone, in a
-replay, or on any stream.
+order on their flop counts.  Each fit's `gap_build_knm` + `gap_solve` is
+captured once into its own graph (about a thousand kernel nodes for the
+largest fits of the recipe), and a sweep replays every fit's graph on its
+stream, so the fits of different streams overlap on the device.  Each fit
+keeps its own handle and workspace; the library's kernels are deterministic,
+so a fit's weights are bitwise the same alone, in a replay, or on any stream.
 
 The autotuner times whole-sweep replays over a small grid of launch shapes
 (stream count, split-K workgroup target of the QR) and keeps a table keyed by
@@ -72,13 +73,14 @@ class Pool:
     X: object               # torch [n_atoms, d] float64 (cuda)
 
 
-def make_pools(specs, seed=0, atoms=(8, 64), device="cuda"):
-    """One descriptor pool per d, as large as the largest fit that uses it."""
+def make_pools(specs, seed=0, atoms=(8, 64), device="cuda", min_configs=0):
+    """One descriptor pool per d, as large as the largest fit that uses it (and at
+    least `min_configs` configurations)."""
     from . import synth
 
     pools = {}
     for d in sorted({s.d for s in specs}):
-        n = max(s.n_configs for s in specs if s.d == d)
+        n = max(max(s.n_configs for s in specs if s.d == d), min_configs)
         inp = synth.make_fit_inputs_torch(n_configs=n, atoms=atoms, d=d, M=1, seed=seed + d, device=device)
         pools[d] = Pool(d, inp.offsets, inp.X)
     return pools
@@ -143,7 +145,7 @@ class Sweep:
             f.c = torch.empty(s.M, dtype=torch.float64, device="cuda")
             self.fits.append(f)
         self._targets()
-        self.graph = None
+        self.graphs = None
 
     def _targets(self):
         """y = prediction with c_true plus sigma * noise, through the library."""
@@ -177,31 +179,44 @@ class Sweep:
             torch.cuda.current_stream().wait_stream(st)
         torch.cuda.synchronize()
 
-    def capture(self):
-        """Capture the whole sweep once: the root stream forks to the S streams and joins them."""
+    def capture(self, log=None):
+        """Capture each fit's build + solve into a graph of its own, on its stream."""
         import torch
 
         torch.cuda.synchronize()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.stream(self.root):
-            g.capture_begin()
-            for st in self.streams:
-                st.wait_stream(self.root)
-            self.enqueue()
-            for st in self.streams:
-                self.root.wait_stream(st)
-            g.capture_end()
+        self.graphs = [None] * len(self.fits)
+        for k, lst in enumerate(self.assign):
+            st = self.streams[k]
+            for i in lst:
+                f = self.fits[i]
+                if log:
+                    log(f"[sweep] capturing fit {i} (N={f.spec.n_configs} M={f.spec.M} d={f.spec.d}) on stream {k}")
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.stream(st):
+                    g.capture_begin()
+                    f.handle.build_knm(f.X, f.offsets, f.XM, f.sigma)
+                    f.handle.solve(f.y, f.c, info=False)
+                    g.capture_end()
+                self.graphs[i] = g
         torch.cuda.synchronize()
-        self.graph = g
-        return g
+        return self.graphs
 
     def replay(self, n=1):
+        """Replay the whole sweep n times; returns seconds per sweep."""
         import torch
 
         torch.cuda.synchronize()
+        cur = torch.cuda.current_stream()
         t0 = time.perf_counter()
         for _ in range(n):
-            self.graph.replay()
+            for st in self.streams:
+                st.wait_stream(cur)
+            for k, lst in enumerate(self.assign):
+                with torch.cuda.stream(self.streams[k]):
+                    for i in lst:
+                        self.graphs[i].replay()
+            for st in self.streams:
+                cur.wait_stream(st)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / n
 
@@ -239,8 +254,10 @@ def autotune(specs, pools, precision=gap.GAP_MIXED_FP32, candidates=None, replay
     candidates = candidates or [dict(streams=s, split_wgs=w) for s in (4, 8, 16) for w in (1024, 2048, 4096)]
     results = []
     for cand in candidates:
+        log(f"[autotune] building {cand}")
         sw = Sweep(specs, pools, precision=precision, streams=cand["streams"], split_wgs=cand["split_wgs"])
         sw.capture()
+        log(f"[autotune] captured {len(specs)} fit graphs; first replay")
         sw.replay(1)
         t = sw.replay(replays)
         results.append(dict(cand, seconds=t))
@@ -254,3 +271,21 @@ def autotune(specs, pools, precision=gap.GAP_MIXED_FP32, candidates=None, replay
     with open(path, "w") as fh:
         json.dump(table, fh, indent=1, sort_keys=True)
     return best, results
+
+
+def main():
+    import argparse
+
+    ap = argparse.ArgumentParser(description="Autotune the sweep's launch shape and store it in the tuning table.")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--n-fits", type=int, default=SWEEP_RECIPE["n_fits"])
+    ap.add_argument("--replays", type=int, default=1)
+    args = ap.parse_args()
+    specs = make_sweep(seed=args.seed, n_fits=args.n_fits)
+    pools = make_pools(specs, seed=args.seed, min_configs=SWEEP_RECIPE["pool_configs"])
+    best, results = autotune(specs, pools, replays=args.replays, log=lambda m: print(m, flush=True))
+    print(json.dumps(dict(bucket=bucket(specs), best=best, results=results)), flush=True)
+
+
+if __name__ == "__main__":
+    main()
