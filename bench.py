@@ -341,8 +341,7 @@ def bench_serve(gap, serve, sweep, pools, big_pool, seed, n_requests=64, rate=6.
         rep["all_fits_ok"] = all(r.meta.get("status") == gap.GAP_OK for r in reqs if r.kind == "fit")
         out[name] = rep
         log(f"[bench] serve {name}: {rep}")
-        for _, v in list(srv.models.items()):
-            v[4].close()
+        serve.close(srv)
         del srv, reqs
         torch.cuda.empty_cache()
     return out

@@ -4,10 +4,15 @@ Requests arrive by a Poisson process.  A fit request carries a training set
 (descriptors already resident on the device, its sparse set, targets); a
 predict request carries a batch of configurations and names a resident model
 (the sparse set and weights of an earlier fit, kept on the device with an LRU
-bound).  The loop admits a waiting request as soon as a slot (a HIP stream) is
-free and its device footprint (`gap_workspace_bytes` for a fit, its inputs and
-outputs for a predict) fits in the remaining HBM budget; in-flight requests
-overlap on the device.  Completion is observed by polling each slot's event,
+bound).  The server owns one device arena of the HBM budget, allocated once;
+a request's device memory (`gap_workspace_bytes` for a fit, weights, outputs)
+is carved from it by a first-fit allocator, so serving never calls the device
+allocator (whose calls can wait for work in flight).  The loop admits a
+waiting request as soon as a slot (a HIP stream) is free and its footprint
+fits in the arena, and hands it to that slot's host thread, which enqueues its
+kernels (a large fit enqueues thousands, and an enqueue waits when the
+hardware queue is full: the admission loop itself never does); in-flight
+requests overlap on the device.  Completion is observed by polling each slot's event,
 so the host never blocks on one request while others are in flight.  Latency
 is arrival -> result on the host clock.
 
@@ -17,6 +22,8 @@ same whether it runs alone or in the mix.
 from __future__ import annotations
 
 import collections
+import queue
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -66,6 +73,56 @@ def make_requests(n, rate, seed=0, mix=(0.70, 0.05, 0.25), small_scale=1.0, real
     return reqs
 
 
+class Arena:
+    """First-fit allocator over one device buffer (offsets aligned to 256 bytes)."""
+
+    ALIGN = 256
+
+    def __init__(self, nbytes):
+        import torch
+
+        self.buf = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        self.size = int(nbytes)
+        self.free = [(0, self.size)]   # sorted (offset, length), coalesced
+        self.used = 0
+
+    def alloc(self, nbytes):
+        n = (int(nbytes) + self.ALIGN - 1) // self.ALIGN * self.ALIGN
+        for k, (off, ln) in enumerate(self.free):
+            if ln >= n:
+                if ln == n:
+                    del self.free[k]
+                else:
+                    self.free[k] = (off + n, ln - n)
+                self.used += n
+                return off, n
+        return None
+
+    def release(self, block):
+        off, n = block
+        self.used -= n
+        self.free.append((off, n))
+        self.free.sort()
+        merged = []
+        for o, ln in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
+            else:
+                merged.append((o, ln))
+        self.free = merged
+
+    def view(self, block, dtype=None, count=None):
+        import torch
+
+        off, n = block
+        t = self.buf[off:off + n]
+        if dtype is not None:
+            t = t.view(dtype)
+            if count is not None:
+                t = t[:count]
+        return t
+
+
 class Server:
     """Continuous-batching executor over `slots` streams and an HBM budget."""
 
@@ -78,13 +135,33 @@ class Server:
         self.refine = dict(max_refine_iters=max_refine_iters, refine_tol=refine_tol)
         self.slots = [torch.cuda.Stream() for _ in range(slots)]
         self.free = list(range(slots))
-        self.budget = hbm_budget
-        self.in_use = 0
+        self.arena = Arena(hbm_budget)
         self.precision = precision
-        self.models = collections.OrderedDict()   # rid -> (XM, c, zeta, d, handle)
+        self.models = collections.OrderedDict()   # rid -> (XM, c, zeta, d, handle, c_block)
         self.resident_max = resident_max
         self.predict_pool = predict_pool           # (offsets, X) for d=400 predict batches
-        self.inflight = []                         # (req, slot, event, keep)
+        self.inflight = []                         # (req, slot, event, keep, arena blocks)
+        self.n_active = 0                          # admitted and not finished
+        self.model_users = {}                      # model -> predicts admitted and not finished
+        self.handles = {}                          # (d, zeta) -> predict-only handle
+        self.handles_lock = threading.Lock()
+        self.launched = queue.Queue()              # filled by the slot threads
+        self.work = [queue.Queue() for _ in range(slots)]
+        self.threads = [threading.Thread(target=self._slot_thread, args=(k,), daemon=True) for k in range(slots)]
+        for t in self.threads:
+            t.start()
+
+    def _slot_thread(self, slot):
+        while True:
+            item = self.work[slot].get()
+            if item is None:
+                return
+            req, blocks = item
+            try:
+                ev, keep = self._launch(req, slot, blocks)
+                self.launched.put((req, slot, ev, keep, blocks, None))
+            except Exception as exc:  # reported by the loop
+                self.launched.put((req, slot, None, None, blocks, exc))
 
     # ---------------------------------------------------------------- helpers
     def _fit_inputs(self, spec):
@@ -122,7 +199,7 @@ class Server:
             torch.cuda.synchronize()
             h.close()
             req.meta = dict(X=X, offsets=offsets, XM=XM, sigma=sigma, y=y)
-            req.footprint = gap.workspace_bytes(p, req.spec.n_configs, X.shape[0], req.spec.M)
+            req.footprint = gap.workspace_bytes(p, req.spec.n_configs, X.shape[0], req.spec.M) + 8 * req.spec.M + 512
         else:
             offs_all, Xp = self.predict_pool
             rng = np.random.default_rng(req.seed)
@@ -132,50 +209,77 @@ class Server:
             a0, a1 = int(offs_all[start]), int(offs_all[start + n])
             offsets = torch.from_numpy(offs_all[start:start + n + 1] - a0).cuda()
             req.meta = dict(X=Xp[a0:a1], offsets=offsets, n=n)
-            req.footprint = (a1 - a0) * Xp.shape[1] * 8 + (n + 1) * 16
+            req.footprint = 8 * n
 
-    def _launch(self, req, slot):
+    def _launch(self, req, slot, blocks):
         import torch
 
         st = self.slots[slot]
         m = req.meta
-        with torch.cuda.stream(st):
-            if req.kind == "fit":
-                p = gap.params(req.spec.d, req.spec.zeta, 1.0, 1e-8, precision=self.precision, **self.refine)
-                h = gap.Handle(p, stream=st)
-                h.alloc_workspace(req.spec.n_configs, m["X"].shape[0], req.spec.M)
-                h.build_knm(m["X"], m["offsets"], m["XM"], m["sigma"])
-                c = torch.empty(req.spec.M, dtype=torch.float64, device="cuda")
-                h.solve(m["y"], c, info=False)
-                keep = (h, c)
-            else:
-                XM, c, zeta, d, mh = self.models[req.model]
-                mh.set_stream(st)
-                out = torch.empty(m["n"], dtype=torch.float64, device="cuda")
-                mh.predict(m["X"], m["offsets"], c, out)
-                keep = (None, out)
-            ev = torch.cuda.Event()
-            ev.record(st)
+        if req.kind == "fit":
+            p = gap.params(req.spec.d, req.spec.zeta, 1.0, 1e-8, precision=self.precision, **self.refine)
+            h = gap.Handle(p, stream=st)
+            ws_block, c_block = blocks
+            h.bind(self.arena.view(ws_block))
+            h.build_knm(m["X"], m["offsets"], m["XM"], m["sigma"])
+            c = self.arena.view(c_block, torch.float64, req.spec.M)
+            h.solve(m["y"], c, info=False)
+            keep = (h, c)
+        else:
+            XM, c, zeta, d, _, _ = self.models[req.model]
+            mh = self._predict_handle(slot, d, zeta)
+            mh.set_model(XM)
+            mh.set_stream(st)
+            out = self.arena.view(blocks[0], torch.float64, m["n"])
+            mh.predict(m["X"], m["offsets"], c, out)
+            keep = (None, out)
+        ev = torch.cuda.Event()
+        ev.record(st)
         return ev, keep
 
-    def _finish(self, req, keep, now):
+    def _predict_handle(self, slot, d, zeta):
+        key = (slot, d, zeta)  # one per slot thread: set_model / set_stream are per call
+        with self.handles_lock:
+            if key not in self.handles:
+                self.handles[key] = gap.Handle(gap.params(d, zeta, 1.0, 1e-8))
+            return self.handles[key]
+
+    def _blocks(self, req):
+        """Arena blocks of a request (None when it does not fit now)."""
+        if req.kind == "fit":
+            p = gap.params(req.spec.d, req.spec.zeta, 1.0, 1e-8, precision=self.precision, **self.refine)
+            ws = self.arena.alloc(gap.workspace_bytes(p, req.spec.n_configs, req.meta["X"].shape[0], req.spec.M))
+            if ws is None:
+                return None
+            cb = self.arena.alloc(8 * req.spec.M)
+            if cb is None:
+                self.arena.release(ws)
+                return None
+            return (ws, cb)
+        ob = self.arena.alloc(8 * req.meta["n"])
+        return None if ob is None else (ob,)
+
+    def _finish(self, req, keep, blocks, now):
         h, out = keep
         req.done = now
         if req.kind == "fit":
             s, info = h.sync()
             req.result = out.cpu().numpy()
             req.meta["status"] = s
-            # keep the model resident (sparse set + weights) and release the fit's workspace
-            mh = gap.Handle(gap.params(req.spec.d, req.spec.zeta, 1.0, 1e-8))
-            mh.set_model(req.meta["XM"])
             h.close()
-            h.ws = None
-            self.models[req.rid] = (req.meta["XM"], out, req.spec.zeta, req.spec.d, mh)
+            # release the workspace; the weights stay resident as the model
+            self.arena.release(blocks[0])
+            self.models[req.rid] = (req.meta["XM"], out, req.spec.zeta, req.spec.d, None, blocks[1])
+            busy = {k for k, v in self.model_users.items() if v > 0}
             while len(self.models) > self.resident_max:
-                _, (_, _, _, _, h_old) = self.models.popitem(last=False)
-                h_old.close()
+                victim = next((k for k in self.models if k not in busy), None)
+                if victim is None:
+                    break
+                self.arena.release(self.models.pop(victim)[5])
         else:
             req.result = out.cpu().numpy()
+            self.arena.release(blocks[0])
+            self.model_users[req.model] -= 1
 
     # ---------------------------------------------------------------- the loop
     def run(self, requests, log=None):
@@ -183,21 +287,29 @@ class Server:
         pending = collections.deque()
         todo = collections.deque(sorted(requests, key=lambda r: r.arrival))
         t0 = time.perf_counter()
-        while todo or pending or self.inflight:
+        while todo or pending or self.n_active:
             now = time.perf_counter() - t0
             while todo and todo[0].arrival <= now:
                 pending.append(todo.popleft())
-            # completions
+            # launches done by the slot threads, then completions
+            while True:
+                try:
+                    req, slot, ev, keep, blocks, exc = self.launched.get_nowait()
+                except queue.Empty:
+                    break
+                if exc is not None:
+                    raise exc
+                self.inflight.append((req, slot, ev, keep, blocks))
             still = []
-            for req, slot, ev, keep in self.inflight:
+            for req, slot, ev, keep, blocks in self.inflight:
                 if ev.query():
-                    self._finish(req, keep, time.perf_counter() - t0)
+                    self._finish(req, keep, blocks, time.perf_counter() - t0)
                     self.free.append(slot)
-                    self.in_use -= req.footprint
+                    self.n_active -= 1
                 else:
-                    still.append((req, slot, ev, keep))
+                    still.append((req, slot, ev, keep, blocks))
             self.inflight = still
-            # admission: first waiting request that fits, while slots are free
+            # admission: first waiting request whose memory fits, while slots are free
             admitted = True
             while self.free and pending and admitted:
                 admitted = False
@@ -207,17 +319,21 @@ class Server:
                         if not fits400:
                             continue
                         req.model = fits400[req.seed % len(fits400)]
-                    if self.in_use + req.footprint > self.budget and self.inflight:
+                    blocks = self._blocks(req)
+                    if blocks is None:
+                        if not self.n_active:
+                            raise RuntimeError(f"request {req.rid} needs more than the whole arena")
                         continue
                     del pending[i]
                     slot = self.free.pop()
-                    self.in_use += req.footprint
                     req.admitted = time.perf_counter() - t0
-                    ev, keep = self._launch(req, slot)
-                    self.inflight.append((req, slot, ev, keep))
+                    self.n_active += 1
+                    if req.kind == "predict":
+                        self.model_users[req.model] = self.model_users.get(req.model, 0) + 1
+                    self.work[slot].put((req, blocks))
                     admitted = True
                     break
-            if not todo and not self.inflight and pending:
+            if not todo and not self.n_active and pending:
                 # only predicts are left and no model exists yet: nothing can serve them
                 if all(r.kind == "predict" for r in pending) and not self.models:
                     break
@@ -231,12 +347,27 @@ def latency_report(requests):
     for kind in ("fit", "predict"):
         lat = np.array([r.done - r.arrival for r in requests if r.kind == kind and r.done >= 0])
         if len(lat):
+            wait = np.array([r.admitted - r.arrival for r in requests if r.kind == kind and r.done >= 0])
             out[kind] = dict(n=int(len(lat)), p50_ms=float(np.percentile(lat, 50, method="inverted_cdf") * 1e3),
                              p99_ms=float(np.percentile(lat, 99, method="inverted_cdf") * 1e3),
-                             mean_ms=float(lat.mean() * 1e3))
+                             mean_ms=float(lat.mean() * 1e3),
+                             admission_wait_p50_ms=float(np.percentile(wait, 50, method="inverted_cdf") * 1e3))
+    big = [r.done - r.arrival for r in requests if r.kind == "fit" and r.done >= 0 and r.spec.n_configs >= 50_000]
+    if big:
+        out["realistic_fits"] = dict(n=len(big), mean_ms=float(np.mean(big) * 1e3))
     done = [r for r in requests if r.done >= 0]
     if done:
         span = max(r.done for r in done) - min(r.arrival for r in done)
         out["fits_per_s"] = sum(r.kind == "fit" for r in done) / span
         out["requests_per_s"] = len(done) / span
     return out
+
+
+def close(server):
+    for q in server.work:
+        q.put(None)
+    for t in server.threads:
+        t.join()
+    for h in server.handles.values():
+        h.close()
+    server.handles.clear()

@@ -30,6 +30,7 @@ def served():
     srv.run(reqs)
     torch.cuda.synchronize()
     yield srv, reqs
+    serve.close(srv)
 
 
 def test_every_request_served(served):
@@ -74,7 +75,7 @@ def test_served_results_match_alone_and_oracle(served):
                 assert err <= 1e-8
                 checked += 1
         elif r.model >= 0:
-            XM, c, zeta, d, _ = srv.models[r.model] if r.model in srv.models else (None,) * 5
+            XM, c, zeta, d, _, _ = srv.models[r.model] if r.model in srv.models else (None,) * 6
             if XM is None:
                 continue
             p = gap.params(d, zeta, 1.0, 1e-8)
