@@ -56,8 +56,10 @@ typedef enum gap_status {
     GAP_ENOTPD = 3,      /* K_MM + jitter is not positive definite (Cholesky pivot <= 0) */
     GAP_ENONFINITE = 4,  /* a NaN or Inf reached the weights */
     GAP_ENOCONV = 5,     /* mixed precision: refinement did not reach refine_tol */
-    GAP_EDEVICE = 6,     /* a HIP runtime call failed */
-    GAP_ESTATE = 7       /* entry points called out of order */
+    GAP_EDEVICE = 6,     /* a HIP runtime call failed, or a device-side wait was abandoned */
+    GAP_ESTATE = 7,      /* entry points called out of order */
+    GAP_ERANK = 8        /* the stacked matrix is numerically rank deficient (a QR panel's
+                            Gram matrix lost positive definiteness even with the shift) */
 } gap_status;
 
 typedef enum gap_precision {
@@ -181,12 +183,17 @@ gap_status gap_layout(gap_handle h, gap_layout_info *out);
  * Waits for the stream.  n = number of floats in ms (up to 8). */
 gap_status gap_stage_times(gap_handle h, float *ms, int n);
 
-/* Launch-shape knobs an autotuner may set per handle (0 = library default).
+/* Launch-shape and method knobs an autotuner may set per handle (0 = library default).
  *   qr_split_wgs  target number of workgroups of the QR's split-K products
- *                 Y^T C (sets the row-chunk height); 256 .. 65536. */
+ *                 Y^T C (sets the row-chunk height); 256 .. 65536.
+ *   qr_panel      panel factorisation of the Householder QR: 0 = shifted
+ *                 CholeskyQR3 (streams the panel; default), 1 = TSQR over a
+ *                 4-ary tree of 256-row tiles.  Both end in the same
+ *                 reconstructed Householder representation. */
 typedef struct gap_tuning {
     int32_t qr_split_wgs;
-    int32_t reserved[7];
+    int32_t qr_panel;
+    int32_t reserved[6];
 } gap_tuning;
 
 /* Set the handle's launch-shape knobs (host-only; affects later calls).  GAP_EINVAL on

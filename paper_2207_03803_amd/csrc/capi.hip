@@ -21,7 +21,8 @@ struct Layout {
     TsqrTree tree;
     size_t off_A = 0, off_tau = 0, off_wpart = 0, off_T = 0, off_Tin = 0, off_U = 0, off_W = 0, off_ts_tiles = 0,
            off_ts_X = 0, off_ts_tau = 0, off_rhs = 0, off_misc = 0, off_tiles = 0, off_counters = 0,
-           off_status = 0, off_tflags = 0, n_tflags = 0, total = 0;
+           off_status = 0, off_tflags = 0, n_tflags = 0, off_cq_S = 0, off_cq_part = 0, off_cq_G = 0, off_cq_R = 0,
+           total = 0;
     // mixed precision only
     bool mixed = false;
     size_t off_A32 = 0, off_W32 = 0, off_r = 0, off_s = 0, off_z = 0, off_dc = 0, off_part = 0,
@@ -65,6 +66,10 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, bool mixed)
     L.off_status = take(sizeof(int32_t) * 4);
     L.n_tflags = trsv_sync_ints(M);
     L.off_tflags = take(sizeof(int32_t) * (size_t)L.n_tflags);
+    L.off_cq_S = take(sizeof(double) * QR_NB * (size_t)L.lda);
+    L.off_cq_part = take(sizeof(double) * (size_t)CQ_MAX_CHUNKS * QR_NB * QR_NB);
+    L.off_cq_G = take(sizeof(double) * QR_NB * QR_NB);
+    L.off_cq_R = take(sizeof(double) * 4 * QR_NB * QR_NB);
     if (mixed) {
         const int64_t ldw = (L.ncols + 63) / 64 * 64;
         L.off_A32 = take(sizeof(float) * (size_t)L.lda * (size_t)L.ncols);
@@ -172,6 +177,7 @@ const char *gap_status_string(gap_status s)
     case GAP_ENOTPD: return "K_MM + jitter is not positive definite";
     case GAP_ENONFINITE: return "non-finite value in the weights";
     case GAP_ENOCONV: return "refinement did not converge";
+    case GAP_ERANK: return "stacked matrix numerically rank deficient";
     case GAP_EDEVICE: return "HIP runtime error";
     case GAP_ESTATE: return "entry point called out of order";
     }
@@ -358,6 +364,12 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
     w.tree = L.tree;
     w.max_chunks = qr_max_chunks();
     w.split_wgs = h->tuning.qr_split_wgs;
+    w.panel = h->tuning.qr_panel;
+    w.cq_S = h->at<double>(L.off_cq_S);
+    w.cq_ld = L.lda;
+    w.cq_part = h->at<double>(L.off_cq_part);
+    w.cq_G = h->at<double>(L.off_cq_G);
+    w.cq_R = h->at<double>(L.off_cq_R);
     w.status = h->status();
     double *rhs = h->at<double>(L.off_rhs);
     if (!L.mixed) {
@@ -486,6 +498,8 @@ gap_status gap_set_tuning(gap_handle h, const gap_tuning *t)
     if (!h || !t)
         return GAP_EINVAL;
     if (t->qr_split_wgs != 0 && (t->qr_split_wgs < 256 || t->qr_split_wgs > 65536))
+        return GAP_EINVAL;
+    if (t->qr_panel != 0 && t->qr_panel != 1)
         return GAP_EINVAL;
     h->tuning = *t;
     return GAP_OK;

@@ -17,6 +17,7 @@ enum : int32_t {
     DST_ENONFINITE = 4,
     DST_ENOCONV = 5,
     DST_EDEVICE = 6,  // a device-side wait was abandoned
+    DST_ERANK = 8,    // a QR panel's Gram matrix lost positive definiteness
 };
 
 // Record the first failure seen on the device; later ones do not overwrite it.

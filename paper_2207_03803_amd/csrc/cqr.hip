@@ -1,0 +1,387 @@
+// Panel factorisation of the blocked Householder QR by shifted CholeskyQR3
+// (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa 2020), followed by the
+// same Householder reconstruction as the TSQR panel (Ballard et al. 2015):
+//
+//   P = Q1 R1   from the Gram matrix P^T P + s I (shift s = 11 (mk pw + pw (pw+1)) u ||P||_F^2)
+//   Q1 = Q2 R2, Q2 = Q R3  (two unshifted Cholesky QR passes)
+//   R = S R3 R2 R1 with S and the unit lower Y1 from the LU of Q[0:pw] - S
+//   Y (rows below the top block) = Q2 (U R3)^-1,  T = -U S Y1^-T,  tau = diag(T)
+//
+// so the panel leaves the LAPACK-form representation H = I - Y T Y^T, R above
+// the diagonal, exactly as the TSQR panel does.  Every pass streams the panel
+// (Gram products on FP64 MFMA, row-parallel triangular solves), so the panel
+// costs a few reads of mk x 64 values instead of 64 dependent column steps.
+// The intermediate Q's are kept in an FP64 scratch panel; the factored matrix
+// may be stored in FP32 (arithmetic stays FP64).
+#include "kernels.h"
+
+namespace gap {
+
+constexpr int CB = QR_NB;        // panel width bound (64)
+constexpr int CQ_ROWS = 256;     // rows per workgroup of the row passes
+using GS = TileShape<64, 64, 16, 2, 2>;
+
+template <int N>
+DEV void load_run_cvt(const double *__restrict__ p, double (&v)[N])
+{
+    load_run(p, v);
+}
+
+template <int N>
+DEV void load_run_cvt(const float *__restrict__ p, double (&v)[N])
+{
+    static_assert(N % 4 == 0, "runs of a multiple of 4 floats");
+    const float4 *q = reinterpret_cast<const float4 *>(p);
+#pragma unroll
+    for (int e = 0; e < N / 4; ++e) {
+        const float4 f = q[e];
+        v[4 * e] = f.x;
+        v[4 * e + 1] = f.y;
+        v[4 * e + 2] = f.z;
+        v[4 * e + 3] = f.w;
+    }
+}
+
+// Partial Gram matrices: part[ch] = sum over rows [ch*chunk, +chunk) of
+// P[r][:]^T P[r][:] for the pw columns of P (column-major, ld; 64 x 64 with
+// zeros outside pw).
+template <class T>
+__global__ __launch_bounds__(256, 2) void cqr_gram_kernel(const T *__restrict__ P, int64_t ld, int64_t rows, int pw,
+                                                          int64_t chunk, double *__restrict__ part)
+{
+    __shared__ double lds[2 * GS::STAGE];
+    const int64_t ch = blockIdx.x;
+    const int64_t lo = ch * chunk;
+    const int64_t hi = (lo + chunk) < rows ? (lo + chunk) : rows;
+    d4 acc[GS::FM][GS::FN];
+    zero_acc<GS>(acc);
+    constexpr int V = GS::BM * GS::BK / GS::NT;
+    auto f = [&](int p, int64_t k, double (&v)[V]) {
+        const int64_t r = lo + k;
+        if (p >= pw) {
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                v[e] = 0.0;
+        } else if (r + V <= hi) {
+            load_run_cvt(P + p * ld + r, v);
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                v[e] = (r + e < hi) ? (double)P[p * ld + r + e] : 0.0;
+        }
+    };
+    if (lo < hi)
+        gemm_tile_runs<GS, true, true>(acc, lds, hi - lo, f, f);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave / GS::WN, wn = wave % GS::WN;
+    double *out = part + ch * (CB * CB);
+#pragma unroll
+    for (int i = 0; i < GS::FM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < GS::FN; ++jj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                out[acc_row<GS>(wm, i, lane, e) * CB + acc_col<GS>(wn, jj, lane, e)] = acc[i][jj][e];
+}
+
+// G = sum of the partials in chunk order (16 workgroups x 256 entries).
+__global__ __launch_bounds__(256) void cqr_gsum_kernel(const double *__restrict__ part, int64_t nch,
+                                                       double *__restrict__ G)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    double s = 0.0;
+    for (int64_t c = 0; c < nch; ++c)
+        s += part[c * (CB * CB) + e];
+    G[e] = s;
+}
+
+// Cholesky G + shift I = R^T R of the leading pw x pw block (identity beyond),
+// by the first wave; every thread of the workgroup reaches the same barriers.
+// S holds G on entry and R (upper, zeros below) on exit.  Returns false when a
+// pivot is not positive (the panel is numerically rank deficient).
+DEV bool chol64(double (&S)[CB][CB + 1], double *rrow, int pw, double shift_coef)
+{
+    const int l = threadIdx.x;
+    __shared__ double tr_lds;
+    if (l < 64) {
+        double d = (l < pw) ? S[l][l] : 0.0;
+        d = wave_sum(d);
+        if (l == 0)
+            tr_lds = d;
+    }
+    __syncthreads();
+    if (l < pw)
+        S[l][l] += shift_coef * tr_lds;
+    bool ok = true;
+    for (int k = 0; k < CB; ++k) {
+        __syncthreads();
+        const double dkk = S[k][k];
+        double rkk = sqrt(dkk);
+        if (!(dkk > 0.0) || !(rkk < INFINITY)) {
+            ok = false;
+            rkk = 1.0;
+        }
+        double rkj = 0.0;
+        if (l < 64) {
+            rkj = (l > k) ? S[k][l] / rkk : (l == k ? rkk : 0.0);
+            rrow[l] = rkj;
+        }
+        __syncthreads();
+        if (l < 64) {
+            S[k][l] = rkj;
+            for (int i = k + 1; i <= l; ++i)
+                S[i][l] -= rrow[i] * rkj;
+        }
+    }
+    __syncthreads();
+    if (l < 64)
+        for (int i = l + 1; i < CB; ++i)
+            S[i][l] = 0.0;  // below the diagonal of column l
+    __syncthreads();
+    return ok;
+}
+
+// R_out = chol(G + shift I) (row-major 64 x 64, identity beyond pw).
+__global__ __launch_bounds__(64) void cqr_chol_kernel(const double *__restrict__ G, int pw, double shift_coef,
+                                                      double *__restrict__ Rout, int32_t *status)
+{
+    __shared__ double S[CB][CB + 1];
+    __shared__ double rrow[CB];
+    const int l = threadIdx.x;
+    for (int i = 0; i < CB; ++i)
+        S[i][l] = (i < pw && l < pw) ? G[i * CB + l] : (i == l ? 1.0 : 0.0);
+    __syncthreads();
+    if (!chol64(S, rrow, pw, shift_coef) && l == 0)
+        set_status(status, DST_ERANK);
+    for (int i = 0; i < CB; ++i)
+        Rout[i * CB + l] = S[i][l];
+}
+
+// Row pass: dst[r][:] = src[r][:] R^-1 (R upper 64 x 64 row-major) for rows
+// r0 .. rows-1, pw columns; one row per thread.
+template <class TS, class TD>
+__global__ __launch_bounds__(256) void cqr_pass_kernel(const TS *__restrict__ src, int64_t lds_, TD *__restrict__ dst,
+                                                       int64_t ldd, int64_t r0, int64_t rows, int pw,
+                                                       const double *__restrict__ R)
+{
+    __shared__ double Rs[CB][CB + 1];
+    __shared__ double rinv[CB];
+    for (int idx = threadIdx.x; idx < CB * CB; idx += 256)
+        Rs[idx / CB][idx % CB] = R[idx];
+    __syncthreads();
+    if (threadIdx.x < CB)
+        rinv[threadIdx.x] = 1.0 / Rs[threadIdx.x][threadIdx.x];
+    __syncthreads();
+    const int64_t r = r0 + (int64_t)blockIdx.x * CQ_ROWS + threadIdx.x;
+    if (r >= rows)
+        return;
+    double y[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+        y[c] = (c < pw) ? (double)src[c * lds_ + r] : 0.0;
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        if (c < pw) {
+            double v = y[c];
+#pragma unroll
+            for (int i = 0; i < c; ++i)
+                v -= y[i] * Rs[i][c];
+            y[c] = v * rinv[c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+        if (c < pw)
+            dst[c * ldd + r] = (TD)y[c];
+}
+
+// The last Cholesky pass and the reconstruction of the top block (one
+// workgroup): R3 = chol(G), Q_top = Q2[0:pw] R3^-1, LU of Q_top - S, the
+// compact-WY T, R = S R3 R2 R1 and Y1 into the panel's top block, tau, and
+// U R3 for the row pass that forms Y below the top block.
+template <class T>
+__global__ __launch_bounds__(256) void cqr_top_kernel(QrWork w, int64_t j0, int pw, double *__restrict__ Tout)
+{
+    __shared__ double R3[CB][CB + 1];
+    __shared__ double B[CB][CB + 1];   // Q_top, then its LU (U on and above, multipliers below)
+    __shared__ double X[CB][CB + 1];   // R2 R1, then Y1^-1
+    __shared__ double rrow[CB];
+    __shared__ double sg[CB];
+    const int t = threadIdx.x;
+    const double *G = w.cq_G;
+    const double *R1 = w.cq_R, *R2 = w.cq_R + CB * CB;
+    for (int idx = t; idx < CB * CB; idx += 256) {
+        const int i = idx / CB, l = idx % CB;
+        R3[i][l] = (i < pw && l < pw) ? G[idx] : (i == l ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    if (!chol64(R3, rrow, pw, 0.0) && t == 0)
+        set_status(w.status, DST_ERANK);
+    // Q_top (row r = t) and X = R2 R1
+    if (t < CB) {
+        const int r = t;
+        double y[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            y[c] = (c < pw && r < pw) ? w.cq_S[c * w.cq_ld + r] : 0.0;
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            double v = y[c];
+#pragma unroll
+            for (int i = 0; i < c; ++i)
+                v -= y[i] * R3[i][c];
+            y[c] = v / R3[c][c];
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            B[r][c] = (r < pw && c < pw) ? y[c] : 0.0;
+    }
+    for (int idx = t; idx < CB * CB; idx += 256) {
+        const int r = idx / CB, c = idx % CB;
+        double v = 0.0;
+        for (int p = r; p <= c; ++p)
+            v += R2[r * CB + p] * R1[p * CB + c];
+        X[r][c] = (r <= c) ? v : 0.0;
+    }
+    __syncthreads();
+    // R = S R3 (R2 R1) written after the LU; first the LU of Q_top - S
+    // (s_k = -sign(pivot), sign(0) = +1), two barriers per step
+    for (int k = 0; k < pw; ++k) {
+        const double d = B[k][k];
+        const double s = (d >= 0.0) ? -1.0 : 1.0;
+        const double piv = d - s;
+        const int wdt = pw - k - 1;
+        double nv[16];
+        int cnt = 0;
+        for (int idx = t; idx < wdt * wdt && cnt < 16; idx += 256, ++cnt) {
+            const int i = k + 1 + idx % wdt, c = k + 1 + idx / wdt;
+            nv[cnt] = B[i][c] - (B[i][k] / piv) * B[k][c];
+        }
+        __syncthreads();
+        cnt = 0;
+        for (int idx = t; idx < wdt * wdt && cnt < 16; idx += 256, ++cnt) {
+            const int i = k + 1 + idx % wdt, c = k + 1 + idx / wdt;
+            B[i][c] = nv[cnt];
+        }
+        if (t > k && t < pw)
+            B[t][k] = B[t][k] / piv;
+        if (t == 0) {
+            B[k][k] = piv;
+            sg[k] = s;
+        }
+        __syncthreads();
+    }
+    // Rc = R3 X (upper), kept in R3's place is not possible while R3 is read:
+    // compute into registers, then write R and Y1 to the panel's top block.
+    double rv[16];
+    {
+        int cnt = 0;
+        for (int idx = t; idx < CB * CB; idx += 256, ++cnt) {
+            const int r = idx / CB, c = idx % CB;
+            double v = 0.0;
+            if (r <= c)
+                for (int p = r; p <= c; ++p)
+                    v += R3[r][p] * X[p][c];
+            rv[cnt] = v;
+        }
+    }
+    __syncthreads();
+    // X := Y1^-1 (unit lower), one wave per group of columns, lane = row
+    {
+        const int lane = t & 63, wave = t >> 6;
+        for (int c = wave; c < CB; c += 4) {
+            double x = (lane == c) ? 1.0 : 0.0;
+            for (int k = 0; k < pw; ++k) {
+                const double xk = __shfl(x, k, 64);
+                if (lane > k && lane < pw)
+                    x -= B[lane][k] * xk;
+            }
+            X[lane][c] = (lane < pw && c < pw) ? x : 0.0;
+        }
+    }
+    __syncthreads();
+    T *Ap = (sizeof(T) == 8) ? reinterpret_cast<T *>(w.A) : reinterpret_cast<T *>(w.A32);
+    {
+        int cnt = 0;
+        for (int idx = t; idx < CB * CB; idx += 256, ++cnt) {
+            const int r = idx / CB, c = idx % CB;
+            // T = -U S Y1^-T:  T[r][c] = -sum_{p=r..c} U[r][p] s_p (Y1^-1)[c][p]
+            double tv = 0.0;
+            if (r < pw && c < pw && r <= c)
+                for (int p = r; p <= c; ++p)
+                    tv -= B[r][p] * sg[p] * X[c][p];
+            Tout[idx] = tv;
+            if (r < pw && c < pw) {
+                const double out = (r <= c) ? sg[r] * rv[cnt] : B[r][c];
+                Ap[(j0 + c) * w.lda + j0 + r] = (T)out;
+            }
+            if (r == c && r < pw)
+                w.tau[j0 + r] = tv;
+            // U R3 (upper) for the row pass below the top block; identity beyond pw
+            double ur = 0.0;
+            if (r < pw && c < pw) {
+                if (r <= c)
+                    for (int p = r; p <= c; ++p)
+                        ur += B[r][p] * R3[p][c];
+            } else if (r == c) {
+                ur = 1.0;
+            }
+            w.cq_R[3 * CB * CB + idx] = ur;
+        }
+    }
+}
+
+template <class T>
+static void cqr_panel(const QrWork &w, int64_t j0, int pw, double *Tout, hipStream_t s)
+{
+    T *base = ((sizeof(T) == 8) ? reinterpret_cast<T *>(w.A) : reinterpret_cast<T *>(w.A32)) + j0 * w.lda + j0;
+    const int64_t mk = w.m - j0;
+    int64_t chunk = (mk + CQ_MAX_CHUNKS - 1) / CQ_MAX_CHUNKS;
+    chunk = (chunk + CQ_ROWS - 1) / CQ_ROWS * CQ_ROWS;
+    if (chunk < CQ_ROWS)
+        chunk = CQ_ROWS;
+    const unsigned nch = (unsigned)((mk + chunk - 1) / chunk);
+    const unsigned nrow = (unsigned)((mk + CQ_ROWS - 1) / CQ_ROWS);
+    const double u = 0x1p-53;
+    const double shift = 11.0 * ((double)mk * pw + (double)pw * (pw + 1)) * u;
+    double *R1 = w.cq_R, *R2 = w.cq_R + CB * CB, *UR3 = w.cq_R + 3 * CB * CB;
+    // pass 1 (shifted): Gram of P, R1, Q1 = P R1^-1 into the scratch
+    hipLaunchKernelGGL(cqr_gram_kernel<T>, dim3(nch), dim3(256), 0, s, (const T *)base, w.lda, mk, pw, chunk,
+                       w.cq_part);
+    hipLaunchKernelGGL(cqr_gsum_kernel, dim3(CB * CB / 256), dim3(256), 0, s, (const double *)w.cq_part,
+                       (int64_t)nch, w.cq_G);
+    hipLaunchKernelGGL(cqr_chol_kernel, dim3(1), dim3(64), 0, s, (const double *)w.cq_G, pw, shift, R1, w.status);
+    hipLaunchKernelGGL((cqr_pass_kernel<T, double>), dim3(nrow), dim3(256), 0, s, (const T *)base, w.lda, w.cq_S,
+                       w.cq_ld, (int64_t)0, mk, pw, (const double *)R1);
+    // pass 2: Q2 = Q1 R2^-1 in place
+    hipLaunchKernelGGL(cqr_gram_kernel<double>, dim3(nch), dim3(256), 0, s, (const double *)w.cq_S, w.cq_ld, mk, pw,
+                       chunk, w.cq_part);
+    hipLaunchKernelGGL(cqr_gsum_kernel, dim3(CB * CB / 256), dim3(256), 0, s, (const double *)w.cq_part,
+                       (int64_t)nch, w.cq_G);
+    hipLaunchKernelGGL(cqr_chol_kernel, dim3(1), dim3(64), 0, s, (const double *)w.cq_G, pw, 0.0, R2, w.status);
+    hipLaunchKernelGGL((cqr_pass_kernel<double, double>), dim3(nrow), dim3(256), 0, s, (const double *)w.cq_S,
+                       w.cq_ld, w.cq_S, w.cq_ld, (int64_t)0, mk, pw, (const double *)R2);
+    // pass 3: R3 from the Gram of Q2, the top block's reconstruction, then Y below it
+    hipLaunchKernelGGL(cqr_gram_kernel<double>, dim3(nch), dim3(256), 0, s, (const double *)w.cq_S, w.cq_ld, mk, pw,
+                       chunk, w.cq_part);
+    hipLaunchKernelGGL(cqr_gsum_kernel, dim3(CB * CB / 256), dim3(256), 0, s, (const double *)w.cq_part,
+                       (int64_t)nch, w.cq_G);
+    hipLaunchKernelGGL(cqr_top_kernel<T>, dim3(1), dim3(256), 0, s, w, j0, pw, Tout);
+    if (mk > pw) {
+        const unsigned nb = (unsigned)((mk - pw + CQ_ROWS - 1) / CQ_ROWS);
+        hipLaunchKernelGGL((cqr_pass_kernel<double, T>), dim3(nb), dim3(256), 0, s, (const double *)w.cq_S, w.cq_ld,
+                           base, w.lda, (int64_t)pw, mk, pw, (const double *)UR3);
+    }
+}
+
+void cqr_panel_f64(const QrWork &w, int64_t j0, int pw, double *Tout, hipStream_t s)
+{
+    cqr_panel<double>(w, j0, pw, Tout, s);
+}
+
+void cqr_panel_f32(const QrWork &w, int64_t j0, int pw, double *Tout, hipStream_t s)
+{
+    cqr_panel<float>(w, j0, pw, Tout, s);
+}
+
+}  // namespace gap

@@ -4,8 +4,9 @@
 // carrying b along as an extra column, which is what applying the stored
 // reflectors to b computes).
 //
-// Each 64-column panel is factored as a tall-skinny QR (TSQR) over a
-// 4-ary tree of 256-row tiles, its explicit Q formed top-down, and the
+// Each 64-column panel is factored by shifted CholeskyQR3 (cqr.hip) or, as
+// selected per handle, as a tall-skinny QR (TSQR) over a 4-ary tree of
+// 256-row tiles with its explicit Q formed top-down; in both cases the
 // Householder vectors Y and the compact-WY factor T recovered from that Q by
 // an LU factorisation of Q - S with the sign matrix S chosen to keep every
 // pivot at least 1 in magnitude (Ballard, Demmel, Grigori, Jacquelin, Knight,
@@ -743,6 +744,13 @@ static void chunking(int64_t rows, int64_t ncb, int64_t &chunk, int64_t &nch, in
 template <class T>
 static void factor_panel(const QrWork &w, int64_t j0, int pw, double *Tout, hipStream_t s)
 {
+    if (w.panel == 0) {
+        if constexpr (sizeof(T) == 8)
+            cqr_panel_f64(w, j0, pw, Tout, s);
+        else
+            cqr_panel_f32(w, j0, pw, Tout, s);
+        return;
+    }
     const int64_t mk = w.m - j0;
     const PanelTree pt = panel_tree(mk);
     for (int l = 0; l < pt.levels; ++l)

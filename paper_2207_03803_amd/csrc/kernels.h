@@ -86,8 +86,18 @@ struct QrWork {
     TsqrTree tree;    // sized for m rows
     int64_t max_chunks;
     int32_t split_wgs;  // target workgroups of the split-K products (0 = default)
+    int32_t panel;      // panel factorisation: 0 = shifted CholeskyQR3, 1 = TSQR
+    double *cq_S;       // CholeskyQR: FP64 scratch panel [QR_NB x cq_ld] (column-major)
+    int64_t cq_ld;      // >= m
+    double *cq_part;    // [CQ_MAX_CHUNKS * QR_NB * QR_NB] partial Gram matrices
+    double *cq_G;       // [QR_NB * QR_NB] Gram matrix
+    double *cq_R;       // [4 * QR_NB * QR_NB] R1, R2, (unused), U R3 (row-major)
     int32_t *status;
 };
+constexpr int64_t CQ_MAX_CHUNKS = 256;
+// Shifted CholeskyQR3 panel + Householder reconstruction (same outputs as the TSQR panel).
+void cqr_panel_f64(const QrWork &w, int64_t j0, int pw, double *Tout, hipStream_t s);
+void cqr_panel_f32(const QrWork &w, int64_t j0, int pw, double *Tout, hipStream_t s);
 int64_t qr_max_chunks();
 hipError_t launch_geqrf(const QrWork &w, hipStream_t s);
 

@@ -13,7 +13,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgap.so")
 
-GAP_OK, GAP_EINVAL, GAP_ENOMEM, GAP_ENOTPD, GAP_ENONFINITE, GAP_ENOCONV, GAP_EDEVICE, GAP_ESTATE = range(8)
+GAP_OK, GAP_EINVAL, GAP_ENOMEM, GAP_ENOTPD, GAP_ENONFINITE, GAP_ENOCONV, GAP_EDEVICE, GAP_ESTATE, GAP_ERANK = range(9)
 GAP_FP64, GAP_MIXED_FP32 = 0, 1
 GAP_FLAG_TIMING = 1
 
@@ -39,7 +39,7 @@ class GapSolveInfo(ctypes.Structure):
 
 
 class GapTuning(ctypes.Structure):
-    _fields_ = [("qr_split_wgs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("qr_split_wgs", ctypes.c_int32), ("qr_panel", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class GapLayoutInfo(ctypes.Structure):
@@ -205,9 +205,10 @@ class Handle:
         off = lay.tau - self.ws.data_ptr()
         return self.ws[off:off + 8 * lay.M].view(torch.float64)
 
-    def set_tuning(self, qr_split_wgs=0):
+    def set_tuning(self, qr_split_wgs=0, qr_panel=0):
         t = GapTuning()
         t.qr_split_wgs = int(qr_split_wgs)
+        t.qr_panel = int(qr_panel)
         _check(lib().gap_set_tuning(self.h, ctypes.byref(t)), "gap_set_tuning")
 
     def set_model(self, XM):

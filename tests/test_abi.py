@@ -28,9 +28,10 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_status_strings():
-    for s in range(8):
-        assert gap.status_string(s)
+    for s in range(9):
+        assert gap.status_string(s) != "unknown status"
     assert gap.status_string(gap.GAP_ENOTPD).startswith("K_MM")
+    assert "rank" in gap.status_string(gap.GAP_ERANK)
 
 
 def test_create_rejects_bad_params_without_a_gpu():
