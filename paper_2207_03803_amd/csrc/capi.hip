@@ -68,7 +68,7 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, bool mixed)
     L.off_tflags = take(sizeof(int32_t) * (size_t)L.n_tflags);
     L.off_cq_S = take(sizeof(double) * QR_NB * (size_t)L.lda);
     L.off_cq_part = take(sizeof(double) * (size_t)CQ_MAX_CHUNKS * QR_NB * QR_NB);
-    L.off_cq_G = take(sizeof(double) * QR_NB * QR_NB);
+    L.off_cq_G = take(sizeof(double) * 4 * QR_NB * QR_NB);
     L.off_cq_R = take(sizeof(double) * 4 * QR_NB * QR_NB);
     if (mixed) {
         const int64_t ldw = (L.ncols + 63) / 64 * 64;

@@ -84,77 +84,135 @@ __global__ __launch_bounds__(256, 2) void cqr_gram_kernel(const T *__restrict__ 
                 out[acc_row<GS>(wm, i, lane, e) * CB + acc_col<GS>(wn, jj, lane, e)] = acc[i][jj][e];
 }
 
-// G = sum of the partials in chunk order (16 workgroups x 256 entries).
+// Four partial sums of the chunk partials: G4[q][e] = sum over chunks
+// c = q, q + 4, ... in order (grid 16 x 4; entries e of block x).
 __global__ __launch_bounds__(256) void cqr_gsum_kernel(const double *__restrict__ part, int64_t nch,
-                                                       double *__restrict__ G)
+                                                       double *__restrict__ G4)
 {
     const int e = blockIdx.x * 256 + threadIdx.x;
-    double s = 0.0;
-    for (int64_t c = 0; c < nch; ++c)
-        s += part[c * (CB * CB) + e];
-    G[e] = s;
+    const int q = blockIdx.y;
+    double s0 = 0.0, s1 = 0.0;
+    int64_t c = q;
+    for (; c + 4 < nch; c += 8) {
+        s0 += part[c * (CB * CB) + e];
+        s1 += part[(c + 4) * (CB * CB) + e];
+    }
+    if (c < nch)
+        s0 += part[c * (CB * CB) + e];
+    G4[q * (CB * CB) + e] = s0 + s1;
 }
 
-// Cholesky G + shift I = R^T R of the leading pw x pw block (identity beyond),
-// by the first wave; every thread of the workgroup reaches the same barriers.
-// S holds G on entry and R (upper, zeros below) on exit.  Returns false when a
-// pivot is not positive (the panel is numerically rank deficient).
-DEV bool chol64(double (&S)[CB][CB + 1], double *rrow, int pw, double shift_coef)
+// Value of v in lane `lane` (uniform) of the wave.
+DEV double readlane_d(double v, int lane)
 {
-    const int l = threadIdx.x;
-    __shared__ double tr_lds;
-    if (l < 64) {
-        double d = (l < pw) ? S[l][l] : 0.0;
-        d = wave_sum(d);
-        if (l == 0)
-            tr_lds = d;
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Order the wave's LDS accesses (the steps below run on one wave).
+DEV void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Gram matrix into S by a 256-thread workgroup (all loads in flight at
+// once): the sum of the four partial sums, identity beyond pw, and
+// shift_coef * trace added to the diagonal.  Ends with a barrier.
+DEV void gram_lds(const double *__restrict__ G4, int pw, double shift_coef, double (&S)[CB][CB + 1])
+{
+    const int t = threadIdx.x;
+    double g[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int e = t + 256 * u;
+        g[u] = (G4[e] + G4[CB * CB + e]) + (G4[2 * CB * CB + e] + G4[3 * CB * CB + e]);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int e = t + 256 * u, i = e / CB, l = e % CB;
+        S[i][l] = (i < pw && l < pw) ? g[u] : (i == l ? 1.0 : 0.0);
     }
     __syncthreads();
-    if (l < pw)
-        S[l][l] += shift_coef * tr_lds;
+    if (t < 64) {
+        const double d = (t < pw) ? S[t][t] : 0.0;
+        const double tr = wave_sum(d);
+        if (t < pw)
+            S[t][t] = d + shift_coef * tr;
+    }
+    __syncthreads();
+}
+
+// Cholesky S = R^T R in place (one wave; lane l owns column l, S[i][l] for
+// i <= l): on exit S holds R (zeros below the diagonal).  A pivot that is not
+// positive is replaced by 1 and reported through the return value.
+DEV bool chol_lds(double (&S)[CB][CB + 1], double *rrow)
+{
+    const int l = threadIdx.x & 63;
     bool ok = true;
     for (int k = 0; k < CB; ++k) {
-        __syncthreads();
         const double dkk = S[k][k];
         double rkk = sqrt(dkk);
         if (!(dkk > 0.0) || !(rkk < INFINITY)) {
             ok = false;
             rkk = 1.0;
         }
-        double rkj = 0.0;
-        if (l < 64) {
-            rkj = (l > k) ? S[k][l] / rkk : (l == k ? rkk : 0.0);
-            rrow[l] = rkj;
-        }
-        __syncthreads();
-        if (l < 64) {
-            S[k][l] = rkj;
-            for (int i = k + 1; i <= l; ++i)
-                S[i][l] -= rrow[i] * rkj;
-        }
+        const double rkj = (l > k) ? S[k][l] / rkk : (l == k ? rkk : 0.0);
+        rrow[l] = rkj;
+        wave_sync();
+        S[k][l] = rkj;
+#pragma unroll 4
+        for (int i = k + 1; i <= l; ++i)
+            S[i][l] -= rrow[i] * rkj;
+        wave_sync();
     }
-    __syncthreads();
-    if (l < 64)
-        for (int i = l + 1; i < CB; ++i)
-            S[i][l] = 0.0;  // below the diagonal of column l
-    __syncthreads();
+    for (int i = l + 1; i < CB; ++i)
+        S[i][l] = 0.0;
+    wave_sync();
     return ok;
 }
 
-// R_out = chol(G + shift I) (row-major 64 x 64, identity beyond pw).
-__global__ __launch_bounds__(64) void cqr_chol_kernel(const double *__restrict__ G, int pw, double shift_coef,
-                                                      double *__restrict__ Rout, int32_t *status)
+// R_out = chol(G + shift I) (row-major 64 x 64, identity beyond pw); when
+// Rprev is given, also Rprod = R_out Rprev (both upper triangular).  The
+// factorisation runs on the first wave; loads and products on all four.
+__global__ __launch_bounds__(256) void cqr_chol_kernel(const double *__restrict__ G4, int pw, double shift_coef,
+                                                       double *__restrict__ Rout, const double *__restrict__ Rprev,
+                                                       double *__restrict__ Rprod, int32_t *status)
 {
     __shared__ double S[CB][CB + 1];
+    __shared__ double Pv[CB][CB + 1];
     __shared__ double rrow[CB];
-    const int l = threadIdx.x;
-    for (int i = 0; i < CB; ++i)
-        S[i][l] = (i < pw && l < pw) ? G[i * CB + l] : (i == l ? 1.0 : 0.0);
-    __syncthreads();
-    if (!chol64(S, rrow, pw, shift_coef) && l == 0)
+    const int t = threadIdx.x;
+    double pv[16];
+    if (Rprev) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            pv[u] = Rprev[t + 256 * u];
+    }
+    gram_lds(G4, pw, shift_coef, S);
+    if (t < 64 && !chol_lds(S, rrow) && t == 0)
         set_status(status, DST_ERANK);
-    for (int i = 0; i < CB; ++i)
-        Rout[i * CB + l] = S[i][l];
+    if (Rprev) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            Pv[(t + 256 * u) / CB][(t + 256 * u) % CB] = pv[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int e = t + 256 * u, i = e / CB, l = e % CB;
+        Rout[e] = S[i][l];
+        if (Rprev) {
+            // entry (i, l) of R Rprev: sum over p in [i, l] of R[i][p] Rprev[p][l]
+            double v = 0.0;
+            for (int p = i; p <= l; ++p)
+                v += S[i][p] * Pv[p][l];
+            Rprod[e] = v;
+        }
+    }
 }
 
 // Row pass: dst[r][:] = src[r][:] R^-1 (R upper 64 x 64 row-major) for rows
@@ -166,8 +224,15 @@ __global__ __launch_bounds__(256) void cqr_pass_kernel(const TS *__restrict__ sr
 {
     __shared__ double Rs[CB][CB + 1];
     __shared__ double rinv[CB];
-    for (int idx = threadIdx.x; idx < CB * CB; idx += 256)
-        Rs[idx / CB][idx % CB] = R[idx];
+    {
+        double rv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            rv[u] = R[threadIdx.x + 256 * u];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            Rs[(threadIdx.x + 256 * u) / CB][(threadIdx.x + 256 * u) % CB] = rv[u];
+    }
     __syncthreads();
     if (threadIdx.x < CB)
         rinv[threadIdx.x] = 1.0 / Rs[threadIdx.x][threadIdx.x];
@@ -198,136 +263,123 @@ __global__ __launch_bounds__(256) void cqr_pass_kernel(const TS *__restrict__ sr
 // The last Cholesky pass and the reconstruction of the top block (one
 // workgroup): R3 = chol(G), Q_top = Q2[0:pw] R3^-1, LU of Q_top - S, the
 // compact-WY T, R = S R3 R2 R1 and Y1 into the panel's top block, tau, and
-// U R3 for the row pass that forms Y below the top block.
+// U R3 for the row pass that forms Y below the top block.  The sequential
+// 64-step parts (Cholesky, triangular solve, LU) run on one wave; the
+// products on all four.
 template <class T>
 __global__ __launch_bounds__(256) void cqr_top_kernel(QrWork w, int64_t j0, int pw, double *__restrict__ Tout)
 {
-    __shared__ double R3[CB][CB + 1];
+    __shared__ double R3[CB][CB + 1];  // R3[i][l], upper
     __shared__ double B[CB][CB + 1];   // Q_top, then its LU (U on and above, multipliers below)
     __shared__ double X[CB][CB + 1];   // R2 R1, then Y1^-1
-    __shared__ double rrow[CB];
     __shared__ double sg[CB];
-    const int t = threadIdx.x;
-    const double *G = w.cq_G;
-    const double *R1 = w.cq_R, *R2 = w.cq_R + CB * CB;
-    for (int idx = t; idx < CB * CB; idx += 256) {
-        const int i = idx / CB, l = idx % CB;
-        R3[i][l] = (i < pw && l < pw) ? G[idx] : (i == l ? 1.0 : 0.0);
+    __shared__ double tmp[CB];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    {
+        double xv[16], bv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = t + 256 * u, r = e / CB, c = e % CB;
+            xv[u] = w.cq_R[2 * CB * CB + e];  // R2 R1
+            bv[u] = (r < pw && c < pw) ? w.cq_S[c * w.cq_ld + r] : 0.0;
+        }
+        gram_lds(w.cq_G, pw, 0.0, R3);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = t + 256 * u;
+            X[e / CB][e % CB] = xv[u];
+            B[e / CB][e % CB] = bv[u];
+        }
+    }
+    if (wave == 0 && !chol_lds(R3, tmp) && lane == 0)
+        set_status(w.status, DST_ERANK);
+    __syncthreads();
+    if (wave == 0) {
+        // Q_top = Q2_top R3^-1 in place, lane = row
+        const int r = lane;
+        for (int c = 0; c < pw; ++c) {
+            double v = B[r][c];
+#pragma unroll 4
+            for (int i = 0; i < c; ++i)
+                v -= B[r][i] * R3[i][c];
+            B[r][c] = v / R3[c][c];
+        }
+        wave_sync();
+        // LU of Q_top - S (s_k = -sign(pivot), sign(0) = +1), lane = row
+        for (int k = 0; k < pw; ++k) {
+            const double d = B[k][k];
+            const double sk = (d >= 0.0) ? -1.0 : 1.0;
+            const double piv = d - sk;
+            if (lane > k && lane < pw) {
+                const double li = B[lane][k] / piv;
+                B[lane][k] = li;
+#pragma unroll 4
+                for (int c = k + 1; c < pw; ++c)
+                    B[lane][c] -= li * B[k][c];
+            }
+            if (lane == k) {
+                B[k][k] = piv;
+                sg[k] = sk;
+            }
+            wave_sync();
+        }
     }
     __syncthreads();
-    if (!chol64(R3, rrow, pw, 0.0) && t == 0)
-        set_status(w.status, DST_ERANK);
-    // Q_top (row r = t) and X = R2 R1
-    if (t < CB) {
-        const int r = t;
-        double y[CB];
-#pragma unroll
-        for (int c = 0; c < CB; ++c)
-            y[c] = (c < pw && r < pw) ? w.cq_S[c * w.cq_ld + r] : 0.0;
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            double v = y[c];
-#pragma unroll
-            for (int i = 0; i < c; ++i)
-                v -= y[i] * R3[i][c];
-            y[c] = v / R3[c][c];
-        }
-#pragma unroll
-        for (int c = 0; c < CB; ++c)
-            B[r][c] = (r < pw && c < pw) ? y[c] : 0.0;
-    }
-    for (int idx = t; idx < CB * CB; idx += 256) {
+    // Rc = R3 (R2 R1), upper, into registers (X is reused below)
+    double rv[16];
+    for (int idx = t, cnt = 0; idx < CB * CB; idx += 256, ++cnt) {
         const int r = idx / CB, c = idx % CB;
         double v = 0.0;
         for (int p = r; p <= c; ++p)
-            v += R2[r * CB + p] * R1[p * CB + c];
-        X[r][c] = (r <= c) ? v : 0.0;
+            v += R3[r][p] * X[p][c];
+        rv[cnt] = v;
     }
     __syncthreads();
-    // R = S R3 (R2 R1) written after the LU; first the LU of Q_top - S
-    // (s_k = -sign(pivot), sign(0) = +1), two barriers per step
-    for (int k = 0; k < pw; ++k) {
-        const double d = B[k][k];
-        const double s = (d >= 0.0) ? -1.0 : 1.0;
-        const double piv = d - s;
-        const int wdt = pw - k - 1;
-        double nv[16];
-        int cnt = 0;
-        for (int idx = t; idx < wdt * wdt && cnt < 16; idx += 256, ++cnt) {
-            const int i = k + 1 + idx % wdt, c = k + 1 + idx / wdt;
-            nv[cnt] = B[i][c] - (B[i][k] / piv) * B[k][c];
-        }
-        __syncthreads();
-        cnt = 0;
-        for (int idx = t; idx < wdt * wdt && cnt < 16; idx += 256, ++cnt) {
-            const int i = k + 1 + idx % wdt, c = k + 1 + idx / wdt;
-            B[i][c] = nv[cnt];
-        }
-        if (t > k && t < pw)
-            B[t][k] = B[t][k] / piv;
-        if (t == 0) {
-            B[k][k] = piv;
-            sg[k] = s;
-        }
-        __syncthreads();
-    }
-    // Rc = R3 X (upper), kept in R3's place is not possible while R3 is read:
-    // compute into registers, then write R and Y1 to the panel's top block.
-    double rv[16];
+    // X := Y1^-1 (unit lower), lane = row, 16 columns per wave at once
     {
-        int cnt = 0;
-        for (int idx = t; idx < CB * CB; idx += 256, ++cnt) {
-            const int r = idx / CB, c = idx % CB;
-            double v = 0.0;
-            if (r <= c)
-                for (int p = r; p <= c; ++p)
-                    v += R3[r][p] * X[p][c];
-            rv[cnt] = v;
-        }
-    }
-    __syncthreads();
-    // X := Y1^-1 (unit lower), one wave per group of columns, lane = row
-    {
-        const int lane = t & 63, wave = t >> 6;
-        for (int c = wave; c < CB; c += 4) {
-            double x = (lane == c) ? 1.0 : 0.0;
-            for (int k = 0; k < pw; ++k) {
-                const double xk = __shfl(x, k, 64);
-                if (lane > k && lane < pw)
-                    x -= B[lane][k] * xk;
+        double x[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj)
+            x[jj] = (lane == wave + 4 * jj) ? 1.0 : 0.0;
+        for (int k = 0; k < pw; ++k) {
+            const double yk = (lane > k && lane < pw) ? B[lane][k] : 0.0;
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                x[jj] -= yk * readlane_d(x[jj], k);
             }
-            X[lane][c] = (lane < pw && c < pw) ? x : 0.0;
+        }
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            const int c = wave + 4 * jj;
+            X[lane][c] = (lane < pw && c < pw) ? x[jj] : 0.0;
         }
     }
     __syncthreads();
     T *Ap = (sizeof(T) == 8) ? reinterpret_cast<T *>(w.A) : reinterpret_cast<T *>(w.A32);
-    {
-        int cnt = 0;
-        for (int idx = t; idx < CB * CB; idx += 256, ++cnt) {
-            const int r = idx / CB, c = idx % CB;
-            // T = -U S Y1^-T:  T[r][c] = -sum_{p=r..c} U[r][p] s_p (Y1^-1)[c][p]
-            double tv = 0.0;
-            if (r < pw && c < pw && r <= c)
-                for (int p = r; p <= c; ++p)
-                    tv -= B[r][p] * sg[p] * X[c][p];
-            Tout[idx] = tv;
-            if (r < pw && c < pw) {
-                const double out = (r <= c) ? sg[r] * rv[cnt] : B[r][c];
-                Ap[(j0 + c) * w.lda + j0 + r] = (T)out;
-            }
-            if (r == c && r < pw)
-                w.tau[j0 + r] = tv;
-            // U R3 (upper) for the row pass below the top block; identity beyond pw
-            double ur = 0.0;
-            if (r < pw && c < pw) {
-                if (r <= c)
-                    for (int p = r; p <= c; ++p)
-                        ur += B[r][p] * R3[p][c];
-            } else if (r == c) {
-                ur = 1.0;
-            }
-            w.cq_R[3 * CB * CB + idx] = ur;
+    for (int idx = t, cnt = 0; idx < CB * CB; idx += 256, ++cnt) {
+        const int r = idx / CB, c = idx % CB;
+        // T = -U S Y1^-T:  T[r][c] = -sum_{p=r..c} U[r][p] s_p (Y1^-1)[c][p]
+        double tv = 0.0;
+        if (r < pw && c < pw && r <= c)
+            for (int p = r; p <= c; ++p)
+                tv -= B[r][p] * sg[p] * X[c][p];
+        Tout[idx] = tv;
+        if (r < pw && c < pw) {
+            const double out = (r <= c) ? sg[r] * rv[cnt] : B[r][c];
+            Ap[(j0 + c) * w.lda + j0 + r] = (T)out;
         }
+        if (r == c && r < pw)
+            w.tau[j0 + r] = tv;
+        // U R3 (upper) for the row pass below the top block; identity beyond pw
+        double ur = 0.0;
+        if (r < pw && c < pw) {
+            if (r <= c)
+                for (int p = r; p <= c; ++p)
+                    ur += B[r][p] * R3[p][c];
+        } else if (r == c) {
+            ur = 1.0;
+        }
+        w.cq_R[3 * CB * CB + idx] = ur;
     }
 }
 
@@ -344,28 +396,28 @@ static void cqr_panel(const QrWork &w, int64_t j0, int pw, double *Tout, hipStre
     const unsigned nrow = (unsigned)((mk + CQ_ROWS - 1) / CQ_ROWS);
     const double u = 0x1p-53;
     const double shift = 11.0 * ((double)mk * pw + (double)pw * (pw + 1)) * u;
-    double *R1 = w.cq_R, *R2 = w.cq_R + CB * CB, *UR3 = w.cq_R + 3 * CB * CB;
+    double *R1 = w.cq_R, *R2 = w.cq_R + CB * CB, *R21 = w.cq_R + 2 * CB * CB, *UR3 = w.cq_R + 3 * CB * CB;
+    const dim3 gsum_grid(CB * CB / 256, 4);
     // pass 1 (shifted): Gram of P, R1, Q1 = P R1^-1 into the scratch
     hipLaunchKernelGGL(cqr_gram_kernel<T>, dim3(nch), dim3(256), 0, s, (const T *)base, w.lda, mk, pw, chunk,
                        w.cq_part);
-    hipLaunchKernelGGL(cqr_gsum_kernel, dim3(CB * CB / 256), dim3(256), 0, s, (const double *)w.cq_part,
-                       (int64_t)nch, w.cq_G);
-    hipLaunchKernelGGL(cqr_chol_kernel, dim3(1), dim3(64), 0, s, (const double *)w.cq_G, pw, shift, R1, w.status);
+    hipLaunchKernelGGL(cqr_gsum_kernel, gsum_grid, dim3(256), 0, s, (const double *)w.cq_part, (int64_t)nch, w.cq_G);
+    hipLaunchKernelGGL(cqr_chol_kernel, dim3(1), dim3(256), 0, s, (const double *)w.cq_G, pw, shift, R1,
+                       (const double *)nullptr, (double *)nullptr, w.status);
     hipLaunchKernelGGL((cqr_pass_kernel<T, double>), dim3(nrow), dim3(256), 0, s, (const T *)base, w.lda, w.cq_S,
                        w.cq_ld, (int64_t)0, mk, pw, (const double *)R1);
     // pass 2: Q2 = Q1 R2^-1 in place
     hipLaunchKernelGGL(cqr_gram_kernel<double>, dim3(nch), dim3(256), 0, s, (const double *)w.cq_S, w.cq_ld, mk, pw,
                        chunk, w.cq_part);
-    hipLaunchKernelGGL(cqr_gsum_kernel, dim3(CB * CB / 256), dim3(256), 0, s, (const double *)w.cq_part,
-                       (int64_t)nch, w.cq_G);
-    hipLaunchKernelGGL(cqr_chol_kernel, dim3(1), dim3(64), 0, s, (const double *)w.cq_G, pw, 0.0, R2, w.status);
+    hipLaunchKernelGGL(cqr_gsum_kernel, gsum_grid, dim3(256), 0, s, (const double *)w.cq_part, (int64_t)nch, w.cq_G);
+    hipLaunchKernelGGL(cqr_chol_kernel, dim3(1), dim3(256), 0, s, (const double *)w.cq_G, pw, 0.0, R2,
+                       (const double *)R1, R21, w.status);
     hipLaunchKernelGGL((cqr_pass_kernel<double, double>), dim3(nrow), dim3(256), 0, s, (const double *)w.cq_S,
                        w.cq_ld, w.cq_S, w.cq_ld, (int64_t)0, mk, pw, (const double *)R2);
     // pass 3: R3 from the Gram of Q2, the top block's reconstruction, then Y below it
     hipLaunchKernelGGL(cqr_gram_kernel<double>, dim3(nch), dim3(256), 0, s, (const double *)w.cq_S, w.cq_ld, mk, pw,
                        chunk, w.cq_part);
-    hipLaunchKernelGGL(cqr_gsum_kernel, dim3(CB * CB / 256), dim3(256), 0, s, (const double *)w.cq_part,
-                       (int64_t)nch, w.cq_G);
+    hipLaunchKernelGGL(cqr_gsum_kernel, gsum_grid, dim3(256), 0, s, (const double *)w.cq_part, (int64_t)nch, w.cq_G);
     hipLaunchKernelGGL(cqr_top_kernel<T>, dim3(1), dim3(256), 0, s, w, j0, pw, Tout);
     if (mk > pw) {
         const unsigned nb = (unsigned)((mk - pw + CQ_ROWS - 1) / CQ_ROWS);

@@ -466,35 +466,84 @@ __global__ __launch_bounds__(256, 2) void qr_wpart_kernel(QrWork w, int64_t j0, 
 
 // W[p][q] = sum_{s <= p} T[s][p] sum_ch P[ch][s][q] (T upper triangular,
 // row-major with leading dimension tld); 64 columns per workgroup, thread
-// (q, part) handles panel rows p = part, part + 4, ...; chunks summed in order.
+// (q, part) handles panel rows p = part, part + 4, ...  The chunk partials
+// are summed in a fixed order (chunks ch = 0, 2, ... and 1, 3, ... then the
+// two sums); T is staged in LDS as its packed upper triangle.
 template <class TW>
 __global__ __launch_bounds__(256) void qr_wred_kernel(QrWork w, const double *__restrict__ T, int tld, int pw,
                                                       int64_t nch, int64_t nt, TW *__restrict__ Wout)
 {
     __shared__ double Pm[OB][64 + 1];
-    const int ql = threadIdx.x & 63, part = threadIdx.x >> 6;
+    __shared__ double Tt[OB * (OB + 1) / 2];  // column p at p (p + 1) / 2 holds T[0..p][p]
+    const int t = threadIdx.x;
+    const int ql = t & 63, part = t >> 6;
     const int64_t q = (int64_t)blockIdx.x * 64 + ql;
+    {
+        double tv[OB * OB / 256];
+#pragma unroll
+        for (int u = 0; u < OB * OB / 256; ++u) {
+            const int idx = t + 256 * u, r = idx / OB, p = idx % OB;
+            tv[u] = (r <= p && p < pw) ? T[r * tld + p] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < OB * OB / 256; ++u) {
+            const int idx = t + 256 * u, r = idx / OB, p = idx % OB;
+            if (r <= p)
+                Tt[p * (p + 1) / 2 + r] = tv[u];
+        }
+    }
     for (int p = part; p < pw; p += 4) {
-        double s = 0.0;
-        if (q < nt)
-            for (int64_t ch = 0; ch < nch; ++ch)
-                s += w.wpart[(ch * OB + p) * w.ncols + q];
-        Pm[p][ql] = s;
+        double s0 = 0.0, s1 = 0.0;
+        if (q < nt) {
+            const double *src = w.wpart + p * w.ncols + q;
+            const int64_t step = (int64_t)OB * w.ncols;
+            int64_t ch = 0;
+            for (; ch + 1 < nch; ch += 2) {
+                s0 += src[ch * step];
+                s1 += src[(ch + 1) * step];
+            }
+            if (ch < nch)
+                s0 += src[ch * step];
+        }
+        Pm[p][ql] = s0 + s1;
     }
     __syncthreads();
     if (q >= nt)
         return;
     for (int p = part; p < pw; p += 4) {
+        const double *tc = Tt + p * (p + 1) / 2;
         double s = 0.0;
         for (int r = 0; r <= p; ++r)
-            s += T[r * tld + p] * Pm[r][ql];
+            s += tc[r] * Pm[r][ql];
         Wout[p * w.ldw + q] = (TW)s;
     }
 }
 
+// G = Y_A^T Y_B from the chunk partials (grid 16: one entry per thread, rows
+// p < 64 of the partials, columns q < pwb; chunks summed in the same fixed
+// order as qr_wred_kernel).
+__global__ __launch_bounds__(256) void qr_gsum_kernel(QrWork w, int pwb, int64_t nch, double *__restrict__ G)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int p = e / NB, q = e % NB;
+    double s0 = 0.0, s1 = 0.0;
+    if (q < pwb) {
+        const double *src = w.wpart + p * w.ncols + q;
+        const int64_t step = (int64_t)OB * w.ncols;
+        int64_t ch = 0;
+        for (; ch + 1 < nch; ch += 2) {
+            s0 += src[ch * step];
+            s1 += src[(ch + 1) * step];
+        }
+        if (ch < nch)
+            s0 += src[ch * step];
+    }
+    G[e] = s0 + s1;
+}
+
 // Combined compact-WY factor of two consecutive panels A | B:
-// T = [[T_A, -T_A G T_B], [0, T_B]] with G = Y_A^T Y_B (chunk partials summed in order).
-__global__ __launch_bounds__(256) void qr_tcombine_kernel(QrWork w, int pwb, int64_t nch)
+// T = [[T_A, -T_A G T_B], [0, T_B]] with G = Y_A^T Y_B (summed by qr_gsum_kernel).
+__global__ __launch_bounds__(256) void qr_tcombine_kernel(QrWork w, const double *__restrict__ Gs)
 {
     __shared__ double TA[NB][NB + 1];
     __shared__ double TB[NB][NB + 1];
@@ -502,15 +551,21 @@ __global__ __launch_bounds__(256) void qr_tcombine_kernel(QrWork w, int pwb, int
     __shared__ double X[NB][NB + 1];
     const int t = threadIdx.x;
     const double *Ta = w.Tin, *Tb = w.Tin + NB * NB;
-    for (int idx = t; idx < NB * NB; idx += 256) {
-        const int r = idx / NB, c = idx % NB;
-        TA[r][c] = Ta[idx];
-        TB[r][c] = Tb[idx];
-        double g = 0.0;
-        if (c < pwb)
-            for (int64_t ch = 0; ch < nch; ++ch)
-                g += w.wpart[(ch * OB + r) * w.ncols + c];
-        G[r][c] = g;
+    {
+        double a[16], b[16], g[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            a[u] = Ta[t + 256 * u];
+            b[u] = Tb[t + 256 * u];
+            g[u] = Gs[t + 256 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = t + 256 * u, r = idx / NB, c = idx % NB;
+            TA[r][c] = a[u];
+            TB[r][c] = b[u];
+            G[r][c] = g[u];
+        }
     }
     __syncthreads();
     for (int idx = t; idx < NB * NB; idx += 256) {  // X = G T_B
@@ -828,7 +883,8 @@ static void geqrf(const QrWork &w, hipStream_t s)
             int64_t chunk, nch;
             chunking(rows, 1, chunk, nch);
             launch_wpart<T>(w, J, pwa, jb, (int64_t)pwb, 1, jb, chunk, 1, nch, s);
-            hipLaunchKernelGGL(qr_tcombine_kernel, dim3(1), dim3(256), 0, s, w, pwb, nch);
+            hipLaunchKernelGGL(qr_gsum_kernel, dim3(NB * NB / 256), dim3(256), 0, s, w, pwb, nch, w.cq_G);
+            hipLaunchKernelGGL(qr_tcombine_kernel, dim3(1), dim3(256), 0, s, w, (const double *)w.cq_G);
         }
         const int64_t c0 = jb + pwb;
         apply_block<T>(w, J, pwa + pwb, w.T, OB, c0, w.ncols - c0, s);

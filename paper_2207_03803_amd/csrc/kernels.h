@@ -90,8 +90,8 @@ struct QrWork {
     double *cq_S;       // CholeskyQR: FP64 scratch panel [QR_NB x cq_ld] (column-major)
     int64_t cq_ld;      // >= m
     double *cq_part;    // [CQ_MAX_CHUNKS * QR_NB * QR_NB] partial Gram matrices
-    double *cq_G;       // [QR_NB * QR_NB] Gram matrix
-    double *cq_R;       // [4 * QR_NB * QR_NB] R1, R2, (unused), U R3 (row-major)
+    double *cq_G;       // [4 * QR_NB * QR_NB] four partial sums of the Gram matrix
+    double *cq_R;       // [4 * QR_NB * QR_NB] R1, R2, R2 R1, U R3 (row-major)
     int32_t *status;
 };
 constexpr int64_t CQ_MAX_CHUNKS = 256;

@@ -99,8 +99,17 @@ __global__ __launch_bounds__(256) void trsv_fused_kernel(const TR *__restrict__ 
         const int64_t b0 = i * TB;
         const int bw = (int)((n - b0) < TB ? (n - b0) : TB);
         // stage the diagonal block (independent of x): D[c][l] = R[b0+l][b0+c]
-        for (int c = grp; c < TB; c += 4)
-            D[c][lane] = (c < bw && lane < bw) ? (double)R[(b0 + c) * ld + b0 + lane] : 0.0;
+        {
+            double dv[TB / 4];
+#pragma unroll
+            for (int e = 0; e < TB / 4; ++e) {
+                const int c = grp + 4 * e;
+                dv[e] = (c < bw && lane < bw) ? (double)R[(b0 + c) * ld + b0 + lane] : 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < TB / 4; ++e)
+                D[grp + 4 * e][lane] = dv[e];
+        }
         // products with the blocks of every earlier block row
         double acc[16];
 #pragma unroll
