@@ -447,7 +447,7 @@ __global__ __launch_bounds__(256, 2) void qr_wpart_kernel(QrWork w, int64_t j0, 
             }
         }
     };
-    gemm_tile_runs<WS, true, true>(acc, lds, rhi - rlo, fa, fb);
+    gemm_tile_runs<WS, true, true, true>(acc, lds, rhi - rlo, fa, fb);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WS::WN, wn = wave % WS::WN;
     double *P = w.wpart + ch * OB * w.ncols;
@@ -634,7 +634,7 @@ __global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0,
                 v[e] = ypanel(A, lda, m, j0, pw, r + e, (int)p);
         }
     };
-    gemm_tile_runs<US, false, false>(acc, lds, pw, fa, fb);
+    gemm_tile_runs<US, false, false, true>(acc, lds, pw, fa, fb);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / US::WN, wn = wave % US::WN;
     double *C = w.A + c0 * lda;
