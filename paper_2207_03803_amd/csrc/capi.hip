@@ -22,7 +22,7 @@ struct Layout {
     size_t off_A = 0, off_tau = 0, off_wpart = 0, off_T = 0, off_Tin = 0, off_U = 0, off_W = 0, off_ts_tiles = 0,
            off_ts_X = 0, off_ts_tau = 0, off_rhs = 0, off_misc = 0, off_tiles = 0, off_counters = 0,
            off_status = 0, off_tflags = 0, n_tflags = 0, off_cq_S = 0, off_cq_part = 0, off_cq_G = 0, off_cq_R = 0,
-           total = 0;
+           off_T2 = 0, off_wpart_s = 0, off_W_s = 0, off_W32_s = 0, total = 0;
     // mixed precision only
     bool mixed = false;
     size_t off_A32 = 0, off_W32 = 0, off_r = 0, off_s = 0, off_z = 0, off_dc = 0, off_part = 0,
@@ -70,6 +70,10 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, bool mixed)
     L.off_cq_part = take(sizeof(double) * (size_t)CQ_MAX_CHUNKS * QR_NB * QR_NB);
     L.off_cq_G = take(sizeof(double) * 4 * QR_NB * QR_NB);
     L.off_cq_R = take(sizeof(double) * 4 * QR_NB * QR_NB);
+    L.off_T2 = take(sizeof(double) * 4 * QR_NB * QR_NB);
+    L.off_wpart_s = take(sizeof(double) * (size_t)qr_max_chunks() * 2 * QR_NB * 2 * QR_NB);
+    L.off_W_s = take(sizeof(double) * 4 * QR_NB * QR_NB);
+    L.off_W32_s = take(sizeof(float) * 4 * QR_NB * QR_NB);
     if (mixed) {
         const int64_t ldw = (L.ncols + 63) / 64 * 64;
         L.off_A32 = take(sizeof(float) * (size_t)L.lda * (size_t)L.ncols);
@@ -102,6 +106,7 @@ struct gap_handle_s {
     int64_t model_M = 0;      // set by gap_set_model
     bool model_only = false;  // predict-only handle (no workspace)
     hipEvent_t ev[2 * N_STAGES] = {};
+    QrAsync la = {};   // side stream and events of the QR look-ahead
     bool timed[N_STAGES] = {};
     bool timing = false;
     gap_tuning tuning = {};
@@ -191,6 +196,21 @@ size_t gap_workspace_bytes(const gap_params *p, int64_t n_configs, int64_t n_ato
     return make_layout(n_configs, n_atoms, M, p->precision == GAP_MIXED_FP32).total;
 }
 
+// Release a handle's events and side stream (those created so far) and the handle.
+static void destroy_handle(gap_handle h)
+{
+    for (int i = 0; i < 2 * N_STAGES; ++i)
+        if (h->ev[i])
+            (void)hipEventDestroy(h->ev[i]);
+    hipEvent_t lev[5] = {h->la.fork, h->la.t_ready, h->la.bulk[0], h->la.bulk[1], h->la.join};
+    for (hipEvent_t e : lev)
+        if (e)
+            (void)hipEventDestroy(e);
+    if (h->la.side)
+        (void)hipStreamDestroy(h->la.side);
+    delete h;
+}
+
 gap_status gap_create(const gap_params *p, void *stream, gap_handle *out)
 {
     if (!out || !valid_params(p))
@@ -209,10 +229,22 @@ gap_status gap_create(const gap_params *p, void *stream, gap_handle *out)
     if (h->timing) {
         for (int i = 0; i < 2 * N_STAGES; ++i)
             if (hipEventCreate(&h->ev[i]) != hipSuccess) {
-                delete h;
+                destroy_handle(h);
                 return GAP_EDEVICE;
             }
     }
+    hipEvent_t *lev[5] = {&h->la.fork, &h->la.t_ready, &h->la.bulk[0], &h->la.bulk[1], &h->la.join};
+    if (hipStreamCreateWithFlags(&h->la.side, hipStreamNonBlocking) != hipSuccess) {
+        h->la.side = nullptr;
+        destroy_handle(h);
+        return GAP_EDEVICE;
+    }
+    for (hipEvent_t *e : lev)
+        if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
+            *e = nullptr;
+            destroy_handle(h);
+            return GAP_EDEVICE;
+        }
     *out = h;
     return GAP_OK;
 }
@@ -352,6 +384,11 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
     w.n = L.M;
     w.ncols = L.ncols;
     w.ldw = (L.ncols + 63) / 64 * 64;
+    w.wp_ld = L.ncols;
+    w.T2 = h->at<double>(L.off_T2);
+    w.wpart_s = h->at<double>(L.off_wpart_s);
+    w.W_s = h->at<double>(L.off_W_s);
+    w.W32_s = h->at<float>(L.off_W32_s);
     w.tau = h->at<double>(L.off_tau);
     w.wpart = h->at<double>(L.off_wpart);
     w.T = h->at<double>(L.off_T);
@@ -374,7 +411,7 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
     double *rhs = h->at<double>(L.off_rhs);
     if (!L.mixed) {
         h->mark(4, false);
-        GAP_TRY(dev(launch_geqrf(w, s)));
+        GAP_TRY(dev(launch_geqrf(w, s, h->tuning.qr_lookahead_off ? nullptr : &h->la)));
         h->mark(4, true);
         const double *qtb = A + L.M * L.lda;
         h->mark(5, false);
@@ -390,7 +427,7 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
         w.W32 = h->at<float>(L.off_W32);
         h->mark(4, false);
         GAP_TRY(dev(launch_convert_f64_f32(A, A32, L.lda * L.ncols, s)));
-        GAP_TRY(dev(launch_geqrf(w, s)));
+        GAP_TRY(dev(launch_geqrf(w, s, h->tuning.qr_lookahead_off ? nullptr : &h->la)));
         h->mark(4, true);
         h->mark(5, false);
         GAP_TRY(dev(launch_copy_f32_f64(A32 + L.M * L.lda, rhs, L.M, s)));
@@ -501,6 +538,8 @@ gap_status gap_set_tuning(gap_handle h, const gap_tuning *t)
         return GAP_EINVAL;
     if (t->qr_panel != 0 && t->qr_panel != 1)
         return GAP_EINVAL;
+    if (t->qr_lookahead_off != 0 && t->qr_lookahead_off != 1)
+        return GAP_EINVAL;
     h->tuning = *t;
     return GAP_OK;
 }
@@ -509,11 +548,7 @@ gap_status gap_destroy(gap_handle h)
 {
     if (!h)
         return GAP_EINVAL;
-    if (h->timing)
-        for (int i = 0; i < 2 * N_STAGES; ++i)
-            if (h->ev[i])
-                (void)hipEventDestroy(h->ev[i]);
-    delete h;
+    destroy_handle(h);
     return GAP_OK;
 }
 

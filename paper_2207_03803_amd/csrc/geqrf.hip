@@ -450,7 +450,7 @@ __global__ __launch_bounds__(256, 2) void qr_wpart_kernel(QrWork w, int64_t j0, 
     gemm_tile_runs<WS, true, true, true>(acc, lds, rhi - rlo, fa, fb);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WS::WN, wn = wave % WS::WN;
-    double *P = w.wpart + ch * OB * w.ncols;
+    double *P = w.wpart + ch * OB * w.wp_ld;
 #pragma unroll
     for (int i = 0; i < WS::FM; ++i)
 #pragma unroll
@@ -460,7 +460,7 @@ __global__ __launch_bounds__(256, 2) void qr_wpart_kernel(QrWork w, int64_t j0, 
                 const int p = acc_row<WS>(wm, i, lane, e);
                 const int64_t q = q0 + acc_col<WS>(wn, jj, lane, e);
                 if (p < pw && q < nt)
-                    P[p * w.ncols + q] = acc[i][jj][e];
+                    P[p * w.wp_ld + q] = acc[i][jj][e];
             }
 }
 
@@ -495,8 +495,8 @@ __global__ __launch_bounds__(256) void qr_wred_kernel(QrWork w, const double *__
     for (int p = part; p < pw; p += 4) {
         double s0 = 0.0, s1 = 0.0;
         if (q < nt) {
-            const double *src = w.wpart + p * w.ncols + q;
-            const int64_t step = (int64_t)OB * w.ncols;
+            const double *src = w.wpart + p * w.wp_ld + q;
+            const int64_t step = (int64_t)OB * w.wp_ld;
             int64_t ch = 0;
             for (; ch + 1 < nch; ch += 2) {
                 s0 += src[ch * step];
@@ -528,8 +528,8 @@ __global__ __launch_bounds__(256) void qr_gsum_kernel(QrWork w, int pwb, int64_t
     const int p = e / NB, q = e % NB;
     double s0 = 0.0, s1 = 0.0;
     if (q < pwb) {
-        const double *src = w.wpart + p * w.ncols + q;
-        const int64_t step = (int64_t)OB * w.ncols;
+        const double *src = w.wpart + p * w.wp_ld + q;
+        const int64_t step = (int64_t)OB * w.wp_ld;
         int64_t ch = 0;
         for (; ch + 1 < nch; ch += 2) {
             s0 += src[ch * step];
@@ -543,7 +543,8 @@ __global__ __launch_bounds__(256) void qr_gsum_kernel(QrWork w, int pwb, int64_t
 
 // Combined compact-WY factor of two consecutive panels A | B:
 // T = [[T_A, -T_A G T_B], [0, T_B]] with G = Y_A^T Y_B (summed by qr_gsum_kernel).
-__global__ __launch_bounds__(256) void qr_tcombine_kernel(QrWork w, const double *__restrict__ Gs)
+__global__ __launch_bounds__(256) void qr_tcombine_kernel(QrWork w, const double *__restrict__ Gs,
+                                                         double *__restrict__ Tout)
 {
     __shared__ double TA[NB][NB + 1];
     __shared__ double TB[NB][NB + 1];
@@ -588,7 +589,7 @@ __global__ __launch_bounds__(256) void qr_tcombine_kernel(QrWork w, const double
             for (int k = r; k < NB; ++k)
                 v -= TA[r][k] * X[k][cc];
         }
-        w.T[idx] = v;
+        Tout[idx] = v;
     }
 }
 
@@ -711,7 +712,7 @@ __global__ __launch_bounds__(256, 2) void qr_wpart32_kernel(QrWork w, int64_t j0
     gemm_tile_runs32<WS32, true, true>(acc, lds, rhi - rlo, fa, fb);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WS32::WN, wn = wave % WS32::WN;
-    double *P = w.wpart + ch * OB * w.ncols;
+    double *P = w.wpart + ch * OB * w.wp_ld;
 #pragma unroll
     for (int i = 0; i < WS32::FM; ++i)
 #pragma unroll
@@ -721,7 +722,7 @@ __global__ __launch_bounds__(256, 2) void qr_wpart32_kernel(QrWork w, int64_t j0
                 const int p = acc32_row<WS32>(wm, i, lane, e);
                 const int64_t q = q0 + acc32_col<WS32>(wn, jj, lane, e);
                 if (p < pw && q < nt)
-                    P[p * w.ncols + q] = (double)acc[i][jj][e];
+                    P[p * w.wp_ld + q] = (double)acc[i][jj][e];
             }
 }
 
@@ -861,42 +862,89 @@ static void apply_block(const QrWork &w, int64_t j0, int pw, const double *Tm, i
     }
 }
 
+// Factor the block of up to two panels at column J (main-stream scratch in w):
+// panel A, its update of panel B, panel B, and the combined compact-WY T into
+// Tout (row-major, ld OB).  Returns the block's width; *Tm / *tld describe its T.
 template <class T>
-static void geqrf(const QrWork &w, hipStream_t s)
+static int factor_block(const QrWork &w, int64_t J, double *Tout, const double **Tm, int *tld, hipStream_t s)
 {
     double *Ta = w.Tin, *Tb = w.Tin + NB * NB;
-    for (int64_t J = 0; J < w.n; J += OB) {
-        const int pwa = (int)((w.n - J) < NB ? (w.n - J) : NB);
-        factor_panel<T>(w, J, pwa, Ta, s);
-        const int64_t jb = J + pwa;
-        const int pwb = (int)((w.n - jb) < NB ? (w.n - jb) : NB);
-        if (pwb <= 0) {
-            apply_block<T>(w, J, pwa, Ta, NB, jb, w.ncols - jb, s);
-            continue;
-        }
-        // bring panel B up to date with panel A, factor it, then merge the two
-        // compact-WY factors and update everything to the right at once
-        apply_block<T>(w, J, pwa, Ta, NB, jb, pwb, s);
-        factor_panel<T>(w, jb, pwb, Tb, s);
-        {
-            const int64_t rows = w.m - jb;
-            int64_t chunk, nch;
-            chunking(rows, 1, chunk, nch);
-            launch_wpart<T>(w, J, pwa, jb, (int64_t)pwb, 1, jb, chunk, 1, nch, s);
-            hipLaunchKernelGGL(qr_gsum_kernel, dim3(NB * NB / 256), dim3(256), 0, s, w, pwb, nch, w.cq_G);
-            hipLaunchKernelGGL(qr_tcombine_kernel, dim3(1), dim3(256), 0, s, w, (const double *)w.cq_G);
-        }
-        const int64_t c0 = jb + pwb;
-        apply_block<T>(w, J, pwa + pwb, w.T, OB, c0, w.ncols - c0, s);
+    const int pwa = (int)((w.n - J) < NB ? (w.n - J) : NB);
+    factor_panel<T>(w, J, pwa, Ta, s);
+    const int64_t jb = J + pwa;
+    const int pwb = (int)((w.n - jb) < NB ? (w.n - jb) : NB);
+    if (pwb <= 0) {
+        *Tm = Ta;
+        *tld = NB;
+        return pwa;
     }
+    apply_block<T>(w, J, pwa, Ta, NB, jb, pwb, s);
+    factor_panel<T>(w, jb, pwb, Tb, s);
+    const int64_t rows = w.m - jb;
+    int64_t chunk, nch;
+    chunking(rows, 1, chunk, nch);
+    launch_wpart<T>(w, J, pwa, jb, (int64_t)pwb, 1, jb, chunk, 1, nch, s);
+    hipLaunchKernelGGL(qr_gsum_kernel, dim3(NB * NB / 256), dim3(256), 0, s, w, pwb, nch, w.cq_G);
+    hipLaunchKernelGGL(qr_tcombine_kernel, dim3(1), dim3(256), 0, s, w, (const double *)w.cq_G, Tout);
+    *Tm = Tout;
+    *tld = OB;
+    return pwa + pwb;
 }
 
-hipError_t launch_geqrf(const QrWork &w, hipStream_t s)
+template <class T>
+static void geqrf(const QrWork &w, hipStream_t s, const QrAsync *la)
+{
+    if (!la) {
+        for (int64_t J = 0; J < w.n; J += OB) {
+            const double *Tm;
+            int tld;
+            const int pw = factor_block<T>(w, J, w.T, &Tm, &tld, s);
+            apply_block<T>(w, J, pw, Tm, tld, J + pw, w.ncols - (J + pw), s);
+        }
+        return;
+    }
+    // main-stream view: small scratch for the next block's update and the panels
+    QrWork wm = w;
+    wm.wpart = w.wpart_s;
+    wm.wp_ld = OB;
+    wm.W = w.W_s;
+    wm.W32 = w.W32_s;
+    wm.ldw = OB;
+    double *Tbuf[2] = {w.T, w.T2};
+    (void)hipEventRecord(la->fork, s);
+    (void)hipStreamWaitEvent(la->side, la->fork, 0);
+    const double *Tm;
+    int tld;
+    int pw = factor_block<T>(wm, 0, Tbuf[0], &Tm, &tld, s);
+    (void)hipEventRecord(la->t_ready, s);
+    int64_t k = 0;
+    for (int64_t J = 0; J < w.n; J += pw, ++k) {
+        pw = (int)((w.n - J) < OB ? (w.n - J) : OB);
+        const int64_t cn = J + pw;                              // first column of block k+1
+        const int64_t nn = (w.n - cn) < OB ? (w.n - cn) : OB;   // its width (0 after the last block)
+        // side: block k's update of everything right of block k+1 (b included)
+        (void)hipStreamWaitEvent(la->side, la->t_ready, 0);
+        apply_block<T>(w, J, pw, Tm, tld, cn + nn, w.ncols - (cn + nn), la->side);
+        (void)hipEventRecord(la->bulk[k & 1], la->side);
+        if (nn <= 0)
+            break;
+        // main: block k+1's columns need every earlier block's update first
+        if (k > 0)
+            (void)hipStreamWaitEvent(s, la->bulk[(k - 1) & 1], 0);
+        apply_block<T>(wm, J, pw, Tm, tld, cn, nn, s);
+        factor_block<T>(wm, cn, Tbuf[(k + 1) & 1], &Tm, &tld, s);
+        (void)hipEventRecord(la->t_ready, s);
+    }
+    (void)hipEventRecord(la->join, la->side);
+    (void)hipStreamWaitEvent(s, la->join, 0);
+}
+
+hipError_t launch_geqrf(const QrWork &w, hipStream_t s, const QrAsync *la)
 {
     if (w.A32)
-        geqrf<float>(w, s);
+        geqrf<float>(w, s, la);
     else
-        geqrf<double>(w, s);
+        geqrf<double>(w, s, la);
     return hipGetLastError();
 }
 

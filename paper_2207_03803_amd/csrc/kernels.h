@@ -74,8 +74,13 @@ struct QrWork {
     int64_t lda, m, n, ncols;
     int64_t ldw;      // leading dimension of W (ncols rounded up to 64)
     double *tau;      // [n]
-    double *wpart;    // [max_chunks * 2 QR_NB * ncols] split-K partials of Y^T C
+    double *wpart;    // [max_chunks * 2 QR_NB * wp_ld] split-K partials of Y^T C
+    int64_t wp_ld;    // row stride of the partials (>= the widest column range updated)
     double *T;        // [2 QR_NB * 2 QR_NB] compact-WY T of the current two-panel block (row-major)
+    double *T2;       // second T buffer (look-ahead: the side stream reads one while the next is formed)
+    double *wpart_s;  // [max_chunks * 2 QR_NB * 2 QR_NB] partials of the main stream's small updates
+    double *W_s;      // [2 QR_NB * 2 QR_NB] W of the main stream's small updates (ld 2 QR_NB)
+    float *W32_s;     // FP32 version
     double *Tin;      // [2 * QR_NB * QR_NB] T of the block's two panels (row-major, ld QR_NB)
     double *U;        // [QR_NB * QR_NB] LU factor of (Q - S) of the current panel
     double *W;        // [2 QR_NB * ldw] T^T Y^T C, row-major by block column
@@ -99,7 +104,13 @@ constexpr int64_t CQ_MAX_CHUNKS = 256;
 void cqr_panel_f64(const QrWork &w, int64_t j0, int pw, double *Tout, hipStream_t s);
 void cqr_panel_f32(const QrWork &w, int64_t j0, int pw, double *Tout, hipStream_t s);
 int64_t qr_max_chunks();
-hipError_t launch_geqrf(const QrWork &w, hipStream_t s);
+// Look-ahead schedule: the trailing update of block k runs on `side` while
+// `s` updates block k+1's columns and factors them.  Null: one stream.
+struct QrAsync {
+    hipStream_t side;
+    hipEvent_t fork, t_ready, bulk[2], join;
+};
+hipError_t launch_geqrf(const QrWork &w, hipStream_t s, const QrAsync *la);
 
 // -------------------------------------------------------- triangular solve
 // Flags of the one-launch blocked substitution: sync.flags holds
