@@ -22,7 +22,7 @@ struct Layout {
     size_t off_A = 0, off_tau = 0, off_wpart = 0, off_T = 0, off_Tin = 0, off_U = 0, off_W = 0, off_ts_tiles = 0,
            off_ts_X = 0, off_ts_tau = 0, off_rhs = 0, off_misc = 0, off_tiles = 0, off_counters = 0,
            off_status = 0, off_tflags = 0, n_tflags = 0, off_cq_S = 0, off_cq_part = 0, off_cq_G = 0, off_cq_R = 0,
-           off_T2 = 0, off_wpart_s = 0, off_W_s = 0, off_W32_s = 0, total = 0;
+           off_T2 = 0, off_wpart_s = 0, off_W_s = 0, off_W32_s = 0, off_plan = 0, total = 0;
     // mixed precision only
     bool mixed = false;
     size_t off_A32 = 0, off_W32 = 0, off_r = 0, off_s = 0, off_z = 0, off_dc = 0, off_part = 0,
@@ -62,6 +62,7 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, bool mixed)
     L.off_rhs = take(sizeof(double) * (size_t)M);
     L.off_misc = take(sizeof(double) * 512);
     L.off_tiles = take(sizeof(int32_t) * (size_t)(L.max_tiles + 2));
+    L.off_plan = take(sizeof(int32_t) * (size_t)(N + knm_plan_chunks(N) * (2049 + 1)));
     L.off_counters = take(sizeof(unsigned) * 16);
     L.off_status = take(sizeof(int32_t) * 4);
     L.n_tflags = trsv_sync_ints(M);
@@ -284,14 +285,21 @@ gap_status gap_build_knm(gap_handle h, const double *x_atoms, int64_t n_atoms, c
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned *>(h->status()), 4);
     hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(256), 0, s, h->at<int32_t>(L.off_tflags), L.n_tflags);
     int32_t *tiles = h->at<int32_t>(L.off_tiles);
-    GAP_TRY(dev(launch_plan_tiles(config_offsets, n_configs, n_atoms, tiles, tiles + L.max_tiles + 1,
-                                  L.max_tiles, h->status(), s)));
+    int32_t *plan = h->at<int32_t>(L.off_plan);
+    KnmPlan kp;
+    kp.tile_start = tiles;
+    kp.n_tiles = tiles + L.max_tiles + 1;
+    kp.cfg_list = plan;
+    kp.lstart = plan + n_configs;
+    kp.lcount = kp.lstart + knm_plan_chunks(n_configs) * 2049;
+    GAP_TRY(dev(launch_plan_tiles(config_offsets, n_configs, n_atoms, kp, L.max_tiles, h->status(), s)));
 
     KnmArgs a{};
     a.X = x_atoms;
     a.offsets = config_offsets;
-    a.tile_cfg = tiles;
-    a.n_tiles_dev = tiles + L.max_tiles + 1;
+    a.tile_start = kp.tile_start;
+    a.cfg_list = kp.cfg_list;
+    a.n_tiles_dev = kp.n_tiles;
     a.XM = x_sparse;
     a.M = M;
     a.d = p.d;

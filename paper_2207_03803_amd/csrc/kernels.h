@@ -15,7 +15,8 @@ constexpr int KNM_MAX_SEG = 256;  // configurations per tile
 struct KnmArgs {
     const double *X;           // [rows x d] row-major descriptors
     const int64_t *offsets;    // [N+1] CSR offsets; nullptr = unit segments (row r is segment r)
-    const int32_t *tile_cfg;   // [n_tiles+1] first configuration of each tile (from the plan)
+    const int32_t *tile_start; // [n_tiles+1] first position of each tile in cfg_list (from the plan)
+    const int32_t *cfg_list;   // [N] configurations, tile by tile
     const int32_t *n_tiles_dev;
     int64_t n_rows_unit;       // unit segments: number of rows
     const double *XM;          // [M x d] sparse points
@@ -32,8 +33,14 @@ struct KnmArgs {
 };
 
 int64_t knm_max_tiles(int64_t N, int64_t n_atoms);
-hipError_t launch_plan_tiles(const int64_t *offsets, int64_t N, int64_t n_atoms, int32_t *tile_cfg,
-                             int32_t *n_tiles, int64_t max_tiles, int32_t *status, hipStream_t s);
+int64_t knm_plan_chunks(int64_t N);
+// Plan arrays (device): tile_start [max_tiles + 1], n_tiles [1], cfg_list [N],
+// lstart [n_chunks * 2049], lcount [n_chunks] (n_chunks = knm_plan_chunks(N)).
+struct KnmPlan {
+    int32_t *tile_start, *n_tiles, *cfg_list, *lstart, *lcount;
+};
+hipError_t launch_plan_tiles(const int64_t *offsets, int64_t N, int64_t n_atoms, const KnmPlan &p, int64_t max_tiles,
+                             int32_t *status, hipStream_t s);
 hipError_t launch_knm(KnmArgs a, int64_t max_tiles, hipStream_t s);
 
 // --------------------------------------------------------------------- predict

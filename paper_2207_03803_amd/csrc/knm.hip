@@ -8,83 +8,166 @@
 namespace gap {
 
 // ---------------------------------------------------------------------------
-// Tile plan: pack whole configurations, in order, into tiles of at most
-// KNM_CAP atoms and KNM_MAX_SEG configurations (greedy).  A configuration with
-// more than KNM_CAP atoms gets a tile of its own, processed in several atom
-// chunks.  Also validates the offsets.  The plan is a sequential scan of the
-// n_configs + 1 offsets by one thread; the workgroup stages them through LDS.
+// Tile plan.  The rows of K_NM are independent per configuration, so a tile
+// may hold any set of whole configurations.  The configurations are split, in
+// order, into chunks of PLAN_C; each chunk is sorted by atom count (largest
+// first, then by index) and packed by one thread: a configuration of more than
+// KNM_CAP atoms gets a tile of its own (processed in atom chunks); the others
+// fill tiles of at most KNM_CAP atoms and KNM_MAX_SEG configurations, each
+// tile taking the largest remaining configuration that still fits until none
+// does.  Output: cfg_list (the configurations, tile by tile) and tile_start[t]
+// (the first position of tile t in cfg_list).  The offsets are validated too.
 // ---------------------------------------------------------------------------
-constexpr int PLAN_SEG = 4096;  // offsets staged in LDS per step of the scan
+constexpr int PLAN_C = 2048;               // configurations per chunk
+constexpr int PLAN_LARGE = KNM_CAP + 1;    // bucket of the configurations above KNM_CAP atoms
+constexpr int PLAN_WORDS = (PLAN_LARGE + 64) / 64;
 
-__global__ __launch_bounds__(256) void plan_tiles_kernel(const int64_t *__restrict__ offsets, int64_t N,
-                                                         int64_t n_atoms, int32_t *__restrict__ tile_cfg,
-                                                         int32_t *__restrict__ n_tiles, int64_t max_tiles,
+int64_t knm_plan_chunks(int64_t N) { return (N + PLAN_C - 1) / PLAN_C; }
+
+__global__ __launch_bounds__(256) void plan_chunk_kernel(const int64_t *__restrict__ offsets, int64_t N,
+                                                         int64_t n_atoms, int32_t *__restrict__ cfg_list,
+                                                         int32_t *__restrict__ lstart, int32_t *__restrict__ lcount,
                                                          int32_t *status)
 {
-    __shared__ int64_t seg[PLAN_SEG + 1];
+    __shared__ int64_t key[PLAN_C];
+    __shared__ int32_t bfirst[PLAN_LARGE + 1], blast[PLAN_LARGE + 1];
     __shared__ int bad_s;
-    // scan state, owned by thread 0
-    int64_t t = 0, tile_atoms = 0, tile_n = 0, prev = 0;
-    bool bad = false;
-    if (threadIdx.x == 0) {
+    const int t = threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.x * PLAN_C;
+    const int cnt = (int)((N - c0) < PLAN_C ? (N - c0) : PLAN_C);
+    if (t == 0) {
         bad_s = 0;
-        tile_cfg[0] = 0;
+        if (blockIdx.x == 0 && offsets[0] != 0)
+            bad_s = 1;
+        if (c0 + cnt == N && offsets[N] != n_atoms)
+            bad_s = 1;
     }
-    for (int64_t base = 0; base < N; base += PLAN_SEG) {
-        const int64_t cnt = (N - base) < PLAN_SEG ? (N - base) : PLAN_SEG;
-        __syncthreads();
-        for (int64_t i = threadIdx.x; i <= cnt; i += 256)
-            seg[i] = offsets[base + i];
-        __syncthreads();
-        if (threadIdx.x == 0 && !bad) {
-            if (base == 0) {
-                prev = seg[0];
-                bad = (prev != 0);
-            }
-            for (int64_t i = 0; i < cnt && !bad; ++i) {
-                const int64_t nx = seg[i + 1];
-                const int64_t na = nx - prev;
-                if (na < 0) {
-                    bad = true;
-                    break;
-                }
-                if (tile_n > 0 && (tile_atoms + na > KNM_CAP || tile_n == KNM_MAX_SEG)) {
-                    if (++t >= max_tiles) {
-                        bad = true;
-                        break;
-                    }
-                    tile_cfg[t] = (int32_t)(base + i);
-                    tile_atoms = 0;
-                    tile_n = 0;
-                }
-                tile_atoms += na;
-                ++tile_n;
-                prev = nx;
-            }
-            bad_s = bad ? 1 : 0;
+    for (int b = t; b <= PLAN_LARGE; b += 256)
+        bfirst[b] = blast[b] = 0;
+    __syncthreads();
+    // key = (PLAN_LARGE - bucket) << 32 | local index: ascending = largest first
+    for (int i = t; i < PLAN_C; i += 256) {
+        int64_t k = INT64_MAX;
+        if (i < cnt) {
+            const int64_t sz = offsets[c0 + i + 1] - offsets[c0 + i];
+            if (sz < 0)
+                bad_s = 1;
+            const int64_t b = sz > KNM_CAP ? PLAN_LARGE : (sz < 0 ? 0 : sz);
+            k = ((int64_t)(PLAN_LARGE - b) << 32) | i;
         }
-        __syncthreads();
-        if (bad_s)
-            break;
+        key[i] = k;
     }
-    if (threadIdx.x != 0)
+    __syncthreads();
+    for (int kk = 2; kk <= PLAN_C; kk <<= 1)
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            for (int i = t; i < PLAN_C; i += 256) {
+                const int l = i ^ jj;
+                if (l > i) {
+                    const int64_t x = key[i], y = key[l];
+                    if ((x > y) == ((i & kk) == 0)) {
+                        key[i] = y;
+                        key[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    // bucket b occupies sorted positions [bfirst[b], blast[b])
+    for (int i = t; i < cnt; i += 256) {
+        const int b = PLAN_LARGE - (int)(key[i] >> 32);
+        if (i == 0 || (key[i - 1] >> 32) != (key[i] >> 32))
+            bfirst[b] = i;
+        if (i == cnt - 1 || (key[i + 1] >> 32) != (key[i] >> 32))
+            blast[b] = i + 1;
+    }
+    __syncthreads();
+    if (t != 0)
         return;
-    if (prev != n_atoms)
-        bad = true;
-    if (bad) {
-        *n_tiles = 0;
+    int32_t *ls = lstart + blockIdx.x * (int64_t)(PLAN_C + 1);
+    if (bad_s) {
         set_status(status, DST_EINVAL);
+        lcount[blockIdx.x] = 0;
         return;
     }
-    tile_cfg[t + 1] = (int32_t)N;
-    *n_tiles = (int32_t)(t + 1);
+    int pos = 0, ntile = 0;
+    for (int i = bfirst[PLAN_LARGE]; i < blast[PLAN_LARGE]; ++i) {  // one tile each
+        ls[ntile++] = pos;
+        cfg_list[c0 + pos++] = (int32_t)(c0 + (key[i] & 0xffffffff));
+    }
+    // non-empty buckets 0..KNM_CAP as a bit set; bfirst[] is each bucket's next item
+    uint64_t nonempty[PLAN_WORDS];
+    for (int w = 0; w < PLAN_WORDS; ++w)
+        nonempty[w] = 0;
+    for (int b = 0; b <= KNM_CAP; ++b)
+        if (bfirst[b] < blast[b])
+            nonempty[b >> 6] |= 1ull << (b & 63);
+    while (pos < cnt) {
+        ls[ntile++] = pos;
+        int r = KNM_CAP, nseg = 0;
+        while (nseg < KNM_MAX_SEG) {
+            // largest non-empty bucket b <= r
+            int found = -1;
+            for (int w = r >> 6; w >= 0 && found < 0; --w) {
+                uint64_t m = nonempty[w];
+                if (w == (r >> 6))
+                    m &= ((r & 63) == 63) ? ~0ull : ((1ull << ((r & 63) + 1)) - 1);
+                if (m)
+                    found = w * 64 + 63 - __clzll(m);
+            }
+            if (found < 0)
+                break;
+            const int i = bfirst[found]++;
+            if (bfirst[found] == blast[found])
+                nonempty[found >> 6] &= ~(1ull << (found & 63));
+            cfg_list[c0 + pos++] = (int32_t)(c0 + (key[i] & 0xffffffff));
+            r -= found;
+            ++nseg;
+        }
+    }
+    lcount[blockIdx.x] = ntile;
+}
+
+// Global tile table: tile_start[base_c + j] = chunk c's j-th tile, n_tiles.
+__global__ __launch_bounds__(256) void plan_publish_kernel(const int32_t *__restrict__ lstart,
+                                                           const int32_t *__restrict__ lcount, int64_t n_chunks,
+                                                           int64_t N, int32_t *__restrict__ tile_start,
+                                                           int32_t *__restrict__ n_tiles, int64_t max_tiles,
+                                                           int32_t *status)
+{
+    __shared__ int64_t base_s;
+    const int64_t c = blockIdx.x;
+    if (threadIdx.x == 0) {
+        int64_t b = 0;
+        for (int64_t q = 0; q < c; ++q)
+            b += lcount[q];
+        base_s = b;
+    }
+    __syncthreads();
+    const int64_t base = base_s, nt = lcount[c];
+    const bool bad = (*status != 0) || base + nt > max_tiles;
+    if (!bad)
+        for (int64_t j = threadIdx.x; j < nt; j += 256)
+            tile_start[base + j] = (int32_t)(c * PLAN_C + lstart[c * (PLAN_C + 1) + j]);
+    if (c == n_chunks - 1 && threadIdx.x == 0) {
+        if (bad) {
+            if (base + nt > max_tiles)
+                set_status(status, DST_EINVAL);
+            *n_tiles = 0;
+        } else {
+            tile_start[base + nt] = (int32_t)N;
+            *n_tiles = (int32_t)(base + nt);
+        }
+    }
 }
 
 int64_t knm_max_tiles(int64_t N, int64_t n_atoms)
 {
-    // Two consecutive tiles hold more than KNM_CAP atoms between them unless the
-    // first was closed by the configuration cap.
-    int64_t bound = 2 * ((n_atoms + KNM_CAP - 1) / KNM_CAP) + (N + KNM_MAX_SEG - 1) / KNM_MAX_SEG + 1;
+    // Within a chunk, a tile closes only when the largest remaining
+    // configuration does not fit, so two consecutive tiles hold more than
+    // KNM_CAP atoms unless the first was closed by the configuration cap; each
+    // chunk may end with one more partial tile.
+    int64_t bound = 2 * ((n_atoms + KNM_CAP - 1) / KNM_CAP) + (N + KNM_MAX_SEG - 1) / KNM_MAX_SEG +
+                    knm_plan_chunks(N) + 1;
     return bound < N ? bound : N;
 }
 
@@ -105,23 +188,21 @@ struct KnmLoads {
     double b[2];
 };
 
-DEV void knm_load(KnmLoads &r, const double *__restrict__ X, int64_t row0, int64_t row_end,
-                  const double *__restrict__ XM, int64_t col0, int64_t M, int d, int k0)
+DEV void knm_load(KnmLoads &r, const double *__restrict__ xr, const double *__restrict__ XM, int64_t col0, int64_t M,
+                  int d, int k0)
 {
     const int tid = threadIdx.x;
     {
-        const int64_t row = row0 + tid;
+        // xr: this thread's atom row (nullptr past the tile's atoms)
         const int kb = k0;
-        const bool rv = row < row_end;
-        const double *p = X + row * (int64_t)d + kb;
-        if (rv && kb + 8 <= d) {
+        if (xr && kb + 8 <= d) {
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-                r.a[e] = p[e];
+                r.a[e] = xr[kb + e];
         } else {
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-                r.a[e] = (rv && kb + e < d) ? p[e] : 0.0;
+                r.a[e] = (xr && kb + e < d) ? xr[kb + e] : 0.0;
         }
     }
     {
@@ -157,16 +238,17 @@ DEV void knm_store(const KnmLoads &r, double *As, double *Bs)
     }
 }
 
-// G = X[row0 : row0+256) . XM[col0 : col0+64)^T, accumulated in registers.
-DEV void knm_gemm(d4 (&acc)[KS::FM][KS::FN], double *lds, const double *__restrict__ X, int64_t row0,
-                  int64_t row_end, const double *__restrict__ XM, int64_t col0, int64_t M, int d)
+// G = (the tile's 256 atom rows, thread t's row at xr) . XM[col0 : col0+64)^T,
+// accumulated in registers.
+DEV void knm_gemm(d4 (&acc)[KS::FM][KS::FN], double *lds, const double *__restrict__ xr,
+                  const double *__restrict__ XM, int64_t col0, int64_t M, int d)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / KS::WN, wn = wave % KS::WN;
     zero_acc<KS>(acc);
     const int nk = (d + KS::BK - 1) / KS::BK;
     KnmLoads r;
-    knm_load(r, X, row0, row_end, XM, col0, M, d, 0);
+    knm_load(r, xr, XM, col0, M, d, 0);
     knm_store(r, lds, lds + KS::A_ELEMS);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
@@ -174,7 +256,7 @@ DEV void knm_gemm(d4 (&acc)[KS::FM][KS::FN], double *lds, const double *__restri
         double *nxt = lds + ((kt + 1) & 1) * KS::STAGE;
         const bool more = kt + 1 < nk;
         if (more)
-            knm_load(r, X, row0, row_end, XM, col0, M, d, (kt + 1) * KS::BK);
+            knm_load(r, xr, XM, col0, M, d, (kt + 1) * KS::BK);
         mma_stage<KS>(cur, cur + KS::A_ELEMS, acc, wm, wn, lane);
         if (more)
             knm_store(r, nxt, nxt + KS::A_ELEMS);
@@ -188,7 +270,9 @@ constexpr int KNM_LDS_DOUBLES =
 __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
 {
     __shared__ double lds[KNM_LDS_DOUBLES];
-    __shared__ int32_t sstart[KNM_MAX_SEG + 1];
+    __shared__ int32_t sstart[KNM_MAX_SEG + 1];  // atom offset of each segment within the tile
+    __shared__ int64_t sbase[KNM_MAX_SEG];       // first atom (row of X) of each segment
+    __shared__ int32_t srow[KNM_MAX_SEG];        // output row of each segment
     __shared__ double carry[KNM_BN];
 
     // The grid is sized for the largest possible tile count; the remap uses
@@ -203,43 +287,68 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
     if (lw >= total)
         return;
     const int64_t t = lw / a.n_ct, ct = lw % a.n_ct;
-
-    int64_t seg_lo, seg_hi, atom_lo, atom_hi;
-    if (unit) {
-        seg_lo = t * KNM_BM;
-        seg_hi = seg_lo + KNM_BM < a.n_rows_unit ? seg_lo + KNM_BM : a.n_rows_unit;
-        atom_lo = seg_lo;
-        atom_hi = seg_hi;
-    } else {
-        seg_lo = a.tile_cfg[t];
-        seg_hi = a.tile_cfg[t + 1];
-        atom_lo = a.offsets[seg_lo];
-        atom_hi = a.offsets[seg_hi];
-    }
-    const int n_seg = (int)(seg_hi - seg_lo);
     const int64_t col0 = ct * KNM_BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / KS::WN, wn = wave % KS::WN;
 
-    // Segment boundaries relative to the tile's first atom.
-    for (int s = tid; s <= n_seg; s += KS::NT)
-        sstart[s] = unit ? s : (int32_t)(a.offsets[seg_lo + s] - atom_lo);
+    // The tile's segments: rows of the unit block, or configurations from the plan.
+    int n_seg;
+    int64_t n_at;  // atoms in the tile
+    if (unit) {
+        const int64_t r0 = t * KNM_BM;
+        n_seg = (int)((a.n_rows_unit - r0) < KNM_BM ? (a.n_rows_unit - r0) : KNM_BM);
+        if (tid == 0)
+            sstart[0] = 0;
+        if (tid < n_seg) {
+            sstart[tid + 1] = tid + 1;
+            sbase[tid] = r0 + tid;
+            srow[tid] = (int32_t)(r0 + tid);
+        }
+        n_at = n_seg;
+    } else {
+        const int64_t p0 = a.tile_start[t];
+        n_seg = (int)(a.tile_start[t + 1] - p0);
+        int64_t sz = 0;
+        if (tid < n_seg) {
+            const int32_t cfg = a.cfg_list[p0 + tid];
+            const int64_t lo = a.offsets[cfg];
+            sz = a.offsets[cfg + 1] - lo;
+            sbase[tid] = lo;
+            srow[tid] = cfg;
+        }
+        // inclusive scan of the segment sizes (one per thread)
+        int32_t *scan = reinterpret_cast<int32_t *>(lds);
+        scan[tid] = (int32_t)sz;
+        __syncthreads();
+        for (int off = 1; off < KNM_MAX_SEG; off <<= 1) {
+            const int32_t x = (tid >= off) ? scan[tid - off] : 0;
+            __syncthreads();
+            scan[tid] += x;
+            __syncthreads();
+        }
+        sstart[tid + 1] = scan[tid];
+        if (tid == 0)
+            sstart[0] = 0;
+        __syncthreads();
+        n_at = sstart[n_seg];
+    }
+    __syncthreads();
 
     auto emit = [&](int s, int64_t colg, double sum) {
-        const int64_t seg = seg_lo + s;
+        const int64_t row = srow[s];
         double v = sum;
         if (unit) {
-            if (seg == colg)
+            if (row == colg)
                 v += a.jitter;
-            if (a.upper_only && seg > colg)
+            if (a.upper_only && row > colg)
                 v = 0.0;
         }
         if (a.sigma)
-            v = v / a.sigma[seg];
-        a.out[colg * a.ldo + a.row_off + seg] = v;
+            v = v / a.sigma[row];
+        a.out[colg * a.ldo + a.row_off + row] = v;
     };
 
-    if (atom_hi == atom_lo) {  // only empty configurations: their sums are zero
+    if (n_at == 0) {  // only empty configurations: their sums are zero
         for (int item = tid; item < n_seg * KNM_BN; item += KS::NT) {
             const int s = item % n_seg, c = item / n_seg;
             const int64_t colg = col0 + c;
@@ -249,12 +358,27 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
         return;
     }
 
-    const bool multi = (atom_hi - atom_lo) > KNM_BM;  // then n_seg == 1
+    // This thread's atom row for a tile of whole segments: segment by binary search.
+    const double *xr_packed = nullptr;
+    const bool multi = n_at > KNM_BM;  // then n_seg == 1: a configuration in several atom chunks
+    if (!multi && tid < n_at) {
+        int lo = 0, hi = n_seg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sstart[mid] <= tid)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        xr_packed = a.X + (sbase[lo] + (tid - sstart[lo])) * (int64_t)a.d;
+    }
     d4 acc[KS::FM][KS::FN];
-    for (int64_t cs = atom_lo; cs < atom_hi; cs += KNM_BM) {
-        const bool first = (cs == atom_lo), last = (cs + KNM_BM >= atom_hi);
+    for (int64_t cs = 0; cs < n_at; cs += KNM_BM) {
+        const bool first = (cs == 0), last = (cs + KNM_BM >= n_at);
+        const double *xr = multi ? ((cs + tid < n_at) ? a.X + (sbase[0] + cs + tid) * (int64_t)a.d : nullptr)
+                                 : xr_packed;
         __syncthreads();
-        knm_gemm(acc, lds, a.X, cs, atom_hi, a.XM, col0, a.M, a.d);
+        knm_gemm(acc, lds, xr, a.XM, col0, a.M, a.d);
 
         // k = sigma_w^2 g^zeta, in registers.
 #pragma unroll
@@ -295,7 +419,7 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
             } else if (tid < EPC) {
                 const int c = tid;
                 const int64_t colg = col0 + p * EPC + c;
-                const int nr = (int)((atom_hi - cs) < KNM_BM ? (atom_hi - cs) : KNM_BM);
+                const int nr = (int)((n_at - cs) < KNM_BM ? (n_at - cs) : KNM_BM);
                 double sum = 0.0;
                 for (int r = 0; r < nr; ++r)
                     sum += E[r * EPLD + c];
@@ -349,7 +473,7 @@ __global__ __launch_bounds__(256, 2) void predict_kernel(const double *__restric
         for (int64_t ct = 0; ct < n_ct; ++ct) {
             const int64_t col0 = ct * KNM_BN;
             __syncthreads();
-            knm_gemm(acc, lds, X, cs, atom_hi, XM, col0, M, d);
+            knm_gemm(acc, lds, (cs + tid < atom_hi) ? X + (cs + tid) * (int64_t)d : nullptr, XM, col0, M, d);
             double cw[KS::FN][4];
 #pragma unroll
             for (int j = 0; j < KS::FN; ++j)
@@ -410,11 +534,14 @@ hipError_t launch_predict(const double *X, int64_t n_atoms, const int64_t *offse
     return hipGetLastError();
 }
 
-hipError_t launch_plan_tiles(const int64_t *offsets, int64_t N, int64_t n_atoms, int32_t *tile_cfg,
-                             int32_t *n_tiles, int64_t max_tiles, int32_t *status, hipStream_t s)
+hipError_t launch_plan_tiles(const int64_t *offsets, int64_t N, int64_t n_atoms, const KnmPlan &p, int64_t max_tiles,
+                             int32_t *status, hipStream_t s)
 {
-    hipLaunchKernelGGL(plan_tiles_kernel, dim3(1), dim3(256), 0, s, offsets, N, n_atoms, tile_cfg,
-                       n_tiles, max_tiles, status);
+    const int64_t nc = knm_plan_chunks(N);
+    hipLaunchKernelGGL(plan_chunk_kernel, dim3((unsigned)nc), dim3(256), 0, s, offsets, N, n_atoms, p.cfg_list,
+                       p.lstart, p.lcount, status);
+    hipLaunchKernelGGL(plan_publish_kernel, dim3((unsigned)nc), dim3(256), 0, s, (const int32_t *)p.lstart,
+                       (const int32_t *)p.lcount, nc, N, p.tile_start, p.n_tiles, max_tiles, status);
     return hipGetLastError();
 }
 
