@@ -43,16 +43,13 @@ def log(msg):
 def knm_traffic():
     """HBM bytes per knm_kernel launch from the committed counter runs, or None when
     the kernel's source has changed since those counters were taken."""
-    import hashlib
+    from paper_2207_03803_amd.profiling import source_hash
 
     path = os.path.join(ROOT, "profiles", "knm_kernel_realistic_fp64_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    h = hashlib.sha256()
-    for f in ("knm.hip", "common.h", "kernels.h"):
-        h.update(open(os.path.join(ROOT, "paper_2207_03803_amd", "csrc", f), "rb").read())
-    if h.hexdigest() != rec.get("source_sha256"):
+    if source_hash() != rec.get("source_sha256"):
         return None
     return rec["traffic_bytes_per_launch"]
 
