@@ -118,7 +118,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="realistic_fp64")
-    ap.add_argument("--forms", default="mixed,serve",
+    ap.add_argument("--forms", default="mixed,sweep,serve",
                     help="comma-separated forms to measure beside the FP64 fit, or none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
@@ -278,10 +278,11 @@ def bench_sweep(gap, sweep, specs, pools, replays=2):
     import torch
 
     table = sweep.load_table()
-    tune = table.get(sweep.bucket(specs), dict(streams=8, split_wgs=0))
+    tune = table.get(sweep.bucket(specs), dict(streams=16, split_wgs=1024, lookahead=1))
     total_flops = sum(s.flops() for s in specs)
     sw = sweep.Sweep(specs, pools, precision=gap.GAP_MIXED_FP32, streams=tune["streams"],
-                     split_wgs=tune["split_wgs"], max_refine_iters=30, refine_tol=1e-12)
+                     split_wgs=tune["split_wgs"], lookahead=tune.get("lookahead", 0), max_refine_iters=30,
+                     refine_tol=1e-12)
     sw.capture(log=log)
     log("[bench] sweep: every fit's graph captured; first replay")
     sw.replay(1)
@@ -311,6 +312,7 @@ def bench_sweep(gap, sweep, specs, pools, replays=2):
     return {"n_fits": len(specs), "fits_per_s": len(specs) / t_graph, "s_per_sweep": t_graph,
             "fp64_sequential_fits_per_s": len(specs) / t_seq, "speedup_vs_fp64_sequential": t_seq / t_graph,
             "launch_shape": {"streams": tune["streams"], "qr_split_wgs": tune["split_wgs"],
+                             "qr_lookahead": tune.get("lookahead", 0),
                              "from_tuning_table": sweep.bucket(specs) in table},
             "tflops_effective": total_flops / t_graph / 1e12,
             "all_ok": all(s == gap.GAP_OK for s in st) and all(s == gap.GAP_OK for s in st64),

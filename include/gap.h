@@ -113,10 +113,11 @@ typedef struct gap_layout_info {
 } gap_layout_info;
 
 /* Create a handle bound to the current HIP device and `stream` (hipStream_t or NULL).
- * Validates p (GAP_EINVAL).  Allocates only host memory, HIP events and one
- * internal HIP stream (default priority) for the QR look-ahead, which forks
- * from and joins `stream` inside gap_solve (so graph capture of `stream`
- * captures it too). */
+ * Validates p (GAP_EINVAL).  Allocates only host memory and HIP events.  The
+ * first gap_build_knm of a fit that uses the QR look-ahead (gap_tuning) also
+ * creates one internal HIP stream (default priority) and its events; make that
+ * first call outside graph capture.  Inside gap_solve that stream forks from
+ * and joins `stream`, so a graph captured on `stream` contains it. */
 gap_status gap_create(const gap_params *p, void *stream, gap_handle *out);
 
 /* Bytes of device workspace a fit of this shape needs.  Pure host function:
@@ -193,16 +194,17 @@ gap_status gap_stage_times(gap_handle h, float *ms, int n);
  *                 CholeskyQR3 (streams the panel; default), 1 = TSQR over a
  *                 4-ary tree of 256-row tiles.  Both end in the same
  *                 reconstructed Householder representation.
- *   qr_lookahead_off  1 = run the whole QR on the handle's stream; 0 (default) =
- *                 look-ahead: the trailing update of each 128-column block runs
- *                 on a second stream the handle owns, while the handle's stream
- *                 updates and factors the next block (the two schedules sum the
- *                 split-K partials of the next block's update over different row
- *                 chunks, so they agree to rounding, each one deterministic). */
+ *   qr_lookahead  0 = automatic (look-ahead from M >= 2048 on), 1 = off (the
+ *                 whole QR on the handle's stream), 2 = on.  Look-ahead: the
+ *                 trailing update of each 128-column block runs on a second
+ *                 stream the handle owns while the handle's stream updates and
+ *                 factors the next block.  The two schedules sum the split-K
+ *                 partials of the next block's update over different row chunks,
+ *                 so they agree to rounding; each one is deterministic. */
 typedef struct gap_tuning {
     int32_t qr_split_wgs;
     int32_t qr_panel;
-    int32_t qr_lookahead_off;
+    int32_t qr_lookahead;
     int32_t reserved[5];
 } gap_tuning;
 

@@ -234,18 +234,7 @@ gap_status gap_create(const gap_params *p, void *stream, gap_handle *out)
                 return GAP_EDEVICE;
             }
     }
-    hipEvent_t *lev[5] = {&h->la.fork, &h->la.t_ready, &h->la.bulk[0], &h->la.bulk[1], &h->la.join};
-    if (hipStreamCreateWithFlags(&h->la.side, hipStreamNonBlocking) != hipSuccess) {
-        h->la.side = nullptr;
-        destroy_handle(h);
-        return GAP_EDEVICE;
-    }
-    for (hipEvent_t *e : lev)
-        if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
-            *e = nullptr;
-            destroy_handle(h);
-            return GAP_EDEVICE;
-        }
+
     *out = h;
     return GAP_OK;
 }
@@ -258,6 +247,29 @@ gap_status gap_bind_workspace(gap_handle h, void *dev_ptr, size_t bytes)
     h->ws_bytes = bytes;
     h->state = ST_BOUND;
     return GAP_OK;
+}
+
+// Look-ahead pays where the panels are many: automatic from 2048 columns on.
+static bool use_lookahead(gap_handle h)
+{
+    const int32_t mode = h->tuning.qr_lookahead;
+    return mode == 2 || (mode == 0 && h->L.M >= 2048);
+}
+
+// The look-ahead's stream and events, created the first time a fit needs them.
+static bool create_lookahead(gap_handle h)
+{
+    if (hipStreamCreateWithFlags(&h->la.side, hipStreamNonBlocking) != hipSuccess) {
+        h->la.side = nullptr;
+        return false;
+    }
+    hipEvent_t *lev[5] = {&h->la.fork, &h->la.t_ready, &h->la.bulk[0], &h->la.bulk[1], &h->la.join};
+    for (hipEvent_t *e : lev)
+        if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
+            *e = nullptr;
+            return false;  // the handle keeps what was created; gap_destroy releases it
+        }
+    return true;
 }
 
 gap_status gap_build_knm(gap_handle h, const double *x_atoms, int64_t n_atoms, const int64_t *config_offsets,
@@ -277,6 +289,8 @@ gap_status gap_build_knm(gap_handle h, const double *x_atoms, int64_t n_atoms, c
     h->x_sparse = x_sparse;
     h->sigma = sigma;
     h->model_only = false;
+    if (use_lookahead(h) && !h->la.side && !create_lookahead(h))
+        return GAP_EDEVICE;
     hipStream_t s = h->stream;
     const gap_params &p = h->p;
     const double sw2 = p.sigma_w * p.sigma_w;
@@ -419,7 +433,7 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
     double *rhs = h->at<double>(L.off_rhs);
     if (!L.mixed) {
         h->mark(4, false);
-        GAP_TRY(dev(launch_geqrf(w, s, h->tuning.qr_lookahead_off ? nullptr : &h->la)));
+        GAP_TRY(dev(launch_geqrf(w, s, (use_lookahead(h) && h->la.join) ? &h->la : nullptr)));
         h->mark(4, true);
         const double *qtb = A + L.M * L.lda;
         h->mark(5, false);
@@ -435,7 +449,7 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
         w.W32 = h->at<float>(L.off_W32);
         h->mark(4, false);
         GAP_TRY(dev(launch_convert_f64_f32(A, A32, L.lda * L.ncols, s)));
-        GAP_TRY(dev(launch_geqrf(w, s, h->tuning.qr_lookahead_off ? nullptr : &h->la)));
+        GAP_TRY(dev(launch_geqrf(w, s, (use_lookahead(h) && h->la.join) ? &h->la : nullptr)));
         h->mark(4, true);
         h->mark(5, false);
         GAP_TRY(dev(launch_copy_f32_f64(A32 + L.M * L.lda, rhs, L.M, s)));
@@ -546,7 +560,7 @@ gap_status gap_set_tuning(gap_handle h, const gap_tuning *t)
         return GAP_EINVAL;
     if (t->qr_panel != 0 && t->qr_panel != 1)
         return GAP_EINVAL;
-    if (t->qr_lookahead_off != 0 && t->qr_lookahead_off != 1)
+    if (t->qr_lookahead < 0 || t->qr_lookahead > 2)
         return GAP_EINVAL;
     h->tuning = *t;
     return GAP_OK;

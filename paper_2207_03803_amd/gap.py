@@ -39,7 +39,7 @@ class GapSolveInfo(ctypes.Structure):
 
 
 class GapTuning(ctypes.Structure):
-    _fields_ = [("qr_split_wgs", ctypes.c_int32), ("qr_panel", ctypes.c_int32), ("qr_lookahead_off", ctypes.c_int32),
+    _fields_ = [("qr_split_wgs", ctypes.c_int32), ("qr_panel", ctypes.c_int32), ("qr_lookahead", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 5)]
 
 
@@ -206,11 +206,12 @@ class Handle:
         off = lay.tau - self.ws.data_ptr()
         return self.ws[off:off + 8 * lay.M].view(torch.float64)
 
-    def set_tuning(self, qr_split_wgs=0, qr_panel=0, qr_lookahead_off=0):
+    def set_tuning(self, qr_split_wgs=0, qr_panel=0, qr_lookahead=0):
+        """qr_lookahead: 0 automatic, 1 off, 2 on."""
         t = GapTuning()
         t.qr_split_wgs = int(qr_split_wgs)
         t.qr_panel = int(qr_panel)
-        t.qr_lookahead_off = int(qr_lookahead_off)
+        t.qr_lookahead = int(qr_lookahead)
         _check(lib().gap_set_tuning(self.h, ctypes.byref(t)), "gap_set_tuning")
 
     def set_model(self, XM):

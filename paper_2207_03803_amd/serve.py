@@ -217,8 +217,7 @@ class Server:
         st = self.slots[slot]
         m = req.meta
         if req.kind == "fit":
-            p = gap.params(req.spec.d, req.spec.zeta, 1.0, 1e-8, precision=self.precision, **self.refine)
-            h = gap.Handle(p, stream=st)
+            h = self._fit_handle(slot, req.spec.d, req.spec.zeta)
             ws_block, c_block = blocks
             h.bind(self.arena.view(ws_block))
             h.build_knm(m["X"], m["offsets"], m["XM"], m["sigma"])
@@ -236,6 +235,17 @@ class Server:
         ev = torch.cuda.Event()
         ev.record(st)
         return ev, keep
+
+    def _fit_handle(self, slot, d, zeta):
+        """A slot's handle for fits of (d, zeta), created once and reused (a handle
+        owns HIP events and a stream: creating and destroying them per request
+        would put those calls on the serving path)."""
+        key = ("fit", slot, d, zeta)
+        with self.handles_lock:
+            if key not in self.handles:
+                p = gap.params(d, zeta, 1.0, 1e-8, precision=self.precision, **self.refine)
+                self.handles[key] = gap.Handle(p, stream=self.slots[slot])
+            return self.handles[key]
 
     def _predict_handle(self, slot, d, zeta):
         key = (slot, d, zeta)  # one per slot thread: set_model / set_stream are per call
@@ -266,8 +276,7 @@ class Server:
             s, info = h.sync()
             req.result = out.cpu().numpy()
             req.meta["status"] = s
-            h.close()
-            # release the workspace; the weights stay resident as the model
+            # release the workspace (the handle stays with its slot); the weights stay resident as the model
             self.arena.release(blocks[0])
             self.models[req.rid] = (req.meta["XM"], out, req.spec.zeta, req.spec.d, None, blocks[1])
             busy = {k for k, v in self.model_users.items() if v > 0}

@@ -12,8 +12,10 @@ keeps its own handle and workspace; the library's kernels are deterministic,
 so a fit's weights are bitwise the same alone, in a replay, or on any stream.
 
 The autotuner times whole-sweep replays over a small grid of launch shapes
-(stream count, split-K workgroup target of the QR) and keeps a table keyed by
-the sweep's shape bucket.
+(stream count, split-K workgroup target of the QR, QR look-ahead) and keeps a
+table keyed by the sweep's shape bucket.  Run it as a program of its own
+(`python -m paper_2207_03803_amd.sweep`); it sets 16 hardware queues, like
+the benchmark.
 """
 from __future__ import annotations
 
@@ -103,7 +105,7 @@ class Fit:
 class Sweep:
     """The fits of one sweep with their inputs resident on the device."""
 
-    def __init__(self, specs, pools, precision=gap.GAP_MIXED_FP32, streams=8, split_wgs=0,
+    def __init__(self, specs, pools, precision=gap.GAP_MIXED_FP32, streams=8, split_wgs=0, lookahead=0,
                  max_refine_iters=20, refine_tol=1e-12):
         import torch
 
@@ -139,8 +141,8 @@ class Sweep:
             p = gap.params(s.d, s.zeta, 1.0, 1e-8, precision=precision, max_refine_iters=max_refine_iters,
                            refine_tol=refine_tol)
             f.handle = gap.Handle(p, stream=self.streams[stream_of[s.idx]])
-            if split_wgs:
-                f.handle.set_tuning(qr_split_wgs=split_wgs)
+            if split_wgs or lookahead:
+                f.handle.set_tuning(qr_split_wgs=split_wgs, qr_lookahead=lookahead)
             f.ws = f.handle.alloc_workspace(s.n_configs, n_atoms, s.M)
             f.c = torch.empty(s.M, dtype=torch.float64, device="cuda")
             self.fits.append(f)
@@ -251,11 +253,13 @@ def autotune(specs, pools, precision=gap.GAP_MIXED_FP32, candidates=None, replay
 
     Returns (best, results); stores {bucket: best} in the table at `path`.
     """
-    candidates = candidates or [dict(streams=s, split_wgs=w) for s in (4, 8, 16) for w in (1024, 2048, 4096)]
+    candidates = candidates or [dict(streams=s, split_wgs=w, lookahead=la) for s in (8, 16) for w in (1024, 2048)
+                                for la in (0, 1)]
     results = []
     for cand in candidates:
         log(f"[autotune] building {cand}")
-        sw = Sweep(specs, pools, precision=precision, streams=cand["streams"], split_wgs=cand["split_wgs"])
+        sw = Sweep(specs, pools, precision=precision, streams=cand["streams"], split_wgs=cand["split_wgs"],
+                   lookahead=cand.get("lookahead", 0))
         sw.capture()
         log(f"[autotune] captured {len(specs)} fit graphs; first replay")
         sw.replay(1)
@@ -267,7 +271,8 @@ def autotune(specs, pools, precision=gap.GAP_MIXED_FP32, candidates=None, replay
     best = min(results, key=lambda r: r["seconds"])
     table = load_table(path)
     table[bucket(specs)] = dict(streams=best["streams"], split_wgs=best["split_wgs"],
-                                seconds=best["seconds"], precision=int(precision))
+                                lookahead=best.get("lookahead", 0), seconds=best["seconds"],
+                                precision=int(precision))
     with open(path, "w") as fh:
         json.dump(table, fh, indent=1, sort_keys=True)
     return best, results
@@ -275,6 +280,8 @@ def autotune(specs, pools, precision=gap.GAP_MIXED_FP32, candidates=None, replay
 
 def main():
     import argparse
+
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"  # before HIP starts: as many queues as streams
 
     ap = argparse.ArgumentParser(description="Autotune the sweep's launch shape and store it in the tuning table.")
     ap.add_argument("--seed", type=int, default=0)

@@ -167,19 +167,19 @@ def test_repeat_runs_are_bitwise_identical(orc_m):
     assert np.array_equal(c1, c2)
 
 
-@pytest.mark.parametrize("panel,lookahead_off", [(0, 0), (0, 1), (1, 0), (1, 1)])
-def test_qr_schedules_and_panels_agree(orc_m, panel, lookahead_off):
+@pytest.mark.parametrize("panel,lookahead", [(0, 2), (0, 1), (1, 2), (1, 1)])
+def test_qr_schedules_and_panels_agree(orc_m, panel, lookahead):
     """Both panel factorisations (shifted CholeskyQR3, TSQR) with and without the
     look-ahead schedule reach the oracle's weights; each is bitwise repeatable."""
     inp, y, ref = _case(orc_m, 1500, (16, 64), 160, 390, 3, 21)
     g = GpuFit(inp.X, inp.offsets, inp.XM, inp.sigma, y, 3)
-    g.h.set_tuning(qr_panel=panel, qr_lookahead_off=lookahead_off)
+    g.h.set_tuning(qr_panel=panel, qr_lookahead=lookahead)
     g.build()
     c1, info = g.solve()
     g.build()
     c2, _ = g.solve()
     err = rel(c1, ref.c)
-    log(f"  panel={'TSQR' if panel else 'CholeskyQR3'} look-ahead={'off' if lookahead_off else 'on'}: "
+    log(f"  panel={'TSQR' if panel else 'CholeskyQR3'} look-ahead={'off' if lookahead == 1 else 'on'}: "
         f"c rel err {err:.2e}")
     assert info.device_status == 0
     assert err <= TOL_C
