@@ -386,6 +386,21 @@ DEV T ypanel(const T *A, int64_t lda, int64_t m, int64_t j0, int pw, int64_t r, 
     return A[(j0 + p) * lda + r];
 }
 
+// Tile of a trailing-update product: logical tiles are numbered row block by
+// row block (the column tiles of one row block consecutive), and consecutive
+// logical tiles run on the same XCD, so that the row block's Y tile stays in
+// that XCD's L2 while its column tiles go by.
+DEV bool update_tile(int64_t n_rb, int64_t n_cb, int64_t &rb, int64_t &cb)
+{
+    const int64_t total = n_rb * n_cb;
+    const int64_t lw = xcd_remap(blockIdx.x, (total + 7) & ~int64_t(7));
+    if (lw >= total)
+        return false;
+    rb = lw / n_cb;
+    cb = lw % n_cb;
+    return true;
+}
+
 constexpr int OB = 2 * NB;                 // outer block: two TSQR panels
 using WS = TileShape<OB, 64, 16, 2, 2>;    // P = Y^T C over a row chunk
 using US = TileShape<128, 128, 16, 2, 2>;  // C^T -= W^T Y^T (rows of C along the MFMA N axis)
@@ -598,8 +613,11 @@ __global__ __launch_bounds__(256) void qr_tcombine_kernel(QrWork w, const double
 __global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt)
 {
     __shared__ double lds[2 * US::STAGE];
-    const int64_t q0 = (int64_t)blockIdx.y * US::BM;
-    const int64_t r0 = j0 + (int64_t)blockIdx.x * US::BN;
+    int64_t rb, cb;
+    if (!update_tile((w.m - j0 + US::BN - 1) / US::BN, (nt + US::BM - 1) / US::BM, rb, cb))
+        return;
+    const int64_t q0 = cb * US::BM;
+    const int64_t r0 = j0 + rb * US::BN;
     const double *A = w.A;
     const int64_t lda = w.lda, m = w.m, ldW = w.ldw;
     const double *W = w.W;
@@ -729,8 +747,11 @@ __global__ __launch_bounds__(256, 2) void qr_wpart32_kernel(QrWork w, int64_t j0
 __global__ __launch_bounds__(256, 2) void qr_update32_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt)
 {
     __shared__ float lds[2 * US32::STAGE];
-    const int64_t q0 = (int64_t)blockIdx.y * US32::BM;
-    const int64_t r0 = j0 + (int64_t)blockIdx.x * US32::BN;
+    int64_t rb, cb;
+    if (!update_tile((w.m - j0 + US32::BN - 1) / US32::BN, (nt + US32::BM - 1) / US32::BM, rb, cb))
+        return;
+    const int64_t q0 = cb * US32::BM;
+    const int64_t r0 = j0 + rb * US32::BN;
     const float *A = w.A32;
     const int64_t lda = w.lda, m = w.m, ldW = w.ldw;
     const float *W = w.W32;
@@ -849,16 +870,15 @@ static void apply_block(const QrWork &w, int64_t j0, int pw, const double *Tm, i
     if constexpr (sizeof(T) == 8) {
         hipLaunchKernelGGL(qr_wred_kernel<double>, dim3((unsigned)((nt + 63) / 64)), dim3(256), 0, s, w, Tm, tld,
                            pw, nch, nt, w.W);
-        hipLaunchKernelGGL(qr_update_kernel,
-                           dim3((unsigned)((rows + US::BN - 1) / US::BN), (unsigned)((nt + US::BM - 1) / US::BM)),
-                           dim3(256), 0, s, w, j0, pw, c0, nt);
+        const int64_t tiles = ((rows + US::BN - 1) / US::BN) * ((nt + US::BM - 1) / US::BM);
+        hipLaunchKernelGGL(qr_update_kernel, dim3((unsigned)((tiles + 7) & ~int64_t(7))), dim3(256), 0, s, w, j0, pw,
+                           c0, nt);
     } else {
         hipLaunchKernelGGL(qr_wred_kernel<float>, dim3((unsigned)((nt + 63) / 64)), dim3(256), 0, s, w, Tm, tld,
                            pw, nch, nt, w.W32);
-        hipLaunchKernelGGL(qr_update32_kernel,
-                           dim3((unsigned)((rows + US32::BN - 1) / US32::BN),
-                                (unsigned)((nt + US32::BM - 1) / US32::BM)),
-                           dim3(256), 0, s, w, j0, pw, c0, nt);
+        const int64_t tiles = ((rows + US32::BN - 1) / US32::BN) * ((nt + US32::BM - 1) / US32::BM);
+        hipLaunchKernelGGL(qr_update32_kernel, dim3((unsigned)((tiles + 7) & ~int64_t(7))), dim3(256), 0, s, w, j0,
+                           pw, c0, nt);
     }
 }
 
