@@ -402,7 +402,7 @@ DEV bool update_tile(int64_t n_rb, int64_t n_cb, int64_t &rb, int64_t &cb)
 }
 
 constexpr int OB = 2 * NB;                 // outer block: two TSQR panels
-using WS = TileShape<OB, 64, 16, 2, 2>;    // P = Y^T C over a row chunk
+using WS = TileShape<OB, 128, 16, 2, 2>;   // P = Y^T C over a row chunk
 using US = TileShape<128, 128, 16, 2, 2>;  // C^T -= W^T Y^T (rows of C along the MFMA N axis)
 
 // P[ch][p][q] = sum over the chunk's rows r of Y[r][p] C[r][q].  Y is the
@@ -670,7 +670,7 @@ __global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0,
             }
 }
 
-using WS32 = TileShape<OB, 64, 32, 2, 2>;    // FP32 P = Y^T C
+using WS32 = TileShape<OB, 128, 32, 2, 2>;   // FP32 P = Y^T C
 using US32 = TileShape<128, 128, 32, 2, 2>;  // FP32 C^T -= W^T Y^T
 
 // FP32-storage versions of qr_wpart_kernel / qr_update_kernel on FP32 MFMA.
