@@ -116,12 +116,15 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="realistic_fp64")
     ap.add_argument("--forms", default="mixed,sweep,serve",
                     help="comma-separated forms to measure beside the FP64 fit, or none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--serve-sweep", action="store_true",
+                    help="only the serving loop: saturation throughput, then latency at 0.5/0.8/1.0/1.2 x it")
+    ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -145,6 +148,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_per_launch": 8 << 27, "launches": 3}), flush=True)
+        return
+    if args.serve_sweep:
+        serve_sweep(args, dev)
         return
     w = dict(synth.WORKLOADS[args.workload])
     N, M, d, zeta = w["n_configs"], w["M"], w["d"], w["zeta"]
@@ -188,8 +194,11 @@ def main():
             log(f"[bench] {tag} warmup {i + 1}/{warmup} done")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        per_step = []
         for i in range(steps):
-            step(True)
+            ts = time.perf_counter()
+            step(True)  # ends with a wait for the stream (the stage timers)
+            per_step.append(time.perf_counter() - ts)
             log(f"[bench] {tag} step {i + 1}/{steps} done")
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
@@ -200,10 +209,12 @@ def main():
         del h
         torch.cuda.empty_cache()
         stages_ms = {k: v / steps for k, v in stage_sum.items() if v > 0}
-        return dict(ms=1e3 * elapsed / steps, stages_ms=stages_ms, info=info, c=c, y=y)
+        return dict(ms=1e3 * elapsed / steps, ms_median=1e3 * float(np.median(per_step)),
+                    ms_min=1e3 * min(per_step), stages_ms=stages_ms, info=info, c=c, y=y)
 
     fp = run_fit(gap.GAP_FP64, args.steps, args.warmup)
     ms_per_step = fp["ms"]
+    step_stats = {"median_ms": fp["ms_median"], "min_ms": fp["ms_min"]}
     stages_ms = fp["stages_ms"]
     knm_s = stages_ms["knm"] / 1e3
     achieved = f["knm"] / knm_s
@@ -220,7 +231,8 @@ def main():
         mx = run_fit(gap.GAP_MIXED_FP32, args.steps, args.warmup, y=fp["y"])
         err = float((mx["c"] - fp["c"]).norm() / fp["c"].norm())
         extra["mixed"] = {
-            "s_per_fit": mx["ms"] / 1e3, "speedup_vs_fp64": ms_per_step / mx["ms"], "stages_ms": mx["stages_ms"],
+            "s_per_fit": mx["ms"] / 1e3, "median_ms": mx["ms_median"], "min_ms": mx["ms_min"],
+            "speedup_vs_fp64": ms_per_step / mx["ms"], "stages_ms": mx["stages_ms"],
             "qr_tflops_fp32": f["qr"] / (mx["stages_ms"]["qr"] / 1e3) / 1e12,
             "refine_iters": mx["info"].refine_iters, "last_dc_over_c": mx["info"].grad_rel,
             "c_rel_err_vs_fp64_path": err,
@@ -252,6 +264,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "step_ms": step_stats,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -317,6 +330,55 @@ def bench_sweep(gap, sweep, specs, pools, replays=2):
             "tflops_effective": total_flops / t_graph / 1e12,
             "all_ok": all(s == gap.GAP_OK for s in st) and all(s == gap.GAP_OK for s in st64),
             "max_c_rel_err_vs_fp64": max(errs)}
+
+
+def serve_sweep(args, dev):
+    """Serving latency against load: a saturation run (every request at t = 0)
+    gives the request throughput; then Poisson arrivals at fractions of it."""
+    import torch
+
+    from paper_2207_03803_amd import gap, serve, sweep, synth
+
+    w = dict(synth.WORKLOADS["realistic_fp64"])
+    inp = synth.make_fit_inputs_torch(seed=args.seed, device=dev, **w)
+    big = sweep.Pool(w["d"], inp.offsets, inp.X)
+    specs = sweep.make_sweep(seed=args.seed)
+    pools = sweep.make_pools(specs, seed=args.seed, min_configs=sweep.SWEEP_RECIPE["pool_configs"])
+    n = args.serve_requests
+    out = {"mode": "serve-sweep", "n_requests_per_point": n, "precision": "mixed",
+           "mix": "70% sweep-sized fits, 5% realistic-size fits, 25% predicts of 1..4096 configurations",
+           "points": []}
+
+    def one(rate, seed):
+        reqs = serve.make_requests(n, rate=rate, seed=seed)
+        srv = serve.Server(pools, slots=8, hbm_budget=96 << 30, precision=gap.GAP_MIXED_FP32,
+                           predict_pool=(pools[400].offsets, pools[400].X), big_pool=big,
+                           max_refine_iters=30, refine_tol=1e-12)
+        for r in reqs:
+            srv.prepare(r)
+        torch.cuda.synchronize()
+        log(f"[serve-sweep] {n} requests prepared (rate {rate:.3g}/s)")
+        srv.run(reqs)
+        torch.cuda.synchronize()
+        rep = serve.latency_report(reqs)
+        rep["all_fits_ok"] = all(r.meta.get("status") == gap.GAP_OK for r in reqs if r.kind == "fit")
+        serve.close(srv)
+        del srv, reqs
+        torch.cuda.empty_cache()
+        return rep
+
+    sat = one(1e9, args.seed + 21)
+    out["saturation"] = sat
+    log(f"[serve-sweep] saturation: {sat['requests_per_s']:.2f} requests/s, {sat['fits_per_s']:.2f} fits/s")
+    for k, f in enumerate((0.5, 0.8, 1.0, 1.2)):
+        rate = f * sat["requests_per_s"]
+        rep = one(rate, args.seed + 22 + k)
+        rep["load"] = f
+        rep["arrival_rate_per_s"] = rate
+        out["points"].append(rep)
+        log(f"[serve-sweep] load {f}: fit p50 {rep['fit']['p50_ms']:.0f} ms p99 {rep['fit']['p99_ms']:.0f} ms; "
+            f"predict p50 {rep['predict']['p50_ms']:.0f} ms p99 {rep['predict']['p99_ms']:.0f} ms")
+    print(json.dumps(out), flush=True)
 
 
 def bench_serve(gap, serve, sweep, pools, big_pool, seed, n_requests=64, rate=6.0):

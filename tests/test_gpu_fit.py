@@ -184,3 +184,63 @@ def test_qr_schedules_and_panels_agree(orc_m, panel, lookahead):
     assert info.device_status == 0
     assert err <= TOL_C
     assert np.array_equal(c1, c2)
+
+
+def test_atom_order_within_configurations(orc_m):
+    """Permuting the atoms inside every configuration changes only the order of
+    the segment sums (K_NM within a few ulps) and leaves c at the oracle's."""
+    inp, y, ref = _case(orc_m, 300, (8, 64), 48, 180, 3, 31)
+    rng = np.random.default_rng(5)
+    X2 = inp.X.copy()
+    for a in range(inp.n_configs):
+        s, e = inp.offsets[a], inp.offsets[a + 1]
+        X2[s:e] = X2[s:e][rng.permutation(e - s)]
+    g1 = GpuFit(inp.X, inp.offsets, inp.XM, inp.sigma, y, 3)
+    g1.build()
+    k1, _ = g1.A_top_and_lower()
+    g2 = GpuFit(X2, inp.offsets, inp.XM, inp.sigma, y, 3)
+    g2.build()
+    k2, _ = g2.A_top_and_lower()
+    assert np.max(np.abs(k1 - k2) / np.abs(k1)) <= 64 * U
+    c2, _ = g2.solve()
+    assert rel(c2, ref.c) <= TOL_C
+
+
+def test_configuration_order_gives_the_same_rows_bitwise(orc_m):
+    """The tile plan packs configurations out of order; a row of K_NM depends only
+    on its configuration's atoms, so permuting the configurations permutes the
+    rows bit for bit, and c stays at the oracle's."""
+    inp, y, ref = _case(orc_m, 700, (8, 64), 40, 150, 2, 33)
+    rng = np.random.default_rng(6)
+    order = rng.permutation(inp.n_configs)
+    counts = np.diff(inp.offsets)
+    offs2 = np.concatenate([[0], np.cumsum(counts[order])]).astype(np.int64)
+    X2 = np.concatenate([inp.X[inp.offsets[a]:inp.offsets[a + 1]] for a in order])
+    g1 = GpuFit(inp.X, inp.offsets, inp.XM, inp.sigma, y, 2)
+    g1.build()
+    k1, _ = g1.A_top_and_lower()
+    g2 = GpuFit(X2, offs2, inp.XM, inp.sigma[order], y[order], 2)
+    g2.build()
+    k2, _ = g2.A_top_and_lower()
+    assert np.array_equal(k2, k1[order])
+    c2, _ = g2.solve()
+    assert rel(c2, ref.c) <= TOL_C
+
+
+def test_one_hot_descriptors_give_exact_counts(orc_m):
+    """x = e_p makes every covariance 0 or sigma_w^2, so K_NM holds integer counts:
+    the GPU's Sigma^-1/2 K_NM equals the oracle's bit for bit."""
+    rng = np.random.default_rng(8)
+    d, N, M = 16, 120, 12
+    counts = rng.integers(1, 40, N)
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    X = np.zeros((offsets[-1], d))
+    X[np.arange(offsets[-1]), rng.integers(0, d, offsets[-1])] = 1.0
+    XM = np.eye(d)[:M]
+    sigma = 1e-3 * counts.astype(float)
+    Knm = orc_m.knm(X, offsets, XM, 3)
+    assert np.array_equal(Knm, np.round(Knm))
+    g = GpuFit(X, offsets, XM, sigma, np.ones(N), 3)
+    g.build()
+    top, _ = g.A_top_and_lower()
+    assert np.array_equal(top, Knm / sigma[:, None])
