@@ -55,7 +55,7 @@ typedef enum gap_status {
     GAP_ENOMEM = 2,      /* the bound workspace is smaller than gap_workspace_bytes() */
     GAP_ENOTPD = 3,      /* K_MM + jitter is not positive definite (Cholesky pivot <= 0) */
     GAP_ENONFINITE = 4,  /* a NaN or Inf reached the weights */
-    GAP_ENOCONV = 5,     /* mixed precision: refinement did not reach refine_tol */
+    GAP_ENOCONV = 5,     /* mixed precision: refinement did not converge within max_refine_iters */
     GAP_EDEVICE = 6,     /* a HIP runtime call failed, or a device-side wait was abandoned */
     GAP_ESTATE = 7,      /* entry points called out of order */
     GAP_ERANK = 8        /* the stacked matrix is numerically rank deficient (a QR panel's
@@ -65,7 +65,10 @@ typedef enum gap_status {
 typedef enum gap_precision {
     GAP_FP64 = 0,        /* every stage in FP64 */
     GAP_MIXED_FP32 = 1   /* FP64 K_NM/Cholesky; FP32 Householder QR with FP64 reflector norms;
-                            FP64 iterative refinement of c against the FP64 A */
+                            FP64 iterative refinement of c against the FP64 A: corrected
+                            semi-normal equations preconditioned by the FP32 R, moving to
+                            R-preconditioned CGLS when a correction fails to halve (A too
+                            ill-conditioned for FP32, kappa(A) near 1/u_32 or above) */
 } gap_precision;
 
 /* Fit parameters (host struct). */
@@ -75,9 +78,10 @@ typedef struct gap_params {
     double sigma_w;           /* kernel prefactor sigma_w (> 0); k carries sigma_w^2 */
     double jitter;            /* added to K_MM's diagonal before the Cholesky (>= 0) */
     int32_t precision;        /* gap_precision */
-    int32_t max_refine_iters; /* mixed precision only: refinement iteration cap */
-    double refine_tol;        /* mixed precision only: stop when ||dc||/||c|| <= refine_tol, or when
-                                 ||dc|| stops halving at a level <= 1e-9 ||c|| (FP64 rounding floor) */
+    int32_t max_refine_iters; /* mixed precision only: refinement iteration cap (both stages) */
+    double refine_tol;        /* mixed precision only: stop when a step's ||dc||/||c|| <= refine_tol,
+                                 or when ||dc|| stops halving at a level <= 1e-9 ||c|| (FP64
+                                 rounding floor) */
     uint32_t flags;           /* GAP_FLAG_* */
 } gap_params;
 
@@ -91,8 +95,10 @@ typedef struct gap_solve_info {
     int32_t refine_iters;    /* mixed precision: refinement iterations done (0 in FP64) */
     double residual_norm2;   /* min of the loss at the returned c: ||(Q^T b)[M:]||^2 in FP64,
                                 ||b - A c||^2 against the FP64 A in mixed precision */
-    double grad_rel;         /* mixed precision: last ||dc|| / ||c||; 0 in FP64 */
-    double est_err;          /* reserved: 0 */
+    double grad_rel;         /* mixed precision: last step's ||dc|| / ||c||; 0 in FP64 */
+    int32_t cgls_iters;      /* mixed precision: how many of refine_iters were preconditioned
+                                CGLS steps (0 when the corrected semi-normal equations converged) */
+    int32_t reserved;        /* 0 */
 } gap_solve_info;
 
 /* Where the library keeps its stage outputs inside the bound workspace (host struct).

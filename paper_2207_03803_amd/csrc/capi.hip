@@ -25,7 +25,7 @@ struct Layout {
            off_T2 = 0, off_wpart_s = 0, off_W_s = 0, off_W32_s = 0, off_plan = 0, total = 0;
     // mixed precision only
     bool mixed = false;
-    size_t off_A32 = 0, off_W32 = 0, off_r = 0, off_s = 0, off_z = 0, off_dc = 0, off_part = 0,
+    size_t off_A32 = 0, off_W32 = 0, off_r = 0, off_s = 0, off_z = 0, off_dc = 0, off_p = 0, off_q = 0, off_part = 0,
            off_rnorm = 0, off_flags = 0, off_stats = 0;
 };
 
@@ -83,6 +83,8 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, bool mixed)
         L.off_s = take(sizeof(double) * (size_t)M);
         L.off_z = take(sizeof(double) * (size_t)M);
         L.off_dc = take(sizeof(double) * (size_t)M);
+        L.off_p = take(sizeof(double) * (size_t)M);
+        L.off_q = take(sizeof(double) * (size_t)L.m);
         L.off_part = take(sizeof(double) * 8 * (size_t)L.m);
         L.off_rnorm = take(sizeof(double) * (size_t)((L.m + 255) / 256 + 1));
         L.off_flags = take(sizeof(int32_t) * 4);
@@ -374,12 +376,13 @@ gap_status gap_sync(gap_handle h, gap_solve_info *info)
         info->device_status = st;
         info->residual_norm2 = res;
         if (h->ws && h->L.total && h->L.mixed) {
-            int32_t it = 0;
+            int32_t it[2] = {0, 0};
             double st2[2] = {0.0, 0.0};
-            if (hipMemcpy(&it, h->at<int32_t>(h->L.off_flags) + 1, sizeof(it), hipMemcpyDeviceToHost) != hipSuccess ||
+            if (hipMemcpy(it, h->at<int32_t>(h->L.off_flags) + 1, sizeof(it), hipMemcpyDeviceToHost) != hipSuccess ||
                 hipMemcpy(st2, h->at<double>(h->L.off_stats), sizeof(st2), hipMemcpyDeviceToHost) != hipSuccess)
                 return GAP_EDEVICE;
-            info->refine_iters = it;
+            info->refine_iters = it[0];
+            info->cgls_iters = it[1];
             info->grad_rel = st2[1];
         }
     }
@@ -466,10 +469,13 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
         rw.s = h->at<double>(L.off_s);
         rw.z = h->at<double>(L.off_z);
         rw.dc = h->at<double>(L.off_dc);
+        rw.p = h->at<double>(L.off_p);
+        rw.q = h->at<double>(L.off_q);
         rw.part = h->at<double>(L.off_part);
         rw.rnorm_part = h->at<double>(L.off_rnorm);
         rw.done = h->at<int32_t>(L.off_flags);
         rw.iters = h->at<int32_t>(L.off_flags) + 1;
+        rw.mode = h->at<int32_t>(L.off_flags) + 3;
         rw.stats = h->at<double>(L.off_stats);
         rw.tol = h->p.refine_tol;
         rw.status = h->status();

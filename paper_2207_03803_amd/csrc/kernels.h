@@ -151,11 +151,14 @@ struct RefineWork {
     double *c;           // [n] solution, refined in place
     double *r;           // [m] residual
     double *s, *z, *dc;  // [n] work
-    double *part;        // [8 * m] column-chunk partials of A c
-    double *rnorm_part;  // [ceil(m / 256)] partial ||r||^2
+    double *p;           // [n] CGLS search direction
+    double *q;           // [m] A p
+    double *part;        // [8 * m] column-chunk partials of A c (A p)
+    double *rnorm_part;  // [ceil(m / 256)] partial ||r||^2 (||q||^2)
     int32_t *done;       // convergence flag
-    int32_t *iters;      // iterations done
-    double *stats;       // [0] ||r||^2, [1] last ||dc|| / ||c||
+    int32_t *iters;      // [0] iterations done, [1] of them CGLS steps
+    int32_t *mode;       // refinement stage: CSNE, CGLS start, CGLS step
+    double *stats;       // [0] ||r||^2, [1] last step / ||c||, [2] CGLS alpha, [3] CGLS gamma
     double tol;
     int32_t *status;
     TrsvSync sync;       // flags of the triangular solves

@@ -35,7 +35,7 @@ class GapParams(ctypes.Structure):
 class GapSolveInfo(ctypes.Structure):
     _fields_ = [("device_status", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
                 ("residual_norm2", ctypes.c_double), ("grad_rel", ctypes.c_double),
-                ("est_err", ctypes.c_double)]
+                ("cgls_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class GapTuning(ctypes.Structure):

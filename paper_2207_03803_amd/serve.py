@@ -127,7 +127,7 @@ class Server:
     """Continuous-batching executor over `slots` streams and an HBM budget."""
 
     def __init__(self, pools, slots=8, hbm_budget=96 << 30, precision=gap.GAP_FP64, resident_max=64,
-                 predict_pool=None, big_pool=None, max_refine_iters=20, refine_tol=1e-12):
+                 predict_pool=None, big_pool=None, max_refine_iters=20, refine_tol=1e-12, fp64_fallback=True):
         import torch
 
         self.pools = pools
@@ -137,6 +137,10 @@ class Server:
         self.free = list(range(slots))
         self.arena = Arena(hbm_budget)
         self.precision = precision
+        # a mixed-precision fit whose refinement did not converge (kappa(A) beyond what
+        # the FP32 factor can precondition) is solved again in FP64 in the same slot
+        # and workspace (an FP64 workspace is smaller than a mixed one)
+        self.fp64_fallback = fp64_fallback and precision != gap.GAP_FP64
         self.models = collections.OrderedDict()   # rid -> (XM, c, zeta, d, handle, c_block)
         self.resident_max = resident_max
         self.predict_pool = predict_pool           # (offsets, X) for d=400 predict batches
@@ -217,7 +221,7 @@ class Server:
         st = self.slots[slot]
         m = req.meta
         if req.kind == "fit":
-            h = self._fit_handle(slot, req.spec.d, req.spec.zeta)
+            h = self._fit_handle(slot, req.spec.d, req.spec.zeta, fp64=req.meta.get("fallback", False))
             ws_block, c_block = blocks
             h.bind(self.arena.view(ws_block))
             h.build_knm(m["X"], m["offsets"], m["XM"], m["sigma"])
@@ -236,14 +240,15 @@ class Server:
         ev.record(st)
         return ev, keep
 
-    def _fit_handle(self, slot, d, zeta):
+    def _fit_handle(self, slot, d, zeta, fp64=False):
         """A slot's handle for fits of (d, zeta), created once and reused (a handle
         owns HIP events and a stream: creating and destroying them per request
         would put those calls on the serving path)."""
-        key = ("fit", slot, d, zeta)
+        prec = gap.GAP_FP64 if fp64 else self.precision
+        key = ("fit", slot, d, zeta, prec)
         with self.handles_lock:
             if key not in self.handles:
-                p = gap.params(d, zeta, 1.0, 1e-8, precision=self.precision, **self.refine)
+                p = gap.params(d, zeta, 1.0, 1e-8, precision=prec, **self.refine)
                 self.handles[key] = gap.Handle(p, stream=self.slots[slot])
             return self.handles[key]
 
@@ -269,11 +274,16 @@ class Server:
         ob = self.arena.alloc(8 * req.meta["n"])
         return None if ob is None else (ob,)
 
-    def _finish(self, req, keep, blocks, now):
+    def _finish(self, req, slot, keep, blocks, now):
+        """Complete a request; True when it was sent back to its slot instead."""
         h, out = keep
-        req.done = now
         if req.kind == "fit":
             s, info = h.sync()
+            if s == gap.GAP_ENOCONV and self.fp64_fallback and not req.meta.get("fallback"):
+                req.meta["fallback"] = True
+                self.work[slot].put((req, blocks))
+                return True
+            req.done = now
             req.result = out.cpu().numpy()
             req.meta["status"] = s
             # release the workspace (the handle stays with its slot); the weights stay resident as the model
@@ -286,9 +296,11 @@ class Server:
                     break
                 self.arena.release(self.models.pop(victim)[5])
         else:
+            req.done = now
             req.result = out.cpu().numpy()
             self.arena.release(blocks[0])
             self.model_users[req.model] -= 1
+        return False
 
     # ---------------------------------------------------------------- the loop
     def run(self, requests, log=None):
@@ -312,9 +324,9 @@ class Server:
             still = []
             for req, slot, ev, keep, blocks in self.inflight:
                 if ev.query():
-                    self._finish(req, keep, blocks, time.perf_counter() - t0)
-                    self.free.append(slot)
-                    self.n_active -= 1
+                    if not self._finish(req, slot, keep, blocks, time.perf_counter() - t0):
+                        self.free.append(slot)
+                        self.n_active -= 1
                 else:
                     still.append((req, slot, ev, keep, blocks))
             self.inflight = still
@@ -364,6 +376,15 @@ def latency_report(requests):
     big = [r.done - r.arrival for r in requests if r.kind == "fit" and r.done >= 0 and r.spec.n_configs >= 50_000]
     if big:
         out["realistic_fits"] = dict(n=len(big), mean_ms=float(np.mean(big) * 1e3))
+    st = collections.Counter(gap.status_string(r.meta["status"]) for r in requests
+                             if r.kind == "fit" and "status" in r.meta)
+    out["fit_status"] = dict(st)
+    out["fp64_fallbacks"] = sum(1 for r in requests if r.kind == "fit" and r.meta.get("fallback"))
+    bad = [r for r in requests if r.kind == "fit" and r.meta.get("status", 0) != gap.GAP_OK]
+    if bad:
+        out["failed_fits"] = [dict(rid=r.rid, n_configs=r.spec.n_configs, M=r.spec.M, d=r.spec.d, zeta=r.spec.zeta,
+                                   sigma_per_atom=r.spec.sigma_per_atom, status=gap.status_string(r.meta["status"]))
+                              for r in bad[:8]]
     done = [r for r in requests if r.done >= 0]
     if done:
         span = max(r.done for r in done) - min(r.arrival for r in done)

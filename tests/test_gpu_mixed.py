@@ -62,7 +62,38 @@ def test_mixed_refines_to_fp64_accuracy(orc_m, name, args):
     log(f"  {name}: c rel err after 1,2,3,5 steps {['%.1e' % e for e in errs]}; "
         f"converged in {info.refine_iters} steps to {err:.2e} (last |dc|/|c| {info.grad_rel:.1e})")
     assert info.device_status == gap.GAP_OK
+    assert info.cgls_iters == 0  # well within FP32's reach: corrected semi-normal equations alone
     assert err <= TOL_MIXED
+    assert abs(info.residual_norm2 - ref.loss_tail) <= 1e-8 * ref.loss_tail
+
+
+@pytest.mark.parametrize("sigma_per_atom", [1e-4, 3e-5])
+def test_ill_conditioned_fit_moves_to_cgls(orc_m, sigma_per_atom):
+    """M > N_c and a small sigma_E: kappa(A) of 1e7..1e8, where FP32's R makes the
+    corrected semi-normal equations contract slowly or diverge.  The refinement
+    moves to R-preconditioned CGLS and still reaches the oracle's c within the
+    FP64 perturbation bound of the least-squares problem,
+    u (kappa + kappa^2 ||r|| / (||A|| ||c||)) up to a small constant."""
+    from paper_2207_03803_amd import gap
+
+    inp = synth.make_fit_inputs(n_configs=600, atoms=(8, 64), d=128, M=800, seed=7, sigma_per_atom=sigma_per_atom)
+    y = oracle.targets(orc_m, inp, 2)
+    ref = orc_m.fit(inp.X, inp.offsets, inp.XM, inp.sigma, y, 2, jitter=1e-8, keep=True)
+    assert ref.status == 0
+    sv = np.linalg.svd(np.triu(ref.A[:800]), compute_uv=False)  # A's singular values are R's
+    kappa = sv[0] / sv[-1]
+    rn = np.sqrt(ref.loss_tail)
+    cn = np.linalg.norm(ref.c)
+    bound = 32 * (np.finfo(np.float64).eps / 2) * (kappa + kappa ** 2 * rn / (sv[0] * cn))
+    g, (s, info) = _mixed(inp, y, 2, 60, tol=1e-12)
+    c = g.c.cpu().numpy()
+    err = rel(c, ref.c)
+    log(f"  sigma_E/atom {sigma_per_atom:g}: kappa(A) {kappa:.2e}; {info.refine_iters} steps, "
+        f"{info.cgls_iters} of them CGLS; c rel err {err:.2e} (bound {bound:.1e}); last |dc|/|c| {info.grad_rel:.1e}")
+    assert s == gap.GAP_OK
+    assert kappa > 5e6
+    assert info.cgls_iters > 0
+    assert err <= max(bound, TOL_MIXED)
     assert abs(info.residual_norm2 - ref.loss_tail) <= 1e-8 * ref.loss_tail
 
 

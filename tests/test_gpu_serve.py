@@ -86,3 +86,39 @@ def test_served_results_match_alone_and_oracle(served):
             torch.cuda.synchronize()
             h.close()
             assert np.array_equal(out.cpu().numpy(), r.result), r.rid
+
+
+def test_mixed_fit_without_convergence_falls_back_to_fp64():
+    """A mixed-precision fit whose refinement ends in GAP_ENOCONV (here forced by a
+    one-step cap) is solved again in FP64 in its slot: every fit ends GAP_OK with
+    exactly the FP64 result of the same request run alone."""
+    import torch
+
+    from paper_2207_03803_amd import gap, serve, sweep
+
+    reqs = [r for r in serve.make_requests(16, rate=400.0, seed=9, mix=(1.0, 0.0, 0.0), small_scale=0.04)]
+    pools = sweep.make_pools([r.spec for r in reqs], seed=9)
+    srv = serve.Server(pools, slots=2, hbm_budget=4 << 30, precision=gap.GAP_MIXED_FP32, max_refine_iters=1,
+                       refine_tol=1e-15)
+    try:
+        for r in reqs:
+            srv.prepare(r)
+        torch.cuda.synchronize()
+        srv.run(reqs)
+        torch.cuda.synchronize()
+        rep = serve.latency_report(reqs)
+        log(f"  fallback run: {rep['fit_status']}, {rep['fp64_fallbacks']} FP64 re-solves of {len(reqs)} fits")
+        assert all(r.meta["status"] == gap.GAP_OK for r in reqs)
+        assert rep["fp64_fallbacks"] >= 1
+        for r in reqs:
+            m = r.meta
+            h = gap.Handle(gap.params(r.spec.d, r.spec.zeta, 1.0, 1e-8))
+            h.alloc_workspace(r.spec.n_configs, m["X"].shape[0], r.spec.M)
+            h.build_knm(m["X"], m["offsets"], m["XM"], m["sigma"])
+            c = torch.empty(r.spec.M, dtype=torch.float64, device="cuda")
+            h.solve(m["y"], c)
+            h.close()
+            if m.get("fallback"):
+                assert np.array_equal(c.cpu().numpy(), r.result), r.rid
+    finally:
+        serve.close(srv)
