@@ -206,12 +206,23 @@ gap_status gap_stage_times(gap_handle h, float *ms, int n);
  *                 stream the handle owns while the handle's stream updates and
  *                 factors the next block.  The two schedules sum the split-K
  *                 partials of the next block's update over different row chunks,
- *                 so they agree to rounding; each one is deterministic. */
+ *                 so they agree to rounding; each one is deterministic.
+ *   qr_free_cus   look-ahead only: CUs kept free of the trailing-update stream
+ *                 (a HIP CU mask) for the next block's panel chain on the
+ *                 handle's stream; 1 .. 128, -1 = no mask, 0 = automatic (32 in
+ *                 FP64, 8 in mixed precision, when the handle has a stream of
+ *                 its own; no mask beside the legacy default stream).  A masked
+ *                 stream is a blocking one (it orders itself with the legacy
+ *                 default stream), and a captured graph does not keep the mask:
+ *                 pass -1 for handles whose solves are captured.  Takes effect
+ *                 at the next gap_build_knm (which replaces the stream after its
+ *                 last work); results are unchanged. */
 typedef struct gap_tuning {
     int32_t qr_split_wgs;
     int32_t qr_panel;
     int32_t qr_lookahead;
-    int32_t reserved[5];
+    int32_t qr_free_cus;
+    int32_t reserved[4];
 } gap_tuning;
 
 /* Set the handle's launch-shape knobs (host-only; affects later calls).  GAP_EINVAL on

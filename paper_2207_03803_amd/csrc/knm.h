@@ -1,0 +1,52 @@
+// K_NM / K_MM and predict kernel interfaces of the GAP fit library.  Every
+// launcher enqueues on the given stream and returns the launch error
+// (hipSuccess when none).
+#pragma once
+
+#include "common.h"
+
+namespace gap {
+
+// ----------------------------------------------------------------- K_NM / K_MM
+constexpr int KNM_BM = 256;       // atoms per chunk (GEMM rows)
+constexpr int KNM_BN = 64;        // sparse points per tile (GEMM columns)
+constexpr int KNM_CAP = KNM_BM;   // atom capacity of a packed tile
+constexpr int KNM_MAX_SEG = 256;  // configurations per tile
+
+struct KnmArgs {
+    const double *X;           // [rows x d] row-major descriptors
+    const int64_t *offsets;    // [N+1] CSR offsets; nullptr = unit segments (row r is segment r)
+    const int32_t *tile_start; // [n_tiles+1] first position of each tile in cfg_list (from the plan)
+    const int32_t *cfg_list;   // [N] configurations, tile by tile
+    const int32_t *n_tiles_dev;
+    int64_t n_rows_unit;       // unit segments: number of rows
+    const double *XM;          // [M x d] sparse points
+    int64_t M;
+    int d, zeta;
+    double sw2;                // sigma_w^2
+    const double *sigma;       // [N] or nullptr: the segment sum is divided by sigma
+    double *out;               // column-major: out[col * ldo + row_off + segment]
+    int64_t ldo, row_off;
+    double jitter;             // unit segments: added where segment == column
+    int upper_only;            // unit segments: write 0 where segment > column
+    int64_t n_ct, total_pad;   // filled by launch_knm
+    int32_t *status;
+};
+
+int64_t knm_max_tiles(int64_t N, int64_t n_atoms);
+int64_t knm_plan_chunks(int64_t N);
+// Plan arrays (device): tile_start [max_tiles + 1], n_tiles [1], cfg_list [N],
+// lstart [n_chunks * 2049], lcount [n_chunks] (n_chunks = knm_plan_chunks(N)).
+struct KnmPlan {
+    int32_t *tile_start, *n_tiles, *cfg_list, *lstart, *lcount;
+};
+hipError_t launch_plan_tiles(const int64_t *offsets, int64_t N, int64_t n_atoms, const KnmPlan &p, int64_t max_tiles,
+                             int32_t *status, hipStream_t s);
+hipError_t launch_knm(KnmArgs a, int64_t max_tiles, hipStream_t s);
+
+// --------------------------------------------------------------------- predict
+hipError_t launch_predict(const double *X, int64_t n_atoms, const int64_t *offsets, int64_t N,
+                          const double *XM, int64_t M, int d, int zeta, double sw2, const double *c,
+                          double *y, hipStream_t s);
+
+}  // namespace gap

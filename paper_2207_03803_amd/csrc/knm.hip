@@ -3,7 +3,7 @@
 // fused into the epilogue (Sec. Theory: definition of K_MN; the upper block of
 // A; Eqs. 1-2).  The n_atoms x M matrix of atom-level covariances is never
 // written to HBM.
-#include "kernels.h"
+#include "knm.h"
 
 namespace gap {
 

@@ -40,7 +40,7 @@ class GapSolveInfo(ctypes.Structure):
 
 class GapTuning(ctypes.Structure):
     _fields_ = [("qr_split_wgs", ctypes.c_int32), ("qr_panel", ctypes.c_int32), ("qr_lookahead", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("qr_free_cus", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class GapLayoutInfo(ctypes.Structure):
@@ -206,12 +206,13 @@ class Handle:
         off = lay.tau - self.ws.data_ptr()
         return self.ws[off:off + 8 * lay.M].view(torch.float64)
 
-    def set_tuning(self, qr_split_wgs=0, qr_panel=0, qr_lookahead=0):
-        """qr_lookahead: 0 automatic, 1 off, 2 on."""
+    def set_tuning(self, qr_split_wgs=0, qr_panel=0, qr_lookahead=0, qr_free_cus=0):
+        """qr_lookahead: 0 automatic, 1 off, 2 on; qr_free_cus: CUs kept from the look-ahead stream."""
         t = GapTuning()
         t.qr_split_wgs = int(qr_split_wgs)
         t.qr_panel = int(qr_panel)
         t.qr_lookahead = int(qr_lookahead)
+        t.qr_free_cus = int(qr_free_cus)
         _check(lib().gap_set_tuning(self.h, ctypes.byref(t)), "gap_set_tuning")
 
     def set_model(self, XM):

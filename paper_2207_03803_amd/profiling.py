@@ -23,7 +23,7 @@ import os
 import sqlite3
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KNM_SOURCES = ("knm.hip", "common.h", "kernels.h")
+KNM_SOURCES = ("knm.hip", "knm.h", "common.h")
 COPY_BYTES = 8 << 27  # one copy launch of bench.py --copy-calibration, each direction
 
 

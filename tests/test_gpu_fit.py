@@ -186,6 +186,32 @@ def test_qr_schedules_and_panels_agree(orc_m, panel, lookahead):
     assert np.array_equal(c1, c2)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_lookahead_free_cus_leave_results_bitwise_unchanged(orc_m, precision):
+    """Keeping CUs free of the look-ahead stream (a CU mask; automatic beside a
+    stream of the handle's own) changes only where kernels run: c is bitwise the
+    unmasked look-ahead's, at the oracle's weights."""
+    import torch
+
+    inp, y, ref = _case(orc_m, 1500, (16, 64), 160, 390, 3, 21)
+    outs = {}
+    with torch.cuda.stream(torch.cuda.Stream()):
+        g = GpuFit(inp.X, inp.offsets, inp.XM, inp.sigma, y, 3, precision=precision)
+        for free in (-1, 16, 0, 64, -1):
+            g.h.set_tuning(qr_lookahead=2, qr_free_cus=free)
+            g.build()
+            g.h.solve(g.y, g.c, info=False)
+            s, info = g.h.sync()
+            assert s == 0
+            outs.setdefault(free, []).append(g.c.cpu().numpy())
+    base = outs[-1][0]
+    log(f"  precision {precision}: c rel err {rel(base, ref.c):.2e}")
+    assert rel(base, ref.c) <= (TOL_C if precision == 0 else 1e-8)
+    for free, cs in outs.items():
+        for c in cs:
+            assert np.array_equal(c, base), free
+
+
 def test_atom_order_within_configurations(orc_m):
     """Permuting the atoms inside every configuration changes only the order of
     the segment sums (K_NM within a few ulps) and leaves c at the oracle's."""
