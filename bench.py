@@ -177,6 +177,9 @@ def main():
         p = gap.params(d, zeta, w["sigma_w"], w["jitter"], precision=precision, flags=gap.GAP_FLAG_TIMING,
                        max_refine_iters=30, refine_tol=1e-12)
         h = gap.Handle(p)
+        # one fit on a stream of its own and nothing on the legacy stream meanwhile:
+        # keep CUs free of the QR look-ahead stream for the panel chain
+        h.set_tuning(qr_free_cus=8 if precision == gap.GAP_MIXED_FP32 else 32)
         h.alloc_workspace(N, n_atoms, M)
         if y is None:
             # targets: model prediction with c_true (through the library) plus noise

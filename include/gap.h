@@ -207,16 +207,17 @@ gap_status gap_stage_times(gap_handle h, float *ms, int n);
  *                 factors the next block.  The two schedules sum the split-K
  *                 partials of the next block's update over different row chunks,
  *                 so they agree to rounding; each one is deterministic.
- *   qr_free_cus   look-ahead only: CUs kept free of the trailing-update stream
- *                 (a HIP CU mask) for the next block's panel chain on the
- *                 handle's stream; 1 .. 128, -1 = no mask, 0 = automatic (32 in
- *                 FP64, 8 in mixed precision, when the handle has a stream of
- *                 its own; no mask beside the legacy default stream).  A masked
- *                 stream is a blocking one (it orders itself with the legacy
- *                 default stream), and a captured graph does not keep the mask:
- *                 pass -1 for handles whose solves are captured.  Takes effect
- *                 at the next gap_build_knm (which replaces the stream after its
- *                 last work); results are unchanged. */
+ *   qr_free_cus   look-ahead only: 1 .. 128 CUs kept free of the trailing-update
+ *                 stream (a HIP CU mask) for the next block's panel chain on the
+ *                 handle's stream; 0 = no mask (default).  At N = 1e5, M = 1e4
+ *                 on MI355X: FP64 QR 731 -> 659 ms with 32, FP32-storage QR
+ *                 480 -> 456 ms with 8.  A masked stream is a blocking one: it
+ *                 orders itself with the legacy default stream, so use it for a
+ *                 handle on a stream of its own in a process that keeps work off
+ *                 the legacy stream meanwhile; a captured graph does not keep
+ *                 the mask.  Takes effect at the next gap_build_knm (which
+ *                 replaces the stream after its last work); results are
+ *                 unchanged. */
 typedef struct gap_tuning {
     int32_t qr_split_wgs;
     int32_t qr_panel;

@@ -260,22 +260,10 @@ static bool use_lookahead(gap_handle h)
 }
 
 // The look-ahead's stream and events, created the first time a fit needs them.
-// CUs kept free of the look-ahead stream: the tuning value, or automatically
-// (measured at the realistic workload: FP64 QR 731 -> 659 ms with 32 free CUs,
-// FP32-storage QR 480 -> 456 ms with 8) when the handle has a stream of its
-// own; beside the legacy default stream a masked (blocking) stream would
-// serialise with it.
-static int free_cus_for(gap_handle h)
-{
-    const int t = h->tuning.qr_free_cus;
-    if (t < 0)
-        return 0;
-    if (t > 0)
-        return t;
-    if (!h->stream)
-        return 0;
-    return h->p.precision == GAP_MIXED_FP32 ? 8 : 32;
-}
+// CUs kept free of the look-ahead stream (0: an unmasked stream).  Opt-in: a
+// masked stream is a blocking one, which serialises with any work on the
+// legacy default stream, e.g. other threads' copies in a serving loop.
+static int free_cus_for(gap_handle h) { return h->tuning.qr_free_cus; }
 
 // The look-ahead stream.  With free CUs it is created with a CU mask that
 // leaves them to the handle's stream (the panel chain of the next block); such
@@ -613,7 +601,7 @@ gap_status gap_set_tuning(gap_handle h, const gap_tuning *t)
         return GAP_EINVAL;
     if (t->qr_lookahead < 0 || t->qr_lookahead > 2)
         return GAP_EINVAL;
-    if (t->qr_free_cus < -1 || t->qr_free_cus > 128)
+    if (t->qr_free_cus < 0 || t->qr_free_cus > 128)
         return GAP_EINVAL;
     h->tuning = *t;
     return GAP_OK;

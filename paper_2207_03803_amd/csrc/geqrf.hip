@@ -610,6 +610,8 @@ __global__ __launch_bounds__(256) void qr_tcombine_kernel(QrWork w, const double
 
 // C[r][q] -= sum_p Y[r][p] W[p][q] for rows j0.. and columns c0 .. c0+nt; the
 // tile is computed transposed so that consecutive lanes write consecutive rows.
+// The accumulators start from the C tile (its loads in flight with the first
+// operand slices) and take -W, so the epilogue is a plain store.
 __global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt)
 {
     __shared__ double lds[2 * US::STAGE];
@@ -621,8 +623,20 @@ __global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0,
     const double *A = w.A;
     const int64_t lda = w.lda, m = w.m, ldW = w.ldw;
     const double *W = w.W;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave / US::WN, wn = wave % US::WN;
+    double *C = w.A + c0 * lda;
     d4 acc[US::FM][US::FN];
-    zero_acc<US>(acc);
+#pragma unroll
+    for (int i = 0; i < US::FM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < US::FN; ++jj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t q = q0 + acc_row<US>(wm, i, lane, e);
+                const int64_t r = r0 + acc_col<US>(wn, jj, lane, e);
+                acc[i][jj][e] = (r < m && q < nt) ? C[q * lda + r] : 0.0;
+            }
     const bool masked = r0 < j0 + pw;  // the row block meets Y's unit upper triangle
     constexpr int VA = US::BM * US::BK / US::NT, VB = US::BN * US::BK / US::NT;
     auto fa = [&](int qi, int64_t p, double (&v)[VA]) {
@@ -633,10 +647,13 @@ __global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0,
                 v[e] = 0.0;
         } else if (q + VA <= nt) {
             load_run(W + p * ldW + q, v);
+#pragma unroll
+            for (int e = 0; e < VA; ++e)
+                v[e] = -v[e];
         } else {
 #pragma unroll
             for (int e = 0; e < VA; ++e)
-                v[e] = (q + e < nt) ? W[p * ldW + q + e] : 0.0;
+                v[e] = (q + e < nt) ? -W[p * ldW + q + e] : 0.0;
         }
     };
     auto fb = [&](int ri, int64_t p, double (&v)[VB]) {
@@ -654,19 +671,19 @@ __global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0,
         }
     };
     gemm_tile_runs<US, false, false, true>(acc, lds, pw, fa, fb);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave / US::WN, wn = wave % US::WN;
-    double *C = w.A + c0 * lda;
+    // recompute the store addresses rather than keep the loads' live through the product
+    int64_t q0s = q0, r0s = r0;
+    asm volatile("" : "+s"(q0s), "+s"(r0s));
 #pragma unroll
     for (int i = 0; i < US::FM; ++i)
 #pragma unroll
         for (int jj = 0; jj < US::FN; ++jj)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int64_t q = q0 + acc_row<US>(wm, i, lane, e);
-                const int64_t r = r0 + acc_col<US>(wn, jj, lane, e);
+                const int64_t q = q0s + acc_row<US>(wm, i, lane, e);
+                const int64_t r = r0s + acc_col<US>(wn, jj, lane, e);
                 if (r < m && q < nt)
-                    C[q * lda + r] -= acc[i][jj][e];
+                    C[q * lda + r] = acc[i][jj][e];
             }
 }
 
@@ -755,8 +772,20 @@ __global__ __launch_bounds__(256, 2) void qr_update32_kernel(QrWork w, int64_t j
     const float *A = w.A32;
     const int64_t lda = w.lda, m = w.m, ldW = w.ldw;
     const float *W = w.W32;
-    f4 acc[US32::FM][US32::FN];
-    zero_acc32<US32>(acc);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave / US32::WN, wn = wave % US32::WN;
+    float *C = w.A32 + c0 * lda;
+    f4 acc[US32::FM][US32::FN];  // starts from the C tile; the product takes -W
+#pragma unroll
+    for (int i = 0; i < US32::FM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < US32::FN; ++jj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t q = q0 + acc32_row<US32>(wm, i, lane, e);
+                const int64_t r = r0 + acc32_col<US32>(wn, jj, lane, e);
+                acc[i][jj][e] = (r < m && q < nt) ? C[q * lda + r] : 0.0f;
+            }
     const bool masked = r0 < j0 + pw;
     constexpr int VA = US32::BM * US32::BK / US32::NT, VB = US32::BN * US32::BK / US32::NT;
     auto fa = [&](int qi, int64_t p, float (&v)[VA]) {
@@ -767,10 +796,13 @@ __global__ __launch_bounds__(256, 2) void qr_update32_kernel(QrWork w, int64_t j
                 v[e] = 0.0f;
         } else if (q + VA <= nt) {
             load_run(W + p * ldW + q, v);
+#pragma unroll
+            for (int e = 0; e < VA; ++e)
+                v[e] = -v[e];
         } else {
 #pragma unroll
             for (int e = 0; e < VA; ++e)
-                v[e] = (q + e < nt) ? W[p * ldW + q + e] : 0.0f;
+                v[e] = (q + e < nt) ? -W[p * ldW + q + e] : 0.0f;
         }
     };
     auto fb = [&](int ri, int64_t p, float (&v)[VB]) {
@@ -788,19 +820,18 @@ __global__ __launch_bounds__(256, 2) void qr_update32_kernel(QrWork w, int64_t j
         }
     };
     gemm_tile_runs32<US32, false, false>(acc, lds, pw, fa, fb);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave / US32::WN, wn = wave % US32::WN;
-    float *C = w.A32 + c0 * lda;
+    int64_t q0s = q0, r0s = r0;
+    asm volatile("" : "+s"(q0s), "+s"(r0s));
 #pragma unroll
     for (int i = 0; i < US32::FM; ++i)
 #pragma unroll
         for (int jj = 0; jj < US32::FN; ++jj)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int64_t q = q0 + acc32_row<US32>(wm, i, lane, e);
-                const int64_t r = r0 + acc32_col<US32>(wn, jj, lane, e);
+                const int64_t q = q0s + acc32_row<US32>(wm, i, lane, e);
+                const int64_t r = r0s + acc32_col<US32>(wn, jj, lane, e);
                 if (r < m && q < nt)
-                    C[q * lda + r] -= acc[i][jj][e];
+                    C[q * lda + r] = acc[i][jj][e];
             }
 }
 

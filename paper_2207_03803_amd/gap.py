@@ -207,7 +207,7 @@ class Handle:
         return self.ws[off:off + 8 * lay.M].view(torch.float64)
 
     def set_tuning(self, qr_split_wgs=0, qr_panel=0, qr_lookahead=0, qr_free_cus=0):
-        """qr_lookahead: 0 automatic, 1 off, 2 on; qr_free_cus: CUs kept from the look-ahead stream."""
+        """qr_lookahead: 0 automatic, 1 off, 2 on; qr_free_cus: CUs kept from the look-ahead stream (0 none)."""
         t = GapTuning()
         t.qr_split_wgs = int(qr_split_wgs)
         t.qr_panel = int(qr_panel)

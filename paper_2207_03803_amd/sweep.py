@@ -141,8 +141,8 @@ class Sweep:
             p = gap.params(s.d, s.zeta, 1.0, 1e-8, precision=precision, max_refine_iters=max_refine_iters,
                            refine_tol=refine_tol)
             f.handle = gap.Handle(p, stream=self.streams[stream_of[s.idx]])
-            # fits are captured into graphs, which do not keep a stream's CU mask
-            f.handle.set_tuning(qr_split_wgs=split_wgs, qr_lookahead=lookahead, qr_free_cus=-1)
+            if split_wgs or lookahead:
+                f.handle.set_tuning(qr_split_wgs=split_wgs, qr_lookahead=lookahead)
             f.ws = f.handle.alloc_workspace(s.n_configs, n_atoms, s.M)
             f.c = torch.empty(s.M, dtype=torch.float64, device="cuda")
             self.fits.append(f)
