@@ -194,14 +194,15 @@ class Server:
         if req.kind == "fit":
             X, offsets, XM, sigma, c_true, noise = self._fit_inputs(req.spec)
             p = gap.params(req.spec.d, req.spec.zeta, 1.0, 1e-8, precision=self.precision, **self.refine)
-            h = gap.Handle(p)
-            h.alloc_workspace(req.spec.n_configs, X.shape[0], req.spec.M)
-            h.build_knm(X, offsets, XM, sigma)
+            # targets: the model's prediction with c_true (a predict-only handle) plus noise
+            h = gap.Handle(gap.params(req.spec.d, req.spec.zeta, 1.0, 1e-8))
+            h.set_model(XM)
             y = torch.empty(req.spec.n_configs, dtype=torch.float64, device="cuda")
             h.predict(X, offsets, torch.from_numpy(c_true).cuda(), y)
-            y += sigma * torch.from_numpy(noise).cuda()
             torch.cuda.synchronize()
             h.close()
+            y += sigma * torch.from_numpy(noise).cuda()
+            torch.cuda.synchronize()
             req.meta = dict(X=X, offsets=offsets, XM=XM, sigma=sigma, y=y)
             req.footprint = gap.workspace_bytes(p, req.spec.n_configs, X.shape[0], req.spec.M) + 8 * req.spec.M + 512
         else:
@@ -303,10 +304,12 @@ class Server:
         return False
 
     # ---------------------------------------------------------------- the loop
-    def run(self, requests, log=None):
-        """Serve `requests` (sorted by arrival).  Returns the requests, filled."""
+    def run(self, requests, log=None, log_every=100):
+        """Serve `requests` (sorted by arrival).  Returns the requests, filled.
+        `log(msg)`, when given, hears of every `log_every` completed requests."""
         pending = collections.deque()
         todo = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        n_done = 0
         t0 = time.perf_counter()
         while todo or pending or self.n_active:
             now = time.perf_counter() - t0
@@ -327,6 +330,9 @@ class Server:
                     if not self._finish(req, slot, keep, blocks, time.perf_counter() - t0):
                         self.free.append(slot)
                         self.n_active -= 1
+                        n_done += 1
+                        if log and n_done % log_every == 0:
+                            log(f"[serve] {n_done}/{len(requests)} requests done at {time.perf_counter() - t0:.1f} s")
                 else:
                     still.append((req, slot, ev, keep, blocks))
             self.inflight = still
