@@ -462,7 +462,7 @@ __global__ __launch_bounds__(256, 2) void qr_wpart_kernel(QrWork w, int64_t j0, 
             }
         }
     };
-    gemm_tile_runs<WS, true, true, true>(acc, lds, rhi - rlo, fa, fb);
+    gemm_tile_runs<WS, true, true, false>(acc, lds, rhi - rlo, fa, fb);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WS::WN, wn = wave % WS::WN;
     double *P = w.wpart + ch * OB * w.wp_ld;
@@ -532,6 +532,31 @@ __global__ __launch_bounds__(256) void qr_wred_kernel(QrWork w, const double *__
             s += tc[r] * Pm[r][ql];
         Wout[p * w.ldw + q] = (TW)s;
     }
+}
+
+// Sum of the split-K partials over the row chunks into chunk 0's slot, one
+// (p, q) element per thread (qr_wred_kernel's fixed order: even chunks, odd
+// chunks, then the two sums).  qr_wred_kernel then reads a single chunk: its
+// own reduction runs on only ceil(nt / 64) workgroups, two for the next
+// block's columns.
+__global__ __launch_bounds__(256) void qr_psum_kernel(QrWork w, int pw, int64_t nch, int64_t nt)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)pw * nt)
+        return;
+    const int64_t p = e / nt, q = e % nt;
+    double *src = w.wpart + p * w.wp_ld + q;
+    const int64_t step = (int64_t)OB * w.wp_ld;
+    double s0 = 0.0, s1 = 0.0;
+    int64_t ch = 0;
+#pragma unroll 4
+    for (; ch + 1 < nch; ch += 2) {
+        s0 += src[ch * step];
+        s1 += src[(ch + 1) * step];
+    }
+    if (ch < nch)
+        s0 += src[ch * step];
+    src[0] = s0 + s1;
 }
 
 // G = Y_A^T Y_B from the chunk partials (grid 16: one entry per thread, rows
@@ -670,7 +695,7 @@ __global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0,
                 v[e] = ypanel(A, lda, m, j0, pw, r + e, (int)p);
         }
     };
-    gemm_tile_runs<US, false, false, true>(acc, lds, pw, fa, fb);
+    gemm_tile_runs<US, false, false, false>(acc, lds, pw, fa, fb);
     // recompute the store addresses rather than keep the loads' live through the product
     int64_t q0s = q0, r0s = r0;
     asm volatile("" : "+s"(q0s), "+s"(r0s));
@@ -898,6 +923,11 @@ static void apply_block(const QrWork &w, int64_t j0, int pw, const double *Tm, i
     int64_t chunk, nch;
     chunking(rows, ncb, chunk, nch, w.split_wgs > 0 ? w.split_wgs : 2048);
     launch_wpart<T>(w, j0, pw, c0, nt, 0, j0, chunk, ncb, nch, s);
+    if (nch > 1) {
+        hipLaunchKernelGGL(qr_psum_kernel, dim3((unsigned)(((int64_t)pw * nt + 255) / 256)), dim3(256), 0, s, w, pw,
+                           nch, nt);
+        nch = 1;
+    }
     if constexpr (sizeof(T) == 8) {
         hipLaunchKernelGGL(qr_wred_kernel<double>, dim3((unsigned)((nt + 63) / 64)), dim3(256), 0, s, w, Tm, tld,
                            pw, nch, nt, w.W);
