@@ -72,7 +72,7 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, bool mixed)
     L.off_cq_G = take(sizeof(double) * 4 * QR_NB * QR_NB);
     L.off_cq_R = take(sizeof(double) * 4 * QR_NB * QR_NB);
     L.off_T2 = take(sizeof(double) * 4 * QR_NB * QR_NB);
-    L.off_wpart_s = take(sizeof(double) * (size_t)qr_max_chunks() * 2 * QR_NB * 2 * QR_NB);
+    L.off_wpart_s = take(sizeof(double) * (size_t)qr_max_chunks_s() * 2 * QR_NB * 2 * QR_NB);
     L.off_W_s = take(sizeof(double) * 4 * QR_NB * QR_NB);
     L.off_W32_s = take(sizeof(float) * 4 * QR_NB * QR_NB);
     if (mixed) {

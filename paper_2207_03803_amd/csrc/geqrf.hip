@@ -29,9 +29,11 @@ constexpr int TILE = TR * NB;  // doubles per tile
 constexpr int NPART = 8;           // threads per tile column
 constexpr int TS_NT = NB * NPART;  // threads of the TSQR kernels
 constexpr int SLOTS = TR / NPART;  // rows held per thread (row = NPART * slot + part)
-constexpr int64_t MAX_CHUNKS = 64;
+constexpr int64_t MAX_CHUNKS = 64;     // row chunks of the split-K products into the bulk buffer
+constexpr int64_t MAX_CHUNKS_S = 256;  // into the look-ahead's small buffer (at most 2 QR_NB columns)
 
 int64_t qr_max_chunks() { return MAX_CHUNKS; }
+int64_t qr_max_chunks_s() { return MAX_CHUNKS_S; }
 
 TsqrTree tsqr_tree(int64_t m)
 {
@@ -861,11 +863,11 @@ __global__ __launch_bounds__(256, 2) void qr_update32_kernel(QrWork w, int64_t j
 }
 
 // Split of rows [r0, m) into chunks for the split-K products.
-static void chunking(int64_t rows, int64_t ncb, int64_t &chunk, int64_t &nch, int64_t target = 2048)
+static void chunking(int64_t rows, int64_t ncb, int64_t &chunk, int64_t &nch, int64_t cap, int64_t target = 2048)
 {
     nch = (target + ncb - 1) / ncb;
-    if (nch > MAX_CHUNKS)
-        nch = MAX_CHUNKS;
+    if (nch > cap)
+        nch = cap;
     chunk = (rows + nch - 1) / nch;
     chunk = (chunk + 15) & ~int64_t(15);
     if (chunk < 256)
@@ -921,7 +923,7 @@ static void apply_block(const QrWork &w, int64_t j0, int pw, const double *Tm, i
     const int64_t rows = w.m - j0;
     const int64_t ncb = (nt + WS::BN - 1) / WS::BN;
     int64_t chunk, nch;
-    chunking(rows, ncb, chunk, nch, w.split_wgs > 0 ? w.split_wgs : 2048);
+    chunking(rows, ncb, chunk, nch, w.max_chunks, w.split_wgs > 0 ? w.split_wgs : 2048);
     launch_wpart<T>(w, j0, pw, c0, nt, 0, j0, chunk, ncb, nch, s);
     if (nch > 1) {
         hipLaunchKernelGGL(qr_psum_kernel, dim3((unsigned)(((int64_t)pw * nt + 255) / 256)), dim3(256), 0, s, w, pw,
@@ -963,7 +965,7 @@ static int factor_block(const QrWork &w, int64_t J, double *Tout, const double *
     factor_panel<T>(w, jb, pwb, Tb, s);
     const int64_t rows = w.m - jb;
     int64_t chunk, nch;
-    chunking(rows, 1, chunk, nch);
+    chunking(rows, 1, chunk, nch, w.max_chunks);
     launch_wpart<T>(w, J, pwa, jb, (int64_t)pwb, 1, jb, chunk, 1, nch, s);
     hipLaunchKernelGGL(qr_gsum_kernel, dim3(NB * NB / 256), dim3(256), 0, s, w, pwb, nch, w.cq_G);
     hipLaunchKernelGGL(qr_tcombine_kernel, dim3(1), dim3(256), 0, s, w, (const double *)w.cq_G, Tout);
@@ -975,22 +977,24 @@ static int factor_block(const QrWork &w, int64_t J, double *Tout, const double *
 template <class T>
 static void geqrf(const QrWork &w, hipStream_t s, const QrAsync *la)
 {
-    if (!la) {
-        for (int64_t J = 0; J < w.n; J += OB) {
-            const double *Tm;
-            int tld;
-            const int pw = factor_block<T>(w, J, w.T, &Tm, &tld, s);
-            apply_block<T>(w, J, pw, Tm, tld, J + pw, w.ncols - (J + pw), s);
-        }
-        return;
-    }
-    // main-stream view: small scratch for the next block's update and the panels
+    // small-scratch view for the narrow products (at most two blocks' columns):
+    // the next block's update and the work inside a block
     QrWork wm = w;
     wm.wpart = w.wpart_s;
     wm.wp_ld = OB;
     wm.W = w.W_s;
     wm.W32 = w.W32_s;
     wm.ldw = OB;
+    wm.max_chunks = MAX_CHUNKS_S;  // more row chunks keep the panel chain's GEMMs wide
+    if (!la) {
+        for (int64_t J = 0; J < w.n; J += OB) {
+            const double *Tm;
+            int tld;
+            const int pw = factor_block<T>(wm, J, w.T, &Tm, &tld, s);
+            apply_block<T>(w, J, pw, Tm, tld, J + pw, w.ncols - (J + pw), s);
+        }
+        return;
+    }
     double *Tbuf[2] = {w.T, w.T2};
     (void)hipEventRecord(la->fork, s);
     (void)hipStreamWaitEvent(la->side, la->fork, 0);

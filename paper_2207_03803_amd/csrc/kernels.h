@@ -44,7 +44,7 @@ struct QrWork {
     int64_t wp_ld;    // row stride of the partials (>= the widest column range updated)
     double *T;        // [2 QR_NB * 2 QR_NB] compact-WY T of the current two-panel block (row-major)
     double *T2;       // second T buffer (look-ahead: the side stream reads one while the next is formed)
-    double *wpart_s;  // [max_chunks * 2 QR_NB * 2 QR_NB] partials of the main stream's small updates
+    double *wpart_s;  // [qr_max_chunks_s() * 2 QR_NB * 2 QR_NB] partials of the main stream's small updates
     double *W_s;      // [2 QR_NB * 2 QR_NB] W of the main stream's small updates (ld 2 QR_NB)
     float *W32_s;     // FP32 version
     double *Tin;      // [2 * QR_NB * QR_NB] T of the block's two panels (row-major, ld QR_NB)
@@ -70,6 +70,7 @@ constexpr int64_t CQ_MAX_CHUNKS = 256;
 void cqr_panel_f64(const QrWork &w, int64_t j0, int pw, double *Tout, hipStream_t s);
 void cqr_panel_f32(const QrWork &w, int64_t j0, int pw, double *Tout, hipStream_t s);
 int64_t qr_max_chunks();
+int64_t qr_max_chunks_s();
 // Look-ahead schedule: the trailing update of block k runs on `side` while
 // `s` updates block k+1's columns and factors them.  Null: one stream.
 struct QrAsync {
