@@ -241,7 +241,7 @@ def main():
         h = gap.Handle(p)
         # one fit on a stream of its own and nothing on the legacy stream meanwhile:
         # keep CUs free of the QR look-ahead stream for the panel chain
-        h.set_tuning(qr_free_cus=8 if precision == gap.GAP_MIXED_FP32 else 32)
+        h.set_tuning(qr_free_cus=32)
         h.alloc_workspace(N, n_atoms, M)
         if y is None:
             # targets: model prediction with c_true (through the library) plus noise

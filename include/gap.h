@@ -210,8 +210,7 @@ gap_status gap_stage_times(gap_handle h, float *ms, int n);
  *   qr_free_cus   look-ahead only: 1 .. 128 CUs kept free of the trailing-update
  *                 stream (a HIP CU mask) for the next block's panel chain on the
  *                 handle's stream; 0 = no mask (default).  At N = 1e5, M = 1e4
- *                 on MI355X: FP64 QR 731 -> 659 ms with 32, FP32-storage QR
- *                 480 -> 456 ms with 8.  A masked stream is a blocking one: it
+ *                 on MI355X, 32 is best in both precisions.  A masked stream is a blocking one: it
  *                 orders itself with the legacy default stream, so use it for a
  *                 handle on a stream of its own in a process that keeps work off
  *                 the legacy stream meanwhile; a captured graph does not keep
