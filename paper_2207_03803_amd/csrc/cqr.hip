@@ -147,30 +147,43 @@ DEV void gram_lds(const double *__restrict__ G4, int pw, double shift_coef, doub
 }
 
 // Cholesky S = R^T R in place (one wave; lane l owns column l, S[i][l] for
-// i <= l): on exit S holds R (zeros below the diagonal).  A pivot that is not
-// positive is replaced by 1 and reported through the return value.
+// i <= l, in registers; row k of each step is shared through LDS): on exit S
+// holds R (zeros below the diagonal).  A pivot that is not positive is
+// replaced by 1 and reported through the return value.
 DEV bool chol_lds(double (&S)[CB][CB + 1], double *rrow)
 {
     const int l = threadIdx.x & 63;
+    double x[CB];
+#pragma unroll
+    for (int i = 0; i < CB; ++i)
+        x[i] = S[i][l];
     bool ok = true;
+#pragma unroll
     for (int k = 0; k < CB; ++k) {
-        const double dkk = S[k][k];
+        if (l == k)
+            rrow[k] = x[k];
+        wave_sync();
+        const double dkk = rrow[k];
         double rkk = sqrt(dkk);
         if (!(dkk > 0.0) || !(rkk < INFINITY)) {
             ok = false;
             rkk = 1.0;
         }
-        const double rkj = (l > k) ? S[k][l] / rkk : (l == k ? rkk : 0.0);
+        const double rkj = (l > k) ? x[k] / rkk : (l == k ? rkk : 0.0);
+        wave_sync();
         rrow[l] = rkj;
         wave_sync();
-        S[k][l] = rkj;
-#pragma unroll 4
-        for (int i = k + 1; i <= l; ++i)
-            S[i][l] -= rrow[i] * rkj;
+        x[k] = rkj;
+        if (l > k) {
+#pragma unroll
+            for (int i = k + 1; i < CB; ++i)
+                x[i] -= rrow[i] * rkj;  // rows past l are below the diagonal: zeroed below
+        }
         wave_sync();
     }
-    for (int i = l + 1; i < CB; ++i)
-        S[i][l] = 0.0;
+#pragma unroll
+    for (int i = 0; i < CB; ++i)
+        S[i][l] = (i <= l) ? x[i] : 0.0;
     wave_sync();
     return ok;
 }

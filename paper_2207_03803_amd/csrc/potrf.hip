@@ -10,88 +10,100 @@ namespace gap {
 constexpr int CNB = CHOL_NB;
 constexpr int CLD = CNB + 1;
 
-// Factor the kb x kb diagonal block starting at (k0, k0).
-__global__ __launch_bounds__(256) void chol_diag_kernel(double *U, int64_t ld, int64_t k0, int kb,
-                                                        int32_t *status)
+// Order the LDS accesses of one wave's lanes (no workgroup barrier: one wave).
+DEV void lane_sync()
 {
-    __shared__ double S[CNB * CLD];
-    __shared__ int failed;
-    const int t = threadIdx.x;
-    for (int idx = t; idx < kb * kb; idx += 256) {
-        const int r = idx % kb, c = idx / kb;
-        S[r * CLD + c] = (r <= c) ? U[(k0 + c) * ld + k0 + r] : 0.0;
-    }
-    if (t == 0)
-        failed = 0;
-    __syncthreads();
-    for (int j = 0; j < kb; ++j) {
-        if (t == 0) {
-            double piv = S[j * CLD + j];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Factor the kb x kb diagonal block starting at (k0, k0) on one wave: lane c
+// holds column c of the block in registers (rows and columns past kb padded
+// with the identity), and row j of each step is shared through LDS.  Each
+// element sees the right-looking order: U[j][j] = sqrt(pivot), U[j][c] /=
+// U[j][j], then U[r][c] -= U[j][r] U[j][c].
+__global__ __launch_bounds__(64) void chol_diag_kernel(double *U, int64_t ld, int64_t k0, int kb, int32_t *status)
+{
+    __shared__ double row[CNB];
+    const int c = threadIdx.x;
+    double x[CNB];
+    const double *col = U + (k0 + c) * ld + k0;
+#pragma unroll
+    for (int r = 0; r < CNB; ++r)
+        x[r] = (c < kb) ? ((r <= c) ? col[r] : 0.0) : (r == c ? 1.0 : 0.0);
+#pragma unroll
+    for (int j = 0; j < CNB; ++j) {
+        if (c == j) {
+            double piv = x[j];
             if (!(piv > 0.0) || !isfinite(piv)) {
-                if (!failed)
-                    set_status(status, DST_ENOTPD);
-                failed = 1;
-                piv = 1.0;  // keep the (discarded) rest finite
+                set_status(status, DST_ENOTPD);  // the first failure is kept
+                piv = 1.0;                       // keep the (discarded) rest finite
             }
-            S[j * CLD + j] = sqrt(piv);
+            x[j] = sqrt(piv);
+            row[j] = x[j];
         }
-        __syncthreads();
-        const double dj = S[j * CLD + j];
-        for (int c = j + 1 + t; c < kb; c += 256)
-            S[j * CLD + c] /= dj;
-        __syncthreads();
-        // trailing: S[r][c] -= U[j][r] U[j][c] for j < r <= c
-        const int w = kb - j - 1;
-        for (int idx = t; idx < w * w; idx += 256) {
-            const int r = j + 1 + idx % w, c = j + 1 + idx / w;
-            if (r <= c)
-                S[r * CLD + c] -= S[j * CLD + r] * S[j * CLD + c];
+        lane_sync();
+        const double dj = row[j];
+        if (c > j) {
+            x[j] = x[j] / dj;
+            row[c] = x[j];
         }
-        __syncthreads();
+        lane_sync();
+        if (c > j) {
+            const double xj = x[j];
+#pragma unroll
+            for (int r = j + 1; r < CNB; ++r)
+                x[r] -= row[r] * xj;  // rows past c are below the diagonal: never stored
+        }
+        lane_sync();
     }
-    for (int idx = t; idx < kb * kb; idx += 256) {
-        const int r = idx % kb, c = idx / kb;
-        U[(k0 + c) * ld + k0 + r] = (r <= c) ? S[r * CLD + c] : 0.0;
+    if (c < kb) {
+        double *out = U + (k0 + c) * ld + k0;
+#pragma unroll
+        for (int r = 0; r < CNB; ++r)
+            if (r < kb)
+                out[r] = (r <= c) ? x[r] : 0.0;
     }
 }
 
 // Block row: X = U_kk^-T B for the 64-column block `blockIdx.x` right of the
-// diagonal block (forward substitution, right-looking, in LDS).
-__global__ __launch_bounds__(256) void chol_trsm_kernel(double *U, int64_t ld, int64_t k0, int kb,
-                                                        int64_t n)
+// diagonal block, one wave per block and one column per lane (each column's
+// forward substitution is independent: no barriers), U_kk staged in LDS.
+__global__ __launch_bounds__(64) void chol_trsm_kernel(double *U, int64_t ld, int64_t k0, int kb, int64_t n)
 {
     __shared__ double Ukk[CNB * CLD];
-    __shared__ double B[CNB * CLD];
-    const int t = threadIdx.x;
+    const int c = threadIdx.x;
     const int64_t c0 = k0 + kb + (int64_t)blockIdx.x * CNB;
     const int cw = (int)((n - c0) < CNB ? (n - c0) : CNB);
-    for (int idx = t; idx < kb * kb; idx += 256) {
-        const int r = idx % kb, c = idx / kb;
-        Ukk[r * CLD + c] = U[(k0 + c) * ld + k0 + r];
+    {
+        const double *col = U + (k0 + c) * ld + k0;
+#pragma unroll
+        for (int r = 0; r < CNB; ++r)
+            Ukk[r * CLD + c] = (c < kb && r <= c) ? col[r] : 0.0;
     }
-    for (int idx = t; idx < kb * cw; idx += 256) {
-        const int r = idx % kb, c = idx / kb;
-        B[r * CLD + c] = U[(c0 + c) * ld + k0 + r];
-    }
-    __syncthreads();
-    for (int i = 0; i < kb; ++i) {
-        const double di = Ukk[i * CLD + i];
-        for (int c = t; c < cw; c += 256)
-            B[i * CLD + c] /= di;
-        __syncthreads();
-        const int rows = kb - i - 1;
-        for (int idx = t; idx < rows * cw; idx += 256) {
-            const int r = i + 1 + idx % rows, c = idx / rows;
-            B[r * CLD + c] -= Ukk[i * CLD + r] * B[i * CLD + c];
+    lane_sync();
+    if (c >= cw)
+        return;
+    double x[CNB];
+    double *bc = U + (c0 + c) * ld + k0;
+#pragma unroll
+    for (int r = 0; r < CNB; ++r)
+        x[r] = (r < kb) ? bc[r] : 0.0;
+#pragma unroll
+    for (int i = 0; i < CNB; ++i) {
+        if (i < kb) {
+            x[i] = x[i] / Ukk[i * CLD + i];
+#pragma unroll
+            for (int r = i + 1; r < CNB; ++r)
+                x[r] -= Ukk[i * CLD + r] * x[i];  // U_kk rows past kb are zero
         }
-        __syncthreads();
     }
-    for (int idx = t; idx < kb * cw; idx += 256) {
-        const int r = idx % kb, c = idx / kb;
-        U[(c0 + c) * ld + k0 + r] = B[r * CLD + c];
-    }
+#pragma unroll
+    for (int r = 0; r < CNB; ++r)
+        if (r < kb)
+            bc[r] = x[r];
 }
-
 using SS = TileShape<128, 128, 16, 2, 2>;
 
 // Trailing update of the upper triangle: A[r][c] -= sum_p U[k0+p][r] U[k0+p][c]
@@ -145,12 +157,12 @@ hipError_t launch_potrf_upper(double *U, int64_t ld, int64_t n, int32_t *status,
 {
     for (int64_t k0 = 0; k0 < n; k0 += CNB) {
         const int kb = (int)((n - k0) < CNB ? (n - k0) : CNB);
-        hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, s, U, ld, k0, kb, status);
+        hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(64), 0, s, U, ld, k0, kb, status);
         const int64_t rest = n - k0 - kb;
         if (rest <= 0)
             break;
         const int64_t nbr = (rest + CNB - 1) / CNB;
-        hipLaunchKernelGGL(chol_trsm_kernel, dim3((unsigned)nbr), dim3(256), 0, s, U, ld, k0, kb, n);
+        hipLaunchKernelGGL(chol_trsm_kernel, dim3((unsigned)nbr), dim3(64), 0, s, U, ld, k0, kb, n);
         const int64_t nt = (rest + SS::BM - 1) / SS::BM;
         const int64_t pairs = nt * (nt + 1) / 2;
         hipLaunchKernelGGL(chol_syrk_kernel, dim3((unsigned)pairs), dim3(256), 0, s, U, ld, k0, kb, n);
