@@ -221,6 +221,7 @@ __global__ __launch_bounds__(256) void cqr_chol_kernel(const double *__restrict_
         if (Rprev) {
             // entry (i, l) of R Rprev: sum over p in [i, l] of R[i][p] Rprev[p][l]
             double v = 0.0;
+#pragma unroll 8
             for (int p = i; p <= l; ++p)
                 v += S[i][p] * Pv[p][l];
             Rprod[e] = v;
@@ -343,6 +344,7 @@ __global__ __launch_bounds__(256) void cqr_top_kernel(QrWork w, int64_t j0, int 
     for (int idx = t, cnt = 0; idx < CB * CB; idx += 256, ++cnt) {
         const int r = idx / CB, c = idx % CB;
         double v = 0.0;
+#pragma unroll 8
         for (int p = r; p <= c; ++p)
             v += R3[r][p] * X[p][c];
         rv[cnt] = v;
@@ -373,9 +375,11 @@ __global__ __launch_bounds__(256) void cqr_top_kernel(QrWork w, int64_t j0, int 
         const int r = idx / CB, c = idx % CB;
         // T = -U S Y1^-T:  T[r][c] = -sum_{p=r..c} U[r][p] s_p (Y1^-1)[c][p]
         double tv = 0.0;
-        if (r < pw && c < pw && r <= c)
+        if (r < pw && c < pw && r <= c) {
+#pragma unroll 8
             for (int p = r; p <= c; ++p)
                 tv -= B[r][p] * sg[p] * X[c][p];
+        }
         Tout[idx] = tv;
         if (r < pw && c < pw) {
             const double out = (r <= c) ? sg[r] * rv[cnt] : B[r][c];
@@ -386,9 +390,11 @@ __global__ __launch_bounds__(256) void cqr_top_kernel(QrWork w, int64_t j0, int 
         // U R3 (upper) for the row pass below the top block; identity beyond pw
         double ur = 0.0;
         if (r < pw && c < pw) {
-            if (r <= c)
+            if (r <= c) {
+#pragma unroll 8
                 for (int p = r; p <= c; ++p)
                     ur += B[r][p] * R3[p][c];
+            }
         } else if (r == c) {
             ur = 1.0;
         }
