@@ -309,34 +309,48 @@ __global__ __launch_bounds__(256) void cqr_top_kernel(QrWork w, int64_t j0, int 
         set_status(w.status, DST_ERANK);
     __syncthreads();
     if (wave == 0) {
-        // Q_top = Q2_top R3^-1 in place, lane = row
-        const int r = lane;
-        for (int c = 0; c < pw; ++c) {
-            double v = B[r][c];
-#pragma unroll 4
-            for (int i = 0; i < c; ++i)
-                v -= B[r][i] * R3[i][c];
-            B[r][c] = v / R3[c][c];
-        }
-        wave_sync();
-        // LU of Q_top - S (s_k = -sign(pivot), sign(0) = +1), lane = row
-        for (int k = 0; k < pw; ++k) {
-            const double d = B[k][k];
-            const double sk = (d >= 0.0) ? -1.0 : 1.0;
-            const double piv = d - sk;
-            if (lane > k && lane < pw) {
-                const double li = B[lane][k] / piv;
-                B[lane][k] = li;
-#pragma unroll 4
-                for (int c = k + 1; c < pw; ++c)
-                    B[lane][c] -= li * B[k][c];
+        // lane = row of Q_top, held in registers (columns past pw are zero)
+        double q[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            q[c] = B[lane][c];
+        // Q_top = Q2_top R3^-1
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            if (c < pw) {
+                double v = q[c];
+#pragma unroll
+                for (int i = 0; i < c; ++i)
+                    v -= q[i] * R3[i][c];
+                q[c] = v / R3[c][c];
             }
-            if (lane == k) {
-                B[k][k] = piv;
-                sg[k] = sk;
-            }
-            wave_sync();
         }
+        // LU of Q_top - S (s_k = -sign(pivot), sign(0) = +1); row k read from lane k
+#pragma unroll
+        for (int k = 0; k < CB; ++k) {
+            if (k < pw) {
+                const double d = readlane_d(q[k], k);
+                const double sk = (d >= 0.0) ? -1.0 : 1.0;
+                const double piv = d - sk;
+                const bool below = lane > k && lane < pw;
+                const double li = below ? q[k] / piv : 0.0;
+#pragma unroll
+                for (int c = k + 1; c < CB; ++c) {
+                    const double u = readlane_d(q[c], k);
+                    if (below)
+                        q[c] -= li * u;
+                }
+                if (below)
+                    q[k] = li;
+                if (lane == k) {
+                    q[k] = piv;
+                    sg[k] = sk;
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            B[lane][c] = q[c];
     }
     __syncthreads();
     // Rc = R3 (R2 R1), upper, into registers (X is reused below)
