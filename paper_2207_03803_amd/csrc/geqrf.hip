@@ -403,6 +403,28 @@ DEV bool update_tile(int64_t n_rb, int64_t n_cb, int64_t &rb, int64_t &cb)
     return true;
 }
 
+// Row-block split of a trailing update: PART 0 every row block, 1 the interior
+// ones (1 .. n_rb - 2: full rows, below Y's unit triangle, loaded without
+// checks), 2 the two edge ones (0 and n_rb - 1).
+template <int PART>
+DEV bool update_tile_part(int64_t n_rb, int64_t n_cb, int64_t &rb, int64_t &cb)
+{
+    if constexpr (PART == 1) {
+        if (!update_tile(n_rb - 2, n_cb, rb, cb))
+            return false;
+        rb += 1;
+    } else if constexpr (PART == 2) {
+        if (!update_tile(n_rb > 1 ? 2 : 1, n_cb, rb, cb))
+            return false;
+        if (rb == 1)
+            rb = n_rb - 1;
+    } else {
+        if (!update_tile(n_rb, n_cb, rb, cb))
+            return false;
+    }
+    return true;
+}
+
 constexpr int OB = 2 * NB;                 // outer block: two TSQR panels
 using WS = TileShape<OB, 128, 16, 2, 2>;   // P = Y^T C over a row chunk
 using US = TileShape<128, 128, 16, 2, 2>;  // C^T -= W^T Y^T (rows of C along the MFMA N axis)
@@ -639,11 +661,12 @@ __global__ __launch_bounds__(256) void qr_tcombine_kernel(QrWork w, const double
 // tile is computed transposed so that consecutive lanes write consecutive rows.
 // The accumulators start from the C tile (its loads in flight with the first
 // operand slices) and take -W, so the epilogue is a plain store.
+template <int PART>
 __global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt)
 {
     __shared__ double lds[2 * US::STAGE];
     int64_t rb, cb;
-    if (!update_tile((w.m - j0 + US::BN - 1) / US::BN, (nt + US::BM - 1) / US::BM, rb, cb))
+    if (!update_tile_part<PART>((w.m - j0 + US::BN - 1) / US::BN, (nt + US::BM - 1) / US::BM, rb, cb))
         return;
     const int64_t q0 = cb * US::BM;
     const int64_t r0 = j0 + rb * US::BN;
@@ -662,7 +685,7 @@ __global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0,
             for (int e = 0; e < 4; ++e) {
                 const int64_t q = q0 + acc_row<US>(wm, i, lane, e);
                 const int64_t r = r0 + acc_col<US>(wn, jj, lane, e);
-                acc[i][jj][e] = (r < m && q < nt) ? C[q * lda + r] : 0.0;
+                acc[i][jj][e] = ((PART == 1 || r < m) && q < nt) ? C[q * lda + r] : 0.0;
             }
     const bool masked = r0 < j0 + pw;  // the row block meets Y's unit upper triangle
     constexpr int VA = US::BM * US::BK / US::NT, VB = US::BN * US::BK / US::NT;
@@ -689,7 +712,7 @@ __global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0,
 #pragma unroll
             for (int e = 0; e < VB; ++e)
                 v[e] = 0.0;
-        } else if (!masked && r + VB <= m) {
+        } else if (PART == 1 || (!masked && r + VB <= m)) {
             load_run(A + (j0 + p) * lda + r, v);
         } else {
 #pragma unroll
@@ -709,7 +732,7 @@ __global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0,
             for (int e = 0; e < 4; ++e) {
                 const int64_t q = q0s + acc_row<US>(wm, i, lane, e);
                 const int64_t r = r0s + acc_col<US>(wn, jj, lane, e);
-                if (r < m && q < nt)
+                if ((PART == 1 || r < m) && q < nt)
                     C[q * lda + r] = acc[i][jj][e];
             }
 }
@@ -788,11 +811,12 @@ __global__ __launch_bounds__(256, 2) void qr_wpart32_kernel(QrWork w, int64_t j0
             }
 }
 
+template <int PART>
 __global__ __launch_bounds__(256, 2) void qr_update32_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt)
 {
     __shared__ float lds[2 * US32::STAGE];
     int64_t rb, cb;
-    if (!update_tile((w.m - j0 + US32::BN - 1) / US32::BN, (nt + US32::BM - 1) / US32::BM, rb, cb))
+    if (!update_tile_part<PART>((w.m - j0 + US32::BN - 1) / US32::BN, (nt + US32::BM - 1) / US32::BM, rb, cb))
         return;
     const int64_t q0 = cb * US32::BM;
     const int64_t r0 = j0 + rb * US32::BN;
@@ -811,7 +835,7 @@ __global__ __launch_bounds__(256, 2) void qr_update32_kernel(QrWork w, int64_t j
             for (int e = 0; e < 4; ++e) {
                 const int64_t q = q0 + acc32_row<US32>(wm, i, lane, e);
                 const int64_t r = r0 + acc32_col<US32>(wn, jj, lane, e);
-                acc[i][jj][e] = (r < m && q < nt) ? C[q * lda + r] : 0.0f;
+                acc[i][jj][e] = ((PART == 1 || r < m) && q < nt) ? C[q * lda + r] : 0.0f;
             }
     const bool masked = r0 < j0 + pw;
     constexpr int VA = US32::BM * US32::BK / US32::NT, VB = US32::BN * US32::BK / US32::NT;
@@ -838,7 +862,7 @@ __global__ __launch_bounds__(256, 2) void qr_update32_kernel(QrWork w, int64_t j
 #pragma unroll
             for (int e = 0; e < VB; ++e)
                 v[e] = 0.0f;
-        } else if (!masked && r + VB <= m) {
+        } else if (PART == 1 || (!masked && r + VB <= m)) {
             load_run(A + (j0 + p) * lda + r, v);
         } else {
 #pragma unroll
@@ -857,7 +881,7 @@ __global__ __launch_bounds__(256, 2) void qr_update32_kernel(QrWork w, int64_t j
             for (int e = 0; e < 4; ++e) {
                 const int64_t q = q0s + acc32_row<US32>(wm, i, lane, e);
                 const int64_t r = r0s + acc32_col<US32>(wn, jj, lane, e);
-                if (r < m && q < nt)
+                if ((PART == 1 || r < m) && q < nt)
                     C[q * lda + r] = acc[i][jj][e];
             }
 }
@@ -933,15 +957,25 @@ static void apply_block(const QrWork &w, int64_t j0, int pw, const double *Tm, i
     if constexpr (sizeof(T) == 8) {
         hipLaunchKernelGGL(qr_wred_kernel<double>, dim3((unsigned)((nt + 63) / 64)), dim3(256), 0, s, w, Tm, tld,
                            pw, nch, nt, w.W);
-        const int64_t tiles = ((rows + US::BN - 1) / US::BN) * ((nt + US::BM - 1) / US::BM);
-        hipLaunchKernelGGL(qr_update_kernel, dim3((unsigned)((tiles + 7) & ~int64_t(7))), dim3(256), 0, s, w, j0, pw,
-                           c0, nt);
+        const int64_t nrb = (rows + US::BN - 1) / US::BN, ncb_u = (nt + US::BM - 1) / US::BM;
+        auto grid = [](int64_t tiles) { return dim3((unsigned)((tiles + 7) & ~int64_t(7))); };
+        if (nrb > 2) {  // interior row blocks without checks, then the two edge ones
+            hipLaunchKernelGGL(qr_update_kernel<1>, grid((nrb - 2) * ncb_u), dim3(256), 0, s, w, j0, pw, c0, nt);
+            hipLaunchKernelGGL(qr_update_kernel<2>, grid(2 * ncb_u), dim3(256), 0, s, w, j0, pw, c0, nt);
+        } else {
+            hipLaunchKernelGGL(qr_update_kernel<0>, grid(nrb * ncb_u), dim3(256), 0, s, w, j0, pw, c0, nt);
+        }
     } else {
         hipLaunchKernelGGL(qr_wred_kernel<float>, dim3((unsigned)((nt + 63) / 64)), dim3(256), 0, s, w, Tm, tld,
                            pw, nch, nt, w.W32);
-        const int64_t tiles = ((rows + US32::BN - 1) / US32::BN) * ((nt + US32::BM - 1) / US32::BM);
-        hipLaunchKernelGGL(qr_update32_kernel, dim3((unsigned)((tiles + 7) & ~int64_t(7))), dim3(256), 0, s, w, j0,
-                           pw, c0, nt);
+        const int64_t nrb = (rows + US32::BN - 1) / US32::BN, ncb_u = (nt + US32::BM - 1) / US32::BM;
+        auto grid = [](int64_t tiles) { return dim3((unsigned)((tiles + 7) & ~int64_t(7))); };
+        if (nrb > 2) {
+            hipLaunchKernelGGL(qr_update32_kernel<1>, grid((nrb - 2) * ncb_u), dim3(256), 0, s, w, j0, pw, c0, nt);
+            hipLaunchKernelGGL(qr_update32_kernel<2>, grid(2 * ncb_u), dim3(256), 0, s, w, j0, pw, c0, nt);
+        } else {
+            hipLaunchKernelGGL(qr_update32_kernel<0>, grid(nrb * ncb_u), dim3(256), 0, s, w, j0, pw, c0, nt);
+        }
     }
 }
 
