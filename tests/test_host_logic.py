@@ -1,0 +1,148 @@
+"""Host-side logic of the sweep, serving loop and benchmark that runs without a
+GPU: request and sweep generation, the arena allocator, the latency report,
+the serving summary and the host LAPACK comparator."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2207_03803_amd import gap, serve, sweep
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_sweep_recipe_ranges_and_determinism():
+    r = sweep.SWEEP_RECIPE
+    a = sweep.make_sweep(seed=3)
+    b = sweep.make_sweep(seed=3)
+    assert a == b and len(a) == r["n_fits"]
+    for s in a:
+        assert r["n_configs"][0] <= s.n_configs <= r["n_configs"][1]
+        assert r["M"][0] <= s.M <= r["M"][1]
+        assert s.d in r["ds"] and s.zeta in r["zetas"] and s.sigma_per_atom in r["sigmas"]
+    assert sweep.make_sweep(seed=4) != a
+    # the tuning-table bucket of the committed table is the recipe's
+    assert sweep.bucket(sweep.make_sweep(seed=0)) in sweep.load_table()
+
+
+def test_requests_follow_the_mix_and_arrive_in_order():
+    reqs = serve.make_requests(2000, rate=10.0, seed=1)
+    t = np.array([r.arrival for r in reqs])
+    assert np.all(np.diff(t) > 0)
+    kinds = [r.kind for r in reqs]
+    big = sum(1 for r in reqs if r.kind == "fit" and r.spec.n_configs == 100_000)
+    small = sum(1 for r in reqs if r.kind == "fit") - big
+    assert abs(small / len(reqs) - 0.70) < 0.04
+    assert abs(big / len(reqs) - 0.05) < 0.02
+    assert abs(kinds.count("predict") / len(reqs) - 0.25) < 0.04
+    assert all(1 <= r.n_configs <= 4096 for r in reqs if r.kind == "predict")
+    # mean inter-arrival time of a Poisson process at rate 10/s
+    assert abs(np.mean(np.diff(t)) - 0.1) < 0.01
+    again = serve.make_requests(2000, rate=10.0, seed=1)
+    assert [(r.kind, r.arrival) for r in again] == [(r.kind, r.arrival) for r in reqs]
+
+
+def _host_arena(nbytes):
+    """An Arena whose bookkeeping runs on the host (no device buffer)."""
+    a = object.__new__(serve.Arena)
+    a.size = nbytes
+    a.free = [(0, nbytes)]
+    a.used = 0
+    return a
+
+
+def test_arena_first_fit_alignment_and_coalescing():
+    a = _host_arena(1 << 20)
+    x = a.alloc(1)
+    y = a.alloc(300)
+    assert x == (0, 256) and y == (256, 512)
+    a.release(x)
+    z = a.alloc(200)  # first fit reuses the hole at 0
+    assert z == (0, 256)
+    a.release(z)
+    a.release(y)
+    assert a.free == [(0, 1 << 20)] and a.used == 0
+    assert a.alloc((1 << 20) + 1) is None
+
+
+def test_arena_random_sequences_never_overlap():
+    rng = np.random.default_rng(11)
+    a = _host_arena(64 << 20)
+    live = []
+    for _ in range(4000):
+        if live and rng.random() < 0.45:
+            a.release(live.pop(int(rng.integers(len(live)))))
+        else:
+            blk = a.alloc(int(rng.integers(1, 2 << 20)))
+            if blk is not None:
+                live.append(blk)
+        spans = sorted(live)
+        for (o1, n1), (o2, _) in zip(spans, spans[1:]):
+            assert o1 + n1 <= o2
+        assert all(o % 256 == 0 and n % 256 == 0 for o, n in live)
+        assert a.used == sum(n for _, n in live)
+        assert a.used + sum(n for _, n in a.free) == a.size
+    for blk in live:
+        a.release(blk)
+    assert a.free == [(0, 64 << 20)]
+
+
+def test_latency_report_counts_and_nearest_rank_percentiles():
+    reqs = []
+    for i in range(100):
+        spec = sweep.FitSpec(i, 400, 1000, 500, 2, 1e-3, i)
+        r = serve.Request(i, "fit", arrival=float(i), spec=spec)
+        r.admitted = r.arrival + 0.01
+        r.done = r.arrival + 0.001 * (i + 1)  # latencies 1 .. 100 ms
+        r.meta = {"status": gap.GAP_OK}
+        if i % 10 == 0:
+            r.meta["fallback"] = True
+        reqs.append(r)
+    bad = serve.Request(100, "fit", arrival=100.0, spec=sweep.FitSpec(100, 128, 10, 20, 3, 1e-4, 0))
+    bad.admitted, bad.done, bad.meta = 100.0, 100.5, {"status": gap.GAP_ENOCONV}
+    reqs.append(bad)
+    for i in range(10):
+        p = serve.Request(200 + i, "predict", arrival=float(i), n_configs=7)
+        p.admitted, p.done = p.arrival, p.arrival + 0.002
+        reqs.append(p)
+    rep = serve.latency_report(reqs)
+    assert rep["fit"]["n"] == 101 and rep["predict"]["n"] == 10
+    assert rep["fit"]["p50_ms"] == pytest.approx(51.0)
+    assert rep["fit"]["p99_ms"] == pytest.approx(100.0)
+    assert rep["predict"]["p50_ms"] == pytest.approx(2.0)
+    assert rep["fit_status"] == {"ok": 100, gap.status_string(gap.GAP_ENOCONV): 1}
+    assert rep["fp64_fallbacks"] == 10
+    assert rep["failed_fits"] == [dict(rid=100, n_configs=10, M=20, d=128, zeta=3, sigma_per_atom=1e-4,
+                                       status=gap.status_string(gap.GAP_ENOCONV))]
+
+
+def _bench():
+    sys.path.insert(0, ROOT)
+    import bench
+
+    return bench
+
+
+def test_serving_summary_renders_every_point():
+    bench = _bench()
+    pt = lambda load, rate: {"load": load, "arrival_rate_per_s": rate, "fit": {"p50_ms": 10, "p99_ms": 90},
+                             "predict": {"p50_ms": 2, "p99_ms": 20}, "fits_per_s": 3.0,
+                             "fit_status": {"ok": 5}, "fp64_fallbacks": 1, "all_fits_ok": True}
+    out = {"n_requests_per_point": 1000, "mix": "m", "points": [pt(0.5, 5.0), pt(1.0, 10.0)],
+           "saturation": {"requests_per_s": 10.0, "fits_per_s": 7.0, "fit_status": {"ok": 9},
+                          "fp64_fallbacks": 0, "all_fits_ok": True}}
+    md = bench.serve_sweep_md(out, None)
+    assert "--serve-requests 1000" in md
+    assert "| 0.5 | 5.00 | 10 | 90 | 2 | 20 | 3.00 | - |" in md
+    assert "| load 1.0 | ok: 5 | 1 |" in md and "| saturation | ok: 9 | 0 |" in md
+    assert md.rstrip().endswith("True.")
+
+
+def test_lapack_comparator_on_the_tiny_workload():
+    bench = _bench()
+    r = bench.lapack_baseline("tiny_fp64")
+    assert r["kind"] == "lapack" and r["unit"] == "s" and r["cores"] >= 1
+    assert np.isfinite(r["value"]) and r["value"] > 0
+    json.dumps(r)
