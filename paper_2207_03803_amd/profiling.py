@@ -97,6 +97,8 @@ def traffic(args):
         "traffic_bytes_per_launch": rd + wr,
     }
     json.dump(rec, open(args.out + ".json", "w"), indent=1)
+    d_ff, d_fw = os.path.dirname(args.fit_fetch), os.path.dirname(args.fit_write)
+    d_cf, d_cw = os.path.dirname(args.copy_fetch), os.path.dirname(args.copy_write)
     md = f"""# HBM traffic of `knm_kernel`, realistic workload (K_NM launch)
 
 Counters from two `rocprofv3 --pmc` passes over one benchmark fit, then the same two
@@ -105,10 +107,10 @@ calibrate what each counter reads for a known byte count.  Produced by
 `python -m paper_2207_03803_amd.profiling traffic ...` from these runs (repository root,
 one MI355X):
 ```
-rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fit_fetch -o fit -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --forms none
-rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_fit_write -o fit -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --forms none
-rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_copy_fetch -o copy -- python3 bench.py --copy-calibration
-rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_copy_write -o copy -- python3 bench.py --copy-calibration
+rocprofv3 --pmc FETCH_SIZE --output-format csv -d {d_ff} -o fit -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --forms none
+rocprofv3 --pmc WRITE_SIZE --output-format csv -d {d_fw} -o fit -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --forms none
+rocprofv3 --pmc FETCH_SIZE --output-format csv -d {d_cf} -o copy -- python3 bench.py --copy-calibration
+rocprofv3 --pmc WRITE_SIZE --output-format csv -d {d_cw} -o copy -- python3 bench.py --copy-calibration
 ```
 
 | quantity | counter reading (KiB) | calibration factor | bytes |
