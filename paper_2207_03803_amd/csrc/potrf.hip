@@ -106,21 +106,25 @@ __global__ __launch_bounds__(64) void chol_trsm_kernel(double *U, int64_t ld, in
 }
 using SS = TileShape<128, 128, 16, 2, 2>;
 
-// Trailing update of the upper triangle: A[r][c] -= sum_p U[k0+p][r] U[k0+p][c]
-// for k1 <= r <= c < n, one 128 x 128 tile per workgroup (upper tiles only).
-__global__ __launch_bounds__(256) void chol_syrk_kernel(double *U, int64_t ld, int64_t k0, int kb,
-                                                        int64_t n)
+// Trailing update of the upper triangle: A[r][c] -= sum_{p < kb} U[k0+p][r] U[k0+p][c]
+// for k1 <= r <= c < n and r < rlim, one 128 x 128 tile per workgroup.  With
+// rlim = n the tiles are the upper ones of the trailing triangle (enumerated
+// column by column); with rlim < n (a strip of at most 128 rows) they are one
+// row of tiles across the columns.
+__global__ __launch_bounds__(256) void chol_syrk_kernel(double *U, int64_t ld, int64_t k0, int kb, int64_t k1,
+                                                        int64_t rlim, int64_t n)
 {
     __shared__ double lds[2 * SS::STAGE];
-    const int64_t k1 = k0 + kb;
-    // linear id -> (ti, tj), ti <= tj, enumerated column by column
     const int64_t L = blockIdx.x;
-    int64_t tj = (int64_t)((sqrt(8.0 * (double)L + 1.0) - 1.0) * 0.5);
-    while ((tj + 1) * (tj + 2) / 2 <= L)
-        ++tj;
-    while (tj * (tj + 1) / 2 > L)
-        --tj;
-    const int64_t ti = L - tj * (tj + 1) / 2;
+    int64_t ti = 0, tj = L;
+    if (rlim >= n) {  // linear id -> (ti, tj), ti <= tj
+        tj = (int64_t)((sqrt(8.0 * (double)L + 1.0) - 1.0) * 0.5);
+        while ((tj + 1) * (tj + 2) / 2 <= L)
+            ++tj;
+        while (tj * (tj + 1) / 2 > L)
+            --tj;
+        ti = L - tj * (tj + 1) / 2;
+    }
     const int64_t r0 = k1 + ti * SS::BM, c0 = k1 + tj * SS::BN;
 
     // The tile is computed transposed, acc(c, r), so that consecutive lanes
@@ -148,24 +152,48 @@ __global__ __launch_bounds__(256) void chol_syrk_kernel(double *U, int64_t ld, i
             for (int e = 0; e < 4; ++e) {
                 const int64_t c = c0 + acc_row<SS>(wm, i, lane, e);
                 const int64_t r = r0 + acc_col<SS>(wn, j, lane, e);
-                if (r <= c && c < n)
+                if (r <= c && c < n && r < rlim)
                     U[c * ld + r] -= acc[i][j][e];
             }
 }
 
+static void syrk(double *U, int64_t ld, int64_t k0, int kb, int64_t k1, int64_t rlim, int64_t n, hipStream_t s)
+{
+    const int64_t nc = (n - k1 + SS::BN - 1) / SS::BN;
+    const int64_t tiles = (rlim >= n) ? nc * (nc + 1) / 2 : nc;
+    hipLaunchKernelGGL(chol_syrk_kernel, dim3((unsigned)tiles), dim3(256), 0, s, U, ld, k0, kb, k1, rlim, n);
+}
+
+// Steps are taken in pairs: block k's rows update only block k + 1's rows
+// (a thin strip), block k + 1 is factored, then one trailing update of depth
+// 128 applies both blocks to everything below (half the trailing passes, each
+// twice as deep).
 hipError_t launch_potrf_upper(double *U, int64_t ld, int64_t n, int32_t *status, hipStream_t s)
 {
-    for (int64_t k0 = 0; k0 < n; k0 += CNB) {
-        const int kb = (int)((n - k0) < CNB ? (n - k0) : CNB);
+    auto factor_row = [&](int64_t k0, int kb) {
         hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(64), 0, s, U, ld, k0, kb, status);
         const int64_t rest = n - k0 - kb;
+        if (rest > 0)
+            hipLaunchKernelGGL(chol_trsm_kernel, dim3((unsigned)((rest + CNB - 1) / CNB)), dim3(64), 0, s, U, ld, k0,
+                               kb, n);
+        return rest;
+    };
+    int64_t k0 = 0;
+    while (k0 < n) {
+        const int kb = (int)((n - k0) < CNB ? (n - k0) : CNB);
+        const int64_t rest = factor_row(k0, kb);
         if (rest <= 0)
             break;
-        const int64_t nbr = (rest + CNB - 1) / CNB;
-        hipLaunchKernelGGL(chol_trsm_kernel, dim3((unsigned)nbr), dim3(64), 0, s, U, ld, k0, kb, n);
-        const int64_t nt = (rest + SS::BM - 1) / SS::BM;
-        const int64_t pairs = nt * (nt + 1) / 2;
-        hipLaunchKernelGGL(chol_syrk_kernel, dim3((unsigned)pairs), dim3(256), 0, s, U, ld, k0, kb, n);
+        const int64_t k1 = k0 + kb;
+        if (rest <= CNB) {  // one block left
+            syrk(U, ld, k0, kb, k1, n, n, s);
+            k0 = k1;
+            continue;
+        }
+        syrk(U, ld, k0, kb, k1, k1 + CNB, n, s);  // block k's rows into block k + 1's rows
+        factor_row(k1, CNB);
+        syrk(U, ld, k0, kb + CNB, k1 + CNB, n, n, s);  // both blocks into the rest
+        k0 = k1 + CNB;
     }
     return hipGetLastError();
 }
