@@ -273,6 +273,7 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
     __shared__ int32_t sstart[KNM_MAX_SEG + 1];  // atom offset of each segment within the tile
     __shared__ int64_t sbase[KNM_MAX_SEG];       // first atom (row of X) of each segment
     __shared__ int32_t srow[KNM_MAX_SEG];        // output row of each segment
+    __shared__ double ssig[KNM_MAX_SEG];         // row scale sigma of each segment (1 without one)
     __shared__ double carry[KNM_BN];
 
     // The grid is sized for the largest possible tile count; the remap uses
@@ -303,6 +304,7 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
             sstart[tid + 1] = tid + 1;
             sbase[tid] = r0 + tid;
             srow[tid] = (int32_t)(r0 + tid);
+            ssig[tid] = a.sigma ? a.sigma[r0 + tid] : 1.0;
         }
         n_at = n_seg;
     } else {
@@ -315,6 +317,7 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
             sz = a.offsets[cfg + 1] - lo;
             sbase[tid] = lo;
             srow[tid] = cfg;
+            ssig[tid] = a.sigma ? a.sigma[cfg] : 1.0;
         }
         // inclusive scan of the segment sizes (one per thread)
         int32_t *scan = reinterpret_cast<int32_t *>(lds);
@@ -344,7 +347,7 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
                 v = 0.0;
         }
         if (a.sigma)
-            v = v / a.sigma[row];
+            v = v / ssig[s];
         a.out[colg * a.ldo + a.row_off + row] = v;
     };
 
@@ -411,8 +414,30 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
                     const int64_t colg = col0 + p * EPC + c;
                     if (colg >= a.M)
                         continue;
+                    // in atom order; the loads of 8 (then 4) rows are issued together
+                    const int a1 = sstart[s + 1];
+                    int r = sstart[s];
                     double sum = 0.0;
-                    for (int r = sstart[s]; r < sstart[s + 1]; ++r)
+                    for (; r + 8 <= a1; r += 8) {
+                        double v[8];
+#pragma unroll
+                        for (int k = 0; k < 8; ++k)
+                            v[k] = E[(r + k) * EPLD + c];
+#pragma unroll
+                        for (int k = 0; k < 8; ++k)
+                            sum += v[k];
+                    }
+                    if (r + 4 <= a1) {
+                        double v[4];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            v[k] = E[(r + k) * EPLD + c];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            sum += v[k];
+                        r += 4;
+                    }
+                    for (; r < a1; ++r)
                         sum += E[r * EPLD + c];
                     emit(s, colg, sum);
                 }
