@@ -273,7 +273,6 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
     __shared__ int32_t sstart[KNM_MAX_SEG + 1];  // atom offset of each segment within the tile
     __shared__ int64_t sbase[KNM_MAX_SEG];       // first atom (row of X) of each segment
     __shared__ int32_t srow[KNM_MAX_SEG];        // output row of each segment
-    __shared__ double ssig[KNM_MAX_SEG];         // row scale sigma of each segment (1 without one)
     __shared__ double carry[KNM_BN];
 
     // The grid is sized for the largest possible tile count; the remap uses
@@ -304,7 +303,6 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
             sstart[tid + 1] = tid + 1;
             sbase[tid] = r0 + tid;
             srow[tid] = (int32_t)(r0 + tid);
-            ssig[tid] = a.sigma ? a.sigma[r0 + tid] : 1.0;
         }
         n_at = n_seg;
     } else {
@@ -317,7 +315,6 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
             sz = a.offsets[cfg + 1] - lo;
             sbase[tid] = lo;
             srow[tid] = cfg;
-            ssig[tid] = a.sigma ? a.sigma[cfg] : 1.0;
         }
         // inclusive scan of the segment sizes (one per thread)
         int32_t *scan = reinterpret_cast<int32_t *>(lds);
@@ -337,7 +334,9 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
     }
     __syncthreads();
 
-    auto emit = [&](int s, int64_t colg, double sum) {
+    // Row scale of segment s (loaded where its latency can overlap other work).
+    auto sig = [&](int s) { return a.sigma ? a.sigma[srow[s]] : 1.0; };
+    auto emit = [&](int s, int64_t colg, double sum, double sg) {
         const int64_t row = srow[s];
         double v = sum;
         if (unit) {
@@ -347,7 +346,7 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
                 v = 0.0;
         }
         if (a.sigma)
-            v = v / ssig[s];
+            v = v / sg;
         a.out[colg * a.ldo + a.row_off + row] = v;
     };
 
@@ -356,7 +355,7 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
             const int s = item % n_seg, c = item / n_seg;
             const int64_t colg = col0 + c;
             if (colg < a.M)
-                emit(s, colg, 0.0);
+                emit(s, colg, 0.0, sig(s));
         }
         return;
     }
@@ -415,6 +414,7 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
                     if (colg >= a.M)
                         continue;
                     // in atom order; the loads of 8 (then 4) rows are issued together
+                    const double sg = sig(s);
                     const int a1 = sstart[s + 1];
                     int r = sstart[s];
                     double sum = 0.0;
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
                     }
                     for (; r < a1; ++r)
                         sum += E[r * EPLD + c];
-                    emit(s, colg, sum);
+                    emit(s, colg, sum, sg);
                 }
             } else if (tid < EPC) {
                 const int c = tid;
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
                 const double tot = first ? sum : carry[p * EPC + c] + sum;
                 carry[p * EPC + c] = tot;
                 if (last && colg < a.M)
-                    emit(0, colg, tot);
+                    emit(0, colg, tot, sig(0));
             }
             __syncthreads();
         }
