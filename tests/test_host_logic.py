@@ -146,3 +146,13 @@ def test_lapack_comparator_on_the_tiny_workload():
     assert r["kind"] == "lapack" and r["unit"] == "s" and r["cores"] >= 1
     assert np.isfinite(r["value"]) and r["value"] > 0
     json.dumps(r)
+
+
+def test_bench_refuses_more_than_one_gpu_before_touching_a_device():
+    import subprocess
+
+    for argv, env in ((["--gpus", "2"], {}), (["--gpus", "8"], {}), ([], {"WORLD_SIZE": "2"})):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *argv], cwd=ROOT, capture_output=True,
+                           text=True, timeout=60, env={**os.environ, **env})
+        assert r.returncode == 2
+        assert "one GPU" in r.stderr and r.stdout == ""
