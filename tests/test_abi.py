@@ -65,3 +65,13 @@ def test_workspace_holds_the_paper_sized_stacked_matrix():
 def test_workspace_fits_one_mi355x(N, M):
     nb = gap.workspace_bytes(gap.params(400, 4), N, 40 * N, M)
     assert nb < 288e9 * 0.5
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    """No fallback: with the library absent, the first call raises."""
+    monkeypatch.setattr(gap, "_lib", None)
+    monkeypatch.setattr(gap, "LIB_PATH", str(tmp_path / "libgap.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        gap.lib()
+    with pytest.raises(RuntimeError, match="not built"):
+        gap.workspace_bytes(gap.params(64, 2, 1.0, 1e-8), 10, 100, 8)
