@@ -156,3 +156,81 @@ def test_bench_refuses_more_than_one_gpu_before_touching_a_device():
                            text=True, timeout=60, env={**os.environ, **env})
         assert r.returncode == 2
         assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def _counter_csv(path, rows):
+    import csv
+
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for name, counter, value in rows:
+            w.writerow({"Kernel_Name": name, "Grid_Size": 256, "Counter_Name": counter, "Counter_Value": value})
+
+
+def test_traffic_record_scales_the_knm_launch_by_the_copy_calibration(tmp_path):
+    import argparse
+
+    from paper_2207_03803_amd import profiling
+
+    knm = "void gap::knm_kernel(gap::KnmArgs)"
+    copy = "__amd_rocclr_copyBuffer"
+    paths = {}
+    for key, counter, rows in (
+            ("fit_fetch", "FETCH_SIZE",
+             [(knm, "FETCH_SIZE", 100.0), (knm, "FETCH_SIZE", 3.0e8), ("other", "FETCH_SIZE", 9e9)]),
+            ("fit_write", "WRITE_SIZE", [(knm, "WRITE_SIZE", 2.0), (knm, "WRITE_SIZE", 3.0e7)]),
+            ("copy_fetch", "FETCH_SIZE", [(copy, "FETCH_SIZE", v) for v in (5.0e5, 5.2e5, 5.4e5)]),
+            ("copy_write", "WRITE_SIZE", [(copy, "WRITE_SIZE", v) for v in (1.0e6, 1.1e6, 1.2e6)])):
+        d = tmp_path / key
+        d.mkdir()
+        paths[key] = str(d / "counter_collection.csv")
+        _counter_csv(paths[key], rows)
+    out = str(tmp_path / "rec")
+    profiling.traffic(argparse.Namespace(out=out, **paths))
+    rec = json.load(open(out + ".json"))
+    ff = profiling.COPY_BYTES / (5.2e5 * 1024)  # the median copy launch, the largest K_NM dispatch
+    wf = profiling.COPY_BYTES / (1.1e6 * 1024)
+    assert rec["fetch_size_kib_per_launch"] == 3.0e8 and rec["write_size_kib_per_launch"] == 3.0e7
+    assert rec["hbm_read_bytes_per_launch"] == pytest.approx(3.0e8 * 1024 * ff, rel=1e-12)
+    assert rec["hbm_write_bytes_per_launch"] == pytest.approx(3.0e7 * 1024 * wf, rel=1e-12)
+    assert rec["traffic_bytes_per_launch"] == pytest.approx(
+        rec["hbm_read_bytes_per_launch"] + rec["hbm_write_bytes_per_launch"], rel=1e-15)
+    assert rec["source_sha256"] == profiling.source_hash()
+    md = open(out + ".md").read()
+    assert f"-d {tmp_path / 'fit_fetch'} -o fit" in md and f"-d {tmp_path / 'copy_write'} -o copy" in md
+
+
+def test_committed_traffic_record_is_consistent():
+    from paper_2207_03803_amd import profiling
+
+    rec = json.load(open(os.path.join(ROOT, "profiles", "knm_kernel_realistic_fp64_traffic.json")))
+    cal = rec["copy_calibration"]
+    assert cal["fetch_factor"] == pytest.approx(profiling.COPY_BYTES / (cal["fetch_size_kib"] * 1024), rel=1e-12)
+    assert rec["hbm_read_bytes_per_launch"] == pytest.approx(
+        rec["fetch_size_kib_per_launch"] * 1024 * cal["fetch_factor"], rel=1e-12)
+    assert rec["traffic_bytes_per_launch"] == pytest.approx(
+        rec["hbm_read_bytes_per_launch"] + rec["hbm_write_bytes_per_launch"], rel=1e-12)
+    # the K_NM launch moves at least its algorithmic bytes: descriptors once, the N x M output once
+    assert rec["traffic_bytes_per_launch"] > 20.8e9
+    bench = _bench()
+    expect = rec["traffic_bytes_per_launch"] if rec["source_sha256"] == profiling.source_hash() else None
+    assert bench.knm_traffic() == expect
+
+
+def test_trace_table_aggregates_kernels_by_name(tmp_path):
+    import sqlite3
+
+    from paper_2207_03803_amd import profiling
+
+    db = str(tmp_path / "t.db")
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (kernel_name text, start integer, end integer)")
+    con.executemany("insert into kernels values (?, ?, ?)",
+                    [("void gap::a(int)", 0, 2_000_000), ("void gap::a(int)", 5_000_000, 9_000_000),
+                     ("gap::b", 0, 500_000)])  # timestamps in ns
+    con.commit()
+    con.close()
+    t = profiling.trace_table(db).splitlines()
+    assert t[2] == "| `gap::a` | 2 | 6.00 | 3000.0 | 2000.0 | 4000.0 |"
+    assert t[3] == "| `gap::b` | 1 | 0.50 | 500.0 | 500.0 | 500.0 |"
