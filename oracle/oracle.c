@@ -72,7 +72,12 @@ int oracle_knm(const double *X, const int64_t *offsets, int64_t N, const double 
     for (int64_t A = 0; A < N; ++A) {
         for (int64_t j = 0; j < M; ++j) {
             double s = 0.0;
-            for (int64_t i = offsets[A]; i < offsets[A + 1]; ++i)
+            int64_t end = offsets[A + 1];
+#ifdef ORACLE_PLANT_SEGMENT_END
+            if (end > offsets[A])
+                end -= 1; /* planted mistake: a configuration's last atom dropped */
+#endif
+            for (int64_t i = offsets[A]; i < end; ++i)
                 s += covariance(X + i * d, XM + j * d, d, zeta, sigma_w);
             K[A * M + j] = s;
         }
@@ -144,7 +149,11 @@ int oracle_stack(const double *Knm, const double *sigma, const double *y, const 
             A[r * M + j] = Knm[r * M + j] / sigma[r];
 #endif
         }
+#ifdef ORACLE_PLANT_B_UNSCALED
+        b[r] = y[r]; /* planted mistake: targets not scaled by 1/sigma */
+#else
         b[r] = y[r] / sigma[r];
+#endif
     }
     for (int64_t i = 0; i < M; ++i) {
         for (int64_t j = 0; j < M; ++j) {
@@ -252,7 +261,12 @@ int oracle_predict(const double *X, const int64_t *offsets, int64_t N, const dou
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t A = 0; A < N; ++A) {
         double e = 0.0;
-        for (int64_t i = offsets[A]; i < offsets[A + 1]; ++i) {
+        int64_t start = offsets[A];
+#ifdef ORACLE_PLANT_PREDICT_SEGMENT
+        if (start < offsets[A + 1])
+            start += 1; /* planted mistake: a configuration's first atom skipped */
+#endif
+        for (int64_t i = start; i < offsets[A + 1]; ++i) {
             double eps = 0.0;
             for (int64_t j = 0; j < M; ++j)
                 eps += c[j] * covariance(X + i * d, XM + j * d, d, zeta, sigma_w);

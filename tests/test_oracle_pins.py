@@ -355,7 +355,8 @@ def test_p17_paper_printed_shapes():
 
 
 PLANTS = ["ORACLE_PLANT_POWER", "ORACLE_PLANT_NO_JITTER", "ORACLE_PLANT_NO_ROW_SCALE",
-          "ORACLE_PLANT_TRANSPOSE_L", "ORACLE_PLANT_TAU", "ORACLE_PLANT_BACKSUB"]
+          "ORACLE_PLANT_TRANSPOSE_L", "ORACLE_PLANT_TAU", "ORACLE_PLANT_BACKSUB", "ORACLE_PLANT_SEGMENT_END",
+          "ORACLE_PLANT_B_UNSCALED", "ORACLE_PLANT_PREDICT_SEGMENT"]
 
 
 @pytest.mark.parametrize("plant", PLANTS)
@@ -372,4 +373,24 @@ def test_planted_mistake_is_caught(plant, tmp_path):
                                                            jitter=0.5)])
     if res.status != 0 or not np.all(np.isfinite(res.c)) or rel(res.c, c_ex) > 1e-12:
         failures += 1
+    # prediction (Eqs. 1-2) against its closed form in numpy, with sigma_w != 1
+    c = np.random.default_rng(3).standard_normal(XM.shape[0])
+    eps = 1.3 ** 2 * (X @ XM.T) ** zeta @ c
+    y_ref = np.array([eps[offsets[a]:offsets[a + 1]].sum() for a in range(len(offsets) - 1)])
+    if rel(bad.predict(X, offsets, XM, c, zeta, sigma_w=1.3), y_ref) > 1e-13:
+        failures += 1
     assert failures > 0
+
+
+def test_the_planted_mistake_checks_pass_on_the_oracle(orc):
+    """The checks the planted-mistake test relies on hold for the oracle as built."""
+    X, offsets, XM, sigma, y, zeta, _ = _micro(7)
+    res = orc.fit(X, offsets, XM, sigma, y, zeta, jitter=0.5)
+    c_ex = np.array([float(v) for v in exact_ref.fit_exact(X.tolist(), offsets.tolist(), XM.tolist(),
+                                                           sigma.tolist(), y.tolist(), zeta,
+                                                           jitter=0.5)])
+    assert res.status == 0 and rel(res.c, c_ex) <= 1e-12
+    c = np.random.default_rng(3).standard_normal(XM.shape[0])
+    eps = 1.3 ** 2 * (X @ XM.T) ** zeta @ c
+    y_ref = np.array([eps[offsets[a]:offsets[a + 1]].sum() for a in range(len(offsets) - 1)])
+    assert rel(orc.predict(X, offsets, XM, c, zeta, sigma_w=1.3), y_ref) <= 1e-13
