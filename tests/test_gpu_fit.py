@@ -80,6 +80,15 @@ def test_ragged_shapes_parity(orc_m, n_configs, atoms, d, M, zeta, seed):
     _compare_fit(orc_m, inp, y, ref, zeta)
 
 
+@pytest.mark.parametrize("M", [64, 128, 129, 192, 193])
+def test_cholesky_step_pairing_boundaries(orc_m, M):
+    """K_MM sizes where the Cholesky's 64-column steps pair up exactly, or leave
+    one step or one column over: L^T and c against the oracle."""
+    log(f"cholesky pairing: N=300 atoms=(1, 4) d=64 M={M} zeta=2")
+    inp, y, ref = _case(orc_m, 300, (1, 4), 64, M, 2, 40 + M)
+    _compare_fit(orc_m, inp, y, ref, 2)
+
+
 def test_large_and_empty_configurations(orc_m):
     """Configurations larger than one 256-atom chunk, and empty ones."""
     rng = np.random.default_rng(9)
