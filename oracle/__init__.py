@@ -48,9 +48,10 @@ def _bind(lib):
     lib.oracle_gradient.argtypes = [P, P, P, P, P, I64, I64, P]
     lib.oracle_fit.argtypes = [P, P, I64, P, I64, I64, ctypes.c_int, ctypes.c_double,
                                ctypes.c_double, P, P, P, P, P, P, P, P, P, P]
+    lib.oracle_singular_extremes.argtypes = [P, I64, I64, ctypes.c_int, ctypes.c_double, P, P, P]
     for name in ("oracle_knm", "oracle_kmm", "oracle_cholesky", "oracle_stack",
                  "oracle_householder_qr", "oracle_back_substitution", "oracle_predict",
-                 "oracle_gradient", "oracle_fit"):
+                 "oracle_gradient", "oracle_fit", "oracle_singular_extremes"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -123,9 +124,13 @@ class Oracle:
                               self._p(A), self._p(b))
         return A, b
 
-    def householder_qr(self, A, b):
-        A = np.array(A, dtype=np.float64, order="C")
-        b = np.array(b, dtype=np.float64)
+    def householder_qr(self, A, b, overwrite=False):
+        """(A holding R and the reflectors, Q^T b, tau).  overwrite=True factors a
+        C-contiguous float64 A (and b) in place instead of copies."""
+        if not (overwrite and A.flags.c_contiguous and A.dtype == np.float64):
+            A = np.array(A, dtype=np.float64, order="C")
+        if not (overwrite and b.flags.c_contiguous and b.dtype == np.float64):
+            b = np.array(b, dtype=np.float64)
         m, n = A.shape
         tau = np.empty(n)
         rc = self.lib.oracle_householder_qr(self._p(A), self._p(b), m, n, self._p(tau))
@@ -139,6 +144,17 @@ class Oracle:
         self.lib.oracle_back_substitution(self._p(R), R.shape[1], self._p(self._f64(rhs)), n,
                                           self._p(c))
         return c
+
+    def singular_extremes(self, R, max_iter=2000, tol=1e-14):
+        """(smax, smin, (power steps, inverse steps)) of the upper triangle of R."""
+        R = self._f64(R)
+        n = R.shape[0]
+        smax, smin = np.zeros(1), np.zeros(1)
+        its = np.zeros(2, dtype=np.int32)
+        rc = self.lib.oracle_singular_extremes(self._p(R), R.shape[1], n, max_iter, tol, self._p(smax),
+                                               self._p(smin), self._p(its))
+        assert rc == ORACLE_OK, rc
+        return float(smax[0]), float(smin[0]), (int(its[0]), int(its[1]))
 
     def predict(self, X, offsets, XM, c, zeta, sigma_w=1.0):
         X, XM, c, offsets = self._f64(X), self._f64(XM), self._f64(c), self._i64(offsets)

@@ -32,6 +32,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* Return codes shared by the functions below. */
 #define ORACLE_OK 0
@@ -180,8 +183,12 @@ int oracle_householder_qr(double *A, double *b, int64_t m, int64_t n, double *ta
     if (m < n || n < 0)
         return ORACLE_EINVAL;
     double *v = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
-    if (!v)
+    double *w = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!v || !w) {
+        free(v);
+        free(w);
         return ORACLE_ENOMEM;
+    }
     for (int64_t k = 0; k < n; ++k) {
         double alpha = A[k * n + k];
         double xnorm2 = 0.0;
@@ -211,24 +218,49 @@ int oracle_householder_qr(double *A, double *b, int64_t m, int64_t n, double *ta
         tau[k] = t;
         if (t == 0.0)
             continue;
-        /* Apply H = I - t v v^T to the remaining columns, then to b. */
-#pragma omp parallel for schedule(static)
-        for (int64_t j = k + 1; j < n; ++j) {
-            double w = 0.0;
-            for (int64_t i = k; i < m; ++i)
-                w += v[i] * A[i * n + j];
-            w *= t;
-            for (int64_t i = k; i < m; ++i)
-                A[i * n + j] -= w * v[i];
+        /*
+         * Apply H = I - t v v^T to the remaining columns, then to b:
+         * w[j] = t * sum_{i >= k} v[i] A[i][j] (each sum in ascending i), then
+         * A[i][j] -= w[j] v[i].  Both loops walk A row by row (it is stored by
+         * rows); every element sees the same operations in the same order as
+         * the column-at-a-time form.
+         */
+        const int64_t nt = n - (k + 1);
+#pragma omp parallel
+        {
+#ifdef _OPENMP
+            const int64_t nth = omp_get_num_threads(), th = omp_get_thread_num();
+#else
+            const int64_t nth = 1, th = 0;
+#endif
+            const int64_t j0 = k + 1 + (nt * th) / nth, j1 = k + 1 + (nt * (th + 1)) / nth;
+            for (int64_t j = j0; j < j1; ++j)
+                w[j] = 0.0;
+            for (int64_t i = k; i < m; ++i) {
+                const double vi = v[i];
+                const double *row = A + i * n;
+                for (int64_t j = j0; j < j1; ++j)
+                    w[j] += vi * row[j];
+            }
+            for (int64_t j = j0; j < j1; ++j)
+                w[j] *= t;
         }
-        double w = 0.0;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = k; i < m; ++i) {
+            const double vi = v[i];
+            double *row = A + i * n;
+            for (int64_t j = k + 1; j < n; ++j)
+                row[j] -= w[j] * vi;
+        }
+        double wb = 0.0;
         for (int64_t i = k; i < m; ++i)
-            w += v[i] * b[i];
-        w *= t;
+            wb += v[i] * b[i];
+        wb *= t;
         for (int64_t i = k; i < m; ++i)
-            b[i] -= w * v[i];
+            b[i] -= wb * v[i];
     }
     free(v);
+    free(w);
     return ORACLE_OK;
 }
 
@@ -248,6 +280,107 @@ int oracle_back_substitution(const double *R, int64_t ldr, const double *rhs, in
 #endif
         c[i] = s / R[i * ldr + i];
     }
+    return ORACLE_OK;
+}
+
+/*
+ * Extreme singular values of the stacked matrix A through the n x n upper
+ * triangle of its QR factor R (row-major, leading dimension ldr): A = QR with
+ * orthonormal columns in Q, so A and R have the same singular values and
+ * kappa_2(A) = smax / smin, the factor that turns a backward-stable solver's
+ * rounding into its error in c (Sec. Practical Examples compares predictions
+ * because reordered fits share only a few digits of c).
+ *   smax: power iteration on R^T R (x <- R^T R x, normalised).
+ *   smin: inverse iteration on R^T R (x <- R^-1 R^-T x, normalised).
+ * Each estimate is the Rayleigh quotient of the unit iterate (||R x||^2, and
+ * ||R^-T x||^2 for the inverse), so it approaches the extreme value from
+ * inside; iteration stops when the quotient changes by at most tol
+ * (relative) between steps, or after max_iter steps.  iters[0], iters[1] =
+ * steps taken.  Starting vector: all ones.  ORACLE_EINVAL on a zero pivot.
+ */
+int oracle_singular_extremes(const double *R, int64_t ldr, int64_t n, int max_iter, double tol,
+                             double *smax, double *smin, int *iters)
+{
+    if (n < 1 || ldr < n || max_iter < 1)
+        return ORACLE_EINVAL;
+    for (int64_t i = 0; i < n; ++i)
+        if (R[i * ldr + i] == 0.0)
+            return ORACLE_EINVAL;
+    double *x = (double *)malloc(sizeof(double) * (size_t)n);
+    double *y = (double *)malloc(sizeof(double) * (size_t)n);
+    double *z = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!x || !y || !z) {
+        free(x);
+        free(y);
+        free(z);
+        return ORACLE_ENOMEM;
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        const int inverse = (pass == 1);
+        for (int64_t i = 0; i < n; ++i)
+            x[i] = 1.0 / sqrt((double)n);
+        double q = 0.0, q_prev = 0.0;
+        int it = 0;
+        while (it < max_iter) {
+            ++it;
+            if (!inverse) {
+                /* y = R x (rows independent) */
+#pragma omp parallel for schedule(static)
+                for (int64_t i = 0; i < n; ++i) {
+                    double s = 0.0;
+                    for (int64_t j = i; j < n; ++j)
+                        s += R[i * ldr + j] * x[j];
+                    y[i] = s;
+                }
+                /* z = R^T y: z[j] = sum_{i <= j} R[i][j] y[i], ascending i */
+                for (int64_t j = 0; j < n; ++j)
+                    z[j] = 0.0;
+                for (int64_t i = 0; i < n; ++i) {
+                    const double yi = y[i];
+                    for (int64_t j = i; j < n; ++j)
+                        z[j] += R[i * ldr + j] * yi;
+                }
+            } else {
+                /* y = R^-T x: forward substitution with the lower triangle R^T */
+                for (int64_t i = 0; i < n; ++i)
+                    z[i] = x[i];
+                for (int64_t k = 0; k < n; ++k) {
+                    y[k] = z[k] / R[k * ldr + k];
+                    const double yk = y[k];
+                    for (int64_t j = k + 1; j < n; ++j)
+                        z[j] -= R[k * ldr + j] * yk;
+                }
+                /* z = R^-1 y: back-substitution */
+                for (int64_t i = n - 1; i >= 0; --i) {
+                    double s = y[i];
+                    for (int64_t j = i + 1; j < n; ++j)
+                        s -= R[i * ldr + j] * z[j];
+                    z[i] = s / R[i * ldr + i];
+                }
+            }
+            q = 0.0;
+            for (int64_t i = 0; i < n; ++i)
+                q += y[i] * y[i];
+            double zn = 0.0;
+            for (int64_t i = 0; i < n; ++i)
+                zn += z[i] * z[i];
+            zn = sqrt(zn);
+            for (int64_t i = 0; i < n; ++i)
+                x[i] = z[i] / zn;
+            if (it > 1 && fabs(q - q_prev) <= tol * q)
+                break;
+            q_prev = q;
+        }
+        if (!inverse)
+            *smax = sqrt(q);
+        else
+            *smin = 1.0 / sqrt(q);
+        if (iters)
+            iters[pass] = it;
+    }
+    free(x);
+    free(y);
+    free(z);
     return ORACLE_OK;
 }
 

@@ -75,17 +75,36 @@ class Pool:
     X: object               # torch [n_atoms, d] float64 (cuda)
 
 
-def make_pools(specs, seed=0, atoms=(8, 64), device="cuda", min_configs=0):
+def make_pools(specs, seed=0, atoms=(8, 64), device="cuda", min_configs=0, host=False, log=None):
     """One descriptor pool per d, as large as the largest fit that uses it (and at
-    least `min_configs` configurations)."""
+    least `min_configs` configurations).  host=False draws the descriptors on
+    the device (torch Philox); host=True draws them on the host
+    (synth.make_fit_inputs_blocked, numpy arrays), so that a CPU program can
+    draw the same pool."""
     from . import synth
 
     pools = {}
     for d in sorted({s.d for s in specs}):
         n = max(max(s.n_configs for s in specs if s.d == d), min_configs)
-        inp = synth.make_fit_inputs_torch(n_configs=n, atoms=atoms, d=d, M=1, seed=seed + d, device=device)
+        if host:
+            inp = synth.make_fit_inputs_blocked(n_configs=n, atoms=atoms, d=d, M=1, seed=seed + d, log=log)
+        else:
+            inp = synth.make_fit_inputs_torch(n_configs=n, atoms=atoms, d=d, M=1, seed=seed + d, device=device)
         pools[d] = Pool(d, inp.offsets, inp.X)
     return pools
+
+
+def draw_fit(spec, pool_offsets):
+    """A fit's own draws over its pool (numpy, seeded by the fit): sparse rows
+    (uniform without replacement over the fit's atoms), c_true, noise, and
+    sigma_A = sigma_per_atom * N_A.  Returns a dict of numpy arrays."""
+    n_atoms = int(pool_offsets[spec.n_configs])
+    rng = np.random.default_rng(spec.seed)
+    sparse_idx = np.sort(rng.choice(n_atoms, size=spec.M, replace=False))
+    counts = np.diff(pool_offsets[:spec.n_configs + 1])
+    sigma = spec.sigma_per_atom * counts.astype(np.float64)
+    return dict(c_true=rng.standard_normal(spec.M), noise=rng.standard_normal(spec.n_configs),
+                sparse_idx=sparse_idx, sigma=sigma, n_atoms=n_atoms)
 
 
 @dataclass
@@ -106,7 +125,7 @@ class Sweep:
     """The fits of one sweep with their inputs resident on the device."""
 
     def __init__(self, specs, pools, precision=gap.GAP_MIXED_FP32, streams=8, split_wgs=0, lookahead=0,
-                 max_refine_iters=20, refine_tol=1e-12):
+                 max_refine_iters=20, refine_tol=1e-12, targets=None):
         import torch
 
         self.specs = specs
@@ -126,18 +145,14 @@ class Sweep:
         stream_of = {i: k for k, lst in enumerate(self.assign) for i in lst}
         for s in specs:
             pool = pools[s.d]
-            n_atoms = int(pool.offsets[s.n_configs])
-            rng = np.random.default_rng(s.seed)
-            sparse_idx = np.sort(rng.choice(n_atoms, size=s.M, replace=False))
-            counts = np.diff(pool.offsets[:s.n_configs + 1])
-            sigma = s.sigma_per_atom * counts.astype(np.float64)
+            dr = draw_fit(s, pool.offsets)
+            n_atoms = dr["n_atoms"]
             f = Fit(s)
             f.X = pool.X[:n_atoms]
             f.offsets = torch.from_numpy(np.ascontiguousarray(pool.offsets[:s.n_configs + 1])).cuda()
-            f.XM = pool.X[torch.from_numpy(sparse_idx).cuda()].contiguous()
-            f.sigma = torch.from_numpy(sigma).cuda()
-            f.host = dict(c_true=rng.standard_normal(s.M), noise=rng.standard_normal(s.n_configs),
-                          sparse_idx=sparse_idx, sigma=sigma)
+            f.XM = pool.X[torch.from_numpy(dr["sparse_idx"]).cuda()].contiguous()
+            f.sigma = torch.from_numpy(dr["sigma"]).cuda()
+            f.host = dict(c_true=dr["c_true"], noise=dr["noise"], sparse_idx=dr["sparse_idx"], sigma=dr["sigma"])
             p = gap.params(s.d, s.zeta, 1.0, 1e-8, precision=precision, max_refine_iters=max_refine_iters,
                            refine_tol=refine_tol)
             f.handle = gap.Handle(p, stream=self.streams[stream_of[s.idx]])
@@ -146,14 +161,18 @@ class Sweep:
             f.ws = f.handle.alloc_workspace(s.n_configs, n_atoms, s.M)
             f.c = torch.empty(s.M, dtype=torch.float64, device="cuda")
             self.fits.append(f)
-        self._targets()
+        self._targets(targets or {})
         self.graphs = None
 
-    def _targets(self):
-        """y = prediction with c_true plus sigma * noise, through the library."""
+    def _targets(self, given):
+        """y = prediction with c_true plus sigma * noise, through the library;
+        given[idx] (host array) is used instead where present."""
         import torch
 
         for f in self.fits:
+            if f.spec.idx in given:
+                f.y = torch.from_numpy(np.ascontiguousarray(given[f.spec.idx], dtype=np.float64)).cuda()
+                continue
             with torch.cuda.stream(f.handle.stream):
                 f.handle.build_knm(f.X, f.offsets, f.XM, f.sigma)
                 y = torch.empty(f.spec.n_configs, dtype=torch.float64, device="cuda")

@@ -16,7 +16,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-__all__ = ["FitInputs", "make_fit_inputs", "make_fit_inputs_torch", "WORKLOADS"]
+__all__ = ["FitInputs", "make_fit_inputs", "make_fit_inputs_blocked", "make_fit_inputs_torch", "WORKLOADS"]
 
 
 # Workload recipes (atom-count range, descriptor length, sparse-set size,
@@ -78,6 +78,59 @@ def make_fit_inputs(n_configs: int, atoms=(8, 64), d: int = 64, M: int = 256,
         np.abs(blk, out=blk)
         blk /= np.sqrt(np.einsum("ij,ij->i", blk, blk))[:, None]
         X[s:e] = blk
+    sparse_idx = np.sort(rng.choice(n_atoms, size=M, replace=False)).astype(np.int64)
+    XM = np.ascontiguousarray(X[sparse_idx])
+    c_true = rng.standard_normal(M)
+    noise = rng.standard_normal(n_configs)
+    sigma = sigma_per_atom * counts.astype(np.float64)
+    return FitInputs(offsets, X, sparse_idx, XM, c_true, noise, sigma)
+
+
+BLOCK_ATOMS = 1 << 16  # descriptors per independent stream of make_fit_inputs_blocked
+
+
+def _draw_block(seed: int, b: int, rows: int, d: int) -> np.ndarray:
+    blk = np.random.default_rng(np.random.SeedSequence([seed, 1, b])).standard_normal((rows, d))
+    np.abs(blk, out=blk)
+    blk /= np.sqrt(np.einsum("ij,ij->i", blk, blk))[:, None]
+    return blk
+
+
+def make_fit_inputs_blocked(n_configs: int, atoms=(16, 64), d: int = 400, M: int = 10_000,
+                            seed: int = 0, sigma_per_atom: float = 1e-3, workers: int = 8,
+                            log=None, **_unused) -> FitInputs:
+    """Same recipe on the host, drawn by several threads: for sizes whose
+    descriptors take minutes to draw from one stream.
+
+    Counts, sparse indices, c_true and noise come from numpy PCG64 (seed), in
+    that order (the descriptors are not on this stream); descriptor block b
+    (BLOCK_ATOMS rows) comes
+    from its own PCG64 stream seeded with SeedSequence([seed, 1, b]), so the
+    arrays do not depend on ``workers``.  ``log`` (optional) is called with a
+    progress string every 16 blocks.
+    """
+    from concurrent.futures import ThreadPoolExecutor
+
+    rng = np.random.default_rng(seed)
+    counts = _counts(rng, n_configs, atoms)
+    offsets = np.zeros(n_configs + 1, dtype=np.int64)
+    np.cumsum(counts, out=offsets[1:])
+    n_atoms = int(offsets[-1])
+    if M > n_atoms:
+        raise ValueError(f"M={M} exceeds the number of descriptors {n_atoms}")
+    X = np.empty((n_atoms, d), dtype=np.float64)
+    n_blocks = (n_atoms + BLOCK_ATOMS - 1) // BLOCK_ATOMS
+
+    def fill(b):
+        s = b * BLOCK_ATOMS
+        e = min(n_atoms, s + BLOCK_ATOMS)
+        X[s:e] = _draw_block(seed, b, e - s, d)
+        return b
+
+    with ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
+        for done, _ in enumerate(ex.map(fill, range(n_blocks)), 1):
+            if log and (done % 16 == 0 or done == n_blocks):
+                log(f"descriptors: {done}/{n_blocks} blocks")
     sparse_idx = np.sort(rng.choice(n_atoms, size=M, replace=False)).astype(np.int64)
     XM = np.ascontiguousarray(X[sparse_idx])
     c_true = rng.standard_normal(M)

@@ -1,0 +1,142 @@
+"""Write the oracle's reference fits for the full-size parity tests.
+
+Every stored number comes from the CPU oracle (``oracle/``) on inputs drawn by
+the seeded generators; nothing here touches the GPU library.  Two parts:
+
+* ``realistic``: the realistic workload at full size (1e5 configurations of
+  16..64 atoms, d = 400, M = 1e4, zeta = 4, sigma_A = 1e-3 N_A, jitter 1e-8),
+  descriptors from ``synth.make_fit_inputs_blocked(seed=0)``.  Stores y, c,
+  |diag R|, the minimum loss ||(Q^T b)[M:]||^2 and the extreme singular values
+  of the stacked matrix A (kappa_2(A) = smax / smin), in
+  ``realistic_fp64_seed0.npz``.  About 45 GB of memory and 2-3 hours on 8
+  cores.
+* ``sweep``: three fits of the benchmark's 64-fit sweep (``sweep.make_sweep(0)``):
+  the one with the largest M, the one with M > N_c, and the smallest-N_c fit
+  at sigma_E = 1e-4 per atom, over host-drawn pools
+  (``sweep.make_pools(host=True, min_configs=30000)``).  Stores y, c, |diag R|,
+  the loss and kappa per fit in ``sweep_fits_seed0.npz``.  About 15 minutes.
+
+Targets are y = K_NM c_true + sigma * noise with K_NM from the oracle (the
+model's prediction with c_true, Eqs. 1-2), and the fit follows the oracle's
+stages in the paper's order (Sec. Theory): K_NM, K_MM + jitter, Cholesky, the
+stacked problem, Householder QR with Q^T b, back-substitution.
+
+Usage: python tests/golden/make_reference_fits.py {realistic|sweep} [--log FILE]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2207_03803_amd import sweep, synth  # noqa: E402
+
+SWEEP_PINNED = (38, 58, 47)  # largest M; M > N_c; smallest N_c at sigma_E = 1e-4
+
+
+def oracle_fit_staged(orc, X, offsets, XM, sigma, c_true, noise, zeta, sigma_w, jitter, log):
+    """The oracle's fit stage by stage, with y formed from its own K_NM."""
+    t = {}
+    t0 = time.time()
+    Knm = orc.knm(X, offsets, XM, zeta, sigma_w)
+    t["knm_s"] = time.time() - t0
+    log(f"K_NM {Knm.shape} in {t['knm_s']:.0f} s")
+    y = Knm @ c_true + sigma * noise
+    t0 = time.time()
+    Kmm = orc.kmm(XM, zeta, sigma_w, jitter)
+    rc, L, fail = orc.cholesky(Kmm)
+    assert rc == oracle.ORACLE_OK, (rc, fail)
+    del Kmm
+    t["kmm_chol_s"] = time.time() - t0
+    A, b = orc.stack(Knm, sigma, y, L)
+    del Knm, L
+    M = XM.shape[0]
+    log(f"stacked A {A.shape}; Householder QR ...")
+    t0 = time.time()
+    A, b, tau = orc.householder_qr(A, b, overwrite=True)
+    t["qr_s"] = time.time() - t0
+    log(f"QR in {t['qr_s']:.0f} s")
+    c = orc.back_substitution(A[:M], b[:M])
+    loss_tail = float(np.sum(b[M:] * b[M:]))
+    R = np.ascontiguousarray(A[:M])
+    diagR = np.abs(np.diag(R)).copy()
+    del A
+    t0 = time.time()
+    smax, smin, its = orc.singular_extremes(R)
+    t["kappa_s"] = time.time() - t0
+    log(f"kappa_2(A) = {smax / smin:.3e} (smax {smax:.4e}, smin {smin:.4e}, steps {its})")
+    return dict(y=y, c=c, diagR_abs=diagR, loss_tail=loss_tail, smax=smax, smin=smin,
+                kappa_iters=np.array(its)), t
+
+
+def run_realistic(log):
+    w = dict(synth.WORKLOADS["realistic_fp64"])
+    t0 = time.time()
+    inp = synth.make_fit_inputs_blocked(seed=0, log=log, **w)
+    log(f"inputs: N={inp.n_configs} n_atoms={inp.n_atoms} in {time.time() - t0:.0f} s")
+    orc = oracle.Oracle()
+    t0 = time.time()
+    res, times = oracle_fit_staged(orc, inp.X, inp.offsets, inp.XM, inp.sigma, inp.c_true, inp.noise,
+                                   w["zeta"], w["sigma_w"], w["jitter"], log)
+    times["total_s"] = time.time() - t0
+    meta = dict(workload="realistic_fp64", seed=0, generator="synth.make_fit_inputs_blocked",
+                n_configs=inp.n_configs, n_atoms=inp.n_atoms, M=w["M"], d=w["d"], zeta=w["zeta"],
+                threads=os.cpu_count(), kappa=res["smax"] / res["smin"], loss_tail=res["loss_tail"], **times)
+    np.savez(os.path.join(HERE, "realistic_fp64_seed0.npz"), meta=json.dumps(meta), **res)
+    log("wrote realistic_fp64_seed0.npz: " + json.dumps(meta))
+
+
+def run_sweep(log):
+    specs = sweep.make_sweep(seed=0)
+    pinned = [specs[i] for i in SWEEP_PINNED]
+    pools = sweep.make_pools(pinned, seed=0, min_configs=sweep.SWEEP_RECIPE["pool_configs"], host=True)
+    orc = oracle.Oracle()
+    out, metas = {}, []
+    for s in pinned:
+        pool = pools[s.d]
+        dr = sweep.draw_fit(s, pool.offsets)
+        X = pool.X[:dr["n_atoms"]]
+        offs = np.ascontiguousarray(pool.offsets[:s.n_configs + 1])
+        XM = np.ascontiguousarray(pool.X[dr["sparse_idx"]])
+        log(f"fit {s.idx}: N={s.n_configs} M={s.M} d={s.d} zeta={s.zeta} sigma_E={s.sigma_per_atom:g}")
+        res, times = oracle_fit_staged(orc, X, offs, XM, dr["sigma"], dr["c_true"], dr["noise"], s.zeta, 1.0,
+                                       1e-8, log)
+        for k, v in res.items():
+            out[f"fit{s.idx}_{k}"] = v
+        metas.append(dict(idx=s.idx, n_configs=s.n_configs, M=s.M, d=s.d, zeta=s.zeta,
+                          sigma_per_atom=s.sigma_per_atom, kappa=res["smax"] / res["smin"],
+                          loss_tail=res["loss_tail"], **times))
+    meta = dict(sweep_seed=0, pool_configs=sweep.SWEEP_RECIPE["pool_configs"], pools="host", fits=metas,
+                threads=os.cpu_count())
+    np.savez(os.path.join(HERE, "sweep_fits_seed0.npz"), meta=json.dumps(meta), **out)
+    log("wrote sweep_fits_seed0.npz: " + json.dumps(meta))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("part", choices=["realistic", "sweep"])
+    ap.add_argument("--log", default=None)
+    a = ap.parse_args()
+    fh = open(a.log, "a") if a.log else None
+
+    def log(msg):
+        line = f"[{time.strftime('%H:%M:%S')}] {msg}"
+        print(line, flush=True)
+        if fh:
+            fh.write(line + "\n")
+            fh.flush()
+
+    {"realistic": run_realistic, "sweep": run_sweep}[a.part](log)
+
+
+if __name__ == "__main__":
+    main()

@@ -322,6 +322,33 @@ def test_p13_zero_column_gives_identity_reflector(orc):
     assert tau[0] == 0.0 and R[0, 0] == 3.0
 
 
+def test_kappa_estimate_matches_svd_of_the_stacked_matrix(tiny_fit, orc):
+    """The singular-value estimator (power and inverse iteration on R) against
+    LAPACK's SVD of A itself: A and its R share their singular values."""
+    w, inp, y, res, A, b = tiny_fit
+    n = A.shape[1]
+    smax, smin, its = orc.singular_extremes(np.triu(res.A[:n]))
+    sv = np.linalg.svd(A, compute_uv=False)
+    kappa = sv[0] / sv[-1]
+    assert abs(smax / sv[0] - 1) <= 1e-12
+    assert abs(smin / sv[-1] - 1) <= 1e-9
+    assert abs(smax / smin / kappa - 1) <= 1e-9
+    assert its[0] < 2000 and its[1] < 2000  # converged, not capped
+
+
+def test_kappa_estimate_closed_forms(orc):
+    """Diagonal R: the extremes are its largest and smallest |entries|.
+    A 2 x 2 triangle [[1, t], [0, e]]: sigma_max sigma_min = |det| = e and
+    sigma_max^2 + sigma_min^2 = 1 + t^2 + e^2 (the Frobenius norm)."""
+    s = np.array([3.0, -0.5, 2.0, 0.01, 1.0])
+    smax, smin, _ = orc.singular_extremes(np.diag(s))
+    assert abs(smax - 3.0) <= 1e-14 * 3.0 and abs(smin - 0.01) <= 1e-13 * 0.01
+    t, e = 4.0, 1e-3
+    smax, smin, _ = orc.singular_extremes(np.array([[1.0, t], [0.0, e]]))
+    assert abs(smax * smin - e) <= 1e-12 * e
+    assert abs(smax ** 2 + smin ** 2 - (1 + t * t + e * e)) <= 1e-14 * (1 + t * t)
+
+
 # ---------------------------------------------------------------- P15 predict
 
 

@@ -65,3 +65,17 @@ def test_workload_recipes_have_the_stated_sizes():
     assert (t["n_configs"], t["d"], t["M"], t["zeta"]) == (200, 64, 256, 2)
     assert (r["n_configs"], r["atoms"], r["d"], r["M"], r["zeta"]) == (100_000, (16, 64), 400, 10_000, 4)
     assert r["jitter"] == t["jitter"] == 1e-8
+
+
+def test_blocked_recipe_is_independent_of_the_worker_count():
+    w = dict(n_configs=4000, atoms=(8, 64), d=24, M=50)
+    a = synth.make_fit_inputs_blocked(seed=5, workers=1, **w)
+    b = synth.make_fit_inputs_blocked(seed=5, workers=5, **w)
+    assert a.n_atoms > 2 * synth.BLOCK_ATOMS  # several blocks and a ragged last one
+    for f in ("offsets", "X", "sparse_idx", "XM", "c_true", "noise", "sigma"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)), f
+    assert np.allclose(np.linalg.norm(a.X, axis=1), 1.0, rtol=0, atol=1e-12) and (a.X >= 0).all()
+    assert np.array_equal(a.XM, a.X[a.sparse_idx])
+    # counts come from the same host stream as the single-stream recipe
+    h = synth.make_fit_inputs(seed=5, **w)
+    assert np.array_equal(h.offsets, a.offsets)
