@@ -229,6 +229,32 @@ typedef struct gap_tuning {
  * out-of-range values. */
 gap_status gap_set_tuning(gap_handle h, const gap_tuning *t);
 
+/*
+ * Allocation-free fit, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): gap_build_knm + gap_solve of one fit with the same arguments and
+ * the same kernels, but with the library's scratch in a static device array
+ * of GAP_STATIC_SCRATCH_BYTES per GPU (allocated when the library's code is
+ * loaded on that GPU and held until the process ends) instead of a bound
+ * workspace.  No handle is kept: the call allocates no device or host memory
+ * and creates no stream or event (the QR runs without look-ahead, and
+ * GAP_FLAG_TIMING is rejected).  Inputs and outputs are the caller's device
+ * arrays, as in gap_build_knm / gap_solve; `info` as in gap_solve (non-NULL:
+ * wait and return the device status; NULL: return after enqueueing).
+ * GAP_ENOMEM when gap_workspace_bytes() of this shape exceeds
+ * GAP_STATIC_SCRATCH_BYTES.  Every call on one GPU uses that GPU's one
+ * array, which keeps the last call's contents: calls that overlap on one GPU
+ * (other host threads, or other streams before the previous call's work has
+ * finished) race and give wrong results.  Each call clears the counters and
+ * flags it relies on with kernels (no memset nodes), so it may be captured.
+ */
+#define GAP_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+gap_status gap_fit_static(const gap_params *p, void *stream, const double *x_atoms, int64_t n_atoms,
+                          const int64_t *config_offsets, int64_t n_configs, const double *x_sparse, int64_t M,
+                          const double *sigma, const double *y, double *c_out, gap_solve_info *info);
+/* GAP_STATIC_SCRATCH_BYTES (for callers that load the library dynamically). */
+size_t gap_static_scratch_bytes(void);
+
 /* Human-readable name of a status code (static string). */
 const char *gap_status_string(gap_status s);
 

@@ -2,6 +2,7 @@
 // order in which the kernels are enqueued.  Declarations and the contract of
 // each entry point are in include/gap.h.
 #include <math.h>
+#include <mutex>
 #include <new>
 #include <string.h>
 
@@ -613,6 +614,71 @@ gap_status gap_destroy(gap_handle h)
         return GAP_EINVAL;
     destroy_handle(h);
     return GAP_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free fit.  Its scratch is this file-scope device array: each GPU
+// the library runs on holds its own copy until the process ends.  Host code
+// never uses the array's name as an address; it takes the device address
+// from hipGetSymbolAddress, once per device, with that device current.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[GAP_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[MAX_DEVICES] = {};
+
+// This device's copy of `scratch` (looked up on its first use).
+gap_status static_scratch(int device, char **out)
+{
+    if (device < 0 || device >= MAX_DEVICES)
+        return GAP_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return GAP_EDEVICE;
+        g_scratch_ptr[device] = static_cast<char *>(ptr);
+    }
+    *out = g_scratch_ptr[device];
+    return GAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gap_static_scratch_bytes(void) { return GAP_STATIC_SCRATCH_BYTES; }
+
+gap_status gap_fit_static(const gap_params *p, void *stream, const double *x_atoms, int64_t n_atoms,
+                          const int64_t *config_offsets, int64_t n_configs, const double *x_sparse, int64_t M,
+                          const double *sigma, const double *y, double *c_out, gap_solve_info *info)
+{
+    if (!valid_params(p) || (p->flags & GAP_FLAG_TIMING))
+        return GAP_EINVAL;
+    if (!x_atoms || !config_offsets || !x_sparse || !sigma || !y || !c_out || n_atoms < 1 || n_configs < 1 ||
+        M < 1 || n_configs > INT32_MAX - 1)
+        return GAP_EINVAL;
+    const size_t need = make_layout(n_configs, n_atoms, M, p->precision == GAP_MIXED_FP32).total;
+    if (need > GAP_STATIC_SCRATCH_BYTES)
+        return GAP_ENOMEM;
+    gap_handle_s h;  // on the stack: no timing events, no look-ahead stream
+    h.p = *p;
+    h.stream = reinterpret_cast<hipStream_t>(stream);
+    if (hipGetDevice(&h.device) != hipSuccess)
+        return GAP_EDEVICE;
+    char *base = nullptr;
+    GAP_TRY(static_scratch(h.device, &base));
+    h.ws = base;
+    h.ws_bytes = GAP_STATIC_SCRATCH_BYTES;
+    h.state = ST_BOUND;
+    h.tuning.qr_lookahead = 1;  // the whole QR on `stream`
+    GAP_TRY(gap_build_knm(&h, x_atoms, n_atoms, config_offsets, n_configs, x_sparse, M, sigma));
+    return gap_solve(&h, y, c_out, info);
 }
 
 }  // extern "C"

@@ -20,7 +20,8 @@ GAP_FLAG_TIMING = 1
 # Every entry point include/gap.h declares.
 EXPORTS = ["gap_create", "gap_workspace_bytes", "gap_bind_workspace", "gap_build_knm", "gap_solve",
            "gap_predict", "gap_sync", "gap_layout", "gap_stage_times", "gap_status_string",
-           "gap_set_tuning", "gap_set_model", "gap_set_stream", "gap_destroy"]
+           "gap_set_tuning", "gap_set_model", "gap_set_stream", "gap_destroy", "gap_fit_static",
+           "gap_static_scratch_bytes"]
 
 STAGES = ["knm", "kmm", "cholesky", "assemble_b", "qr", "trsv", "refine", "reserved"]
 
@@ -83,6 +84,11 @@ def lib():
     L.gap_set_tuning.argtypes = [P, ctypes.POINTER(GapTuning)]
     L.gap_set_model.argtypes = [P, P, I64]
     L.gap_set_stream.argtypes = [P, P]
+    L.gap_fit_static.argtypes = [ctypes.POINTER(GapParams), P, P, I64, P, I64, P, I64, P, P, P,
+                                 ctypes.POINTER(GapSolveInfo)]
+    L.gap_fit_static.restype = I32
+    L.gap_static_scratch_bytes.argtypes = []
+    L.gap_static_scratch_bytes.restype = ctypes.c_size_t
     for n in ("gap_create", "gap_bind_workspace", "gap_build_knm", "gap_solve", "gap_predict", "gap_sync",
               "gap_layout", "gap_stage_times", "gap_set_tuning", "gap_set_model", "gap_set_stream",
               "gap_destroy"):
@@ -111,6 +117,24 @@ def _ptr(t):
 def _check(s, where):
     if s != GAP_OK:
         raise GapError(s, where)
+
+
+def fit_static(p: GapParams, X, offsets, XM, sigma, y, c_out, info=True, stream=None):
+    """gap_fit_static: one fit with the library's static scratch (no workspace,
+    no handle).  Returns the GapSolveInfo (info=True: waits for the stream)."""
+    import torch
+
+    st = stream if stream is not None else torch.cuda.current_stream()
+    inf = GapSolveInfo() if info else None
+    s = lib().gap_fit_static(ctypes.byref(p), ctypes.c_void_p(st.cuda_stream), _ptr(X), X.shape[0], _ptr(offsets),
+                             offsets.numel() - 1, _ptr(XM), XM.shape[0], _ptr(sigma), _ptr(y), _ptr(c_out),
+                             ctypes.byref(inf) if info else None)
+    _check(s, "gap_fit_static")
+    return inf
+
+
+def static_scratch_bytes() -> int:
+    return int(lib().gap_static_scratch_bytes())
 
 
 class Handle:

@@ -75,3 +75,24 @@ def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
         gap.lib()
     with pytest.raises(RuntimeError, match="not built"):
         gap.workspace_bytes(gap.params(64, 2, 1.0, 1e-8), 10, 100, 8)
+
+
+def test_fit_static_checks_arguments_and_size_without_a_gpu():
+    """The allocation-free fit rejects bad parameters, timing events and shapes whose
+    scratch would exceed the static array before it touches the GPU."""
+    lib = gap.lib()
+    dummy = ctypes.c_void_p(256)  # never dereferenced: every check here fails first
+    cap = gap.static_scratch_bytes()
+    assert cap == 256 << 20
+
+    def call(p, n_atoms, N, M):
+        return lib.gap_fit_static(ctypes.byref(p), None, dummy, n_atoms, dummy, N, dummy, M, dummy, dummy,
+                                  dummy, None)
+
+    assert call(gap.params(0, 2), 100, 10, 8) == gap.GAP_EINVAL
+    assert call(gap.params(64, 2, flags=gap.GAP_FLAG_TIMING), 100, 10, 8) == gap.GAP_EINVAL
+    assert call(gap.params(64, 2), 0, 10, 8) == gap.GAP_EINVAL
+    big = (100_000, 10_000)
+    assert gap.workspace_bytes(gap.params(64, 2), big[0], 40 * big[0], big[1]) > cap
+    assert call(gap.params(64, 2), 40 * big[0], *big) == gap.GAP_ENOMEM
+    assert gap.workspace_bytes(gap.params(64, 2), 200, 7200, 256) <= cap
