@@ -64,11 +64,19 @@ typedef enum gap_status {
 
 typedef enum gap_precision {
     GAP_FP64 = 0,        /* every stage in FP64 */
-    GAP_MIXED_FP32 = 1   /* FP64 K_NM/Cholesky; FP32 Householder QR with FP64 reflector norms;
+    GAP_MIXED_FP32 = 1,  /* FP64 K_NM/Cholesky; FP32 Householder QR with FP64 reflector norms;
                             FP64 iterative refinement of c against the FP64 A: corrected
                             semi-normal equations preconditioned by the FP32 R, moving to
                             R-preconditioned CGLS when a correction fails to halve (A too
-                            ill-conditioned for FP32, kappa(A) near 1/u_32 or above) */
+                            ill-conditioned for FP32, kappa(A) near 1/u_32 or above).
+                            The factored FP32 matrix is the FP64 A rounded to FP32. */
+    GAP_MIXED_BF16 = 2,  /* as GAP_MIXED_FP32, but the factored matrix's K_NM block comes from
+                            descriptor dot products on BF16 MFMA (descriptors rounded to BF16,
+                            FP32 accumulation), with the power, the per-configuration sums and
+                            the row scale in FP32.  The FP64 K_NM is built as well: the
+                            refinement's residuals use the FP64 A, so c converges to the FP64
+                            problem's solution (or the status is GAP_ENOCONV). */
+    GAP_MIXED_FP16 = 3   /* as GAP_MIXED_BF16 with FP16 descriptors and FP16 MFMA */
 } gap_precision;
 
 /* Fit parameters (host struct). */
@@ -165,17 +173,25 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
 
 /*
  * Predict total energies (Eqs. 1-2) of n_configs configurations against the
- * sparse set bound by the last gap_build_knm:
+ * sparse set bound by the last gap_build_knm (or gap_set_model):
  *   y_out[A] = sum_{i in A} sum_j c_j sigma_w^2 (x_i . x_j)^zeta.
  * x_atoms/offsets as in gap_build_knm; c [M] and y_out [n_configs] device FP64.
- * Uses no workspace.
+ * Uses no workspace.  The offsets are checked on the device before any
+ * descriptor is read: a configuration whose range is not inside [0, n_atoms),
+ * or offsets[0] != 0, or offsets[n_configs] != n_atoms, gives NaN energies for
+ * the configurations of its workgroup and GAP_EINVAL in the device status
+ * (read by gap_sync): the fit's status word on a fit handle, the first word of
+ * a bound workspace on a predict-only handle (none if it has no workspace).
  */
 gap_status gap_predict(gap_handle h, const double *x_atoms, int64_t n_atoms,
                        const int64_t *offsets, int64_t n_configs, const double *c, double *y_out);
 
 /* Bind a resident model's sparse set [M x d] (device FP64, caller-owned) for
  * gap_predict without a fit or a workspace (e.g. a served model whose fit has
- * finished and released its workspace).  GAP_EINVAL on NULL or M < 1. */
+ * finished and released its workspace).  The handle becomes predict-only: a
+ * fit's workspace bound before is no longer used.  A workspace bound after
+ * this call (>= 16 bytes) holds the handle's status word, which stays set
+ * until the workspace is bound again.  GAP_EINVAL on NULL or M < 1. */
 gap_status gap_set_model(gap_handle h, const double *x_sparse, int64_t M);
 
 /* Move the handle to another HIP stream (hipStream_t or NULL) for later calls. */
@@ -189,7 +205,8 @@ gap_status gap_layout(gap_handle h, gap_layout_info *out);
 
 /* Per-stage milliseconds of the last build/solve when GAP_FLAG_TIMING is set:
  * [0] K_NM kernel, [1] K_MM kernel, [2] Cholesky, [3] b assembly,
- * [4] Householder QR incl. Q^T b, [5] back-substitution, [6] refinement.
+ * [4] Householder QR incl. Q^T b, [5] back-substitution, [6] refinement,
+ * [7] low-precision K_NM (rounding the descriptors and the BF16/FP16 kernel).
  * Waits for the stream.  n = number of floats in ms (up to 8). */
 gap_status gap_stage_times(gap_handle h, float *ms, int n);
 

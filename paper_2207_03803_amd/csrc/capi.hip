@@ -28,14 +28,23 @@ struct Layout {
     bool mixed = false;
     size_t off_A32 = 0, off_W32 = 0, off_r = 0, off_s = 0, off_z = 0, off_dc = 0, off_p = 0, off_q = 0, off_part = 0,
            off_rnorm = 0, off_flags = 0, off_stats = 0;
+    // low-precision K_NM (GAP_MIXED_BF16 / GAP_MIXED_FP16) only: rounded descriptors
+    bool lp = false;
+    int dp = 0;
+    size_t off_Xlp = 0, off_XMlp = 0;
 };
+
+bool is_mixed(int32_t precision) { return precision != GAP_FP64; }
+bool is_lp(int32_t precision) { return precision == GAP_MIXED_BF16 || precision == GAP_MIXED_FP16; }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, bool mixed)
+Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, int32_t precision, int d)
 {
     Layout L;
+    const bool mixed = is_mixed(precision);
     L.mixed = mixed;
+    L.lp = is_lp(precision);
     L.N = N;
     L.M = M;
     L.n_atoms = n_atoms;
@@ -90,6 +99,11 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, bool mixed)
         L.off_rnorm = take(sizeof(double) * (size_t)((L.m + 255) / 256 + 1));
         L.off_flags = take(sizeof(int32_t) * 4);
         L.off_stats = take(sizeof(double) * 4);
+    }
+    if (L.lp) {
+        L.dp = knm_lp_dpad(d);
+        L.off_Xlp = take(sizeof(uint16_t) * (size_t)n_atoms * (size_t)L.dp);
+        L.off_XMlp = take(sizeof(uint16_t) * (size_t)M * (size_t)L.dp);
     }
     L.total = o;
     return L;
@@ -156,11 +170,21 @@ __global__ void copy_kernel(const double *src, double *dst, int64_t n)
         dst[i] = src[i];
 }
 
+// Where gap_predict reports malformed offsets: the fit's status word, or, on a
+// predict-only handle, the first word of a bound workspace (none without one).
+int32_t *predict_status(gap_handle h)
+{
+    if (!h->ws)
+        return nullptr;
+    return h->model_only ? reinterpret_cast<int32_t *>(h->ws) : h->status();
+}
+
 bool valid_params(const gap_params *p)
 {
     return p && p->d >= 1 && p->zeta >= 1 && p->zeta <= 8 && p->sigma_w > 0.0 && isfinite(p->sigma_w) &&
            p->jitter >= 0.0 && isfinite(p->jitter) &&
-           (p->precision == GAP_FP64 || p->precision == GAP_MIXED_FP32) &&
+           (p->precision == GAP_FP64 || p->precision == GAP_MIXED_FP32 || p->precision == GAP_MIXED_BF16 ||
+            p->precision == GAP_MIXED_FP16) &&
            (p->precision == GAP_FP64 || (p->max_refine_iters >= 0 && p->max_refine_iters <= 1000 &&
                                           p->refine_tol >= 0.0));
 }
@@ -198,7 +222,7 @@ size_t gap_workspace_bytes(const gap_params *p, int64_t n_configs, int64_t n_ato
 {
     if (!valid_params(p) || n_configs < 1 || n_atoms < 0 || M < 1)
         return 0;
-    return make_layout(n_configs, n_atoms, M, p->precision == GAP_MIXED_FP32).total;
+    return make_layout(n_configs, n_atoms, M, p->precision, p->d).total;
 }
 
 // Release a handle's events and side stream (those created so far) and the handle.
@@ -247,9 +271,16 @@ gap_status gap_bind_workspace(gap_handle h, void *dev_ptr, size_t bytes)
 {
     if (!h || !dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) & 255u))
         return GAP_EINVAL;
+    if (h->model_only && bytes < 16)
+        return GAP_EINVAL;
     h->ws = static_cast<char *>(dev_ptr);
     h->ws_bytes = bytes;
     h->state = ST_BOUND;
+    if (h->model_only) {
+        // a predict-only handle keeps its status word in the workspace's first bytes
+        hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, h->stream, reinterpret_cast<unsigned *>(h->ws), 4);
+        return dev(hipGetLastError());
+    }
     return GAP_OK;
 }
 
@@ -312,7 +343,7 @@ gap_status gap_build_knm(gap_handle h, const double *x_atoms, int64_t n_atoms, c
     if (!x_atoms || !config_offsets || !x_sparse || !sigma || n_atoms < 1 || n_configs < 1 || M < 1 ||
         n_configs > INT32_MAX - 1)
         return GAP_EINVAL;
-    const Layout L = make_layout(n_configs, n_atoms, M, h->p.precision == GAP_MIXED_FP32);
+    const Layout L = make_layout(n_configs, n_atoms, M, h->p.precision, h->p.d);
     if (L.total > h->ws_bytes)
         return GAP_ENOMEM;
     h->L = L;
@@ -364,6 +395,33 @@ gap_status gap_build_knm(gap_handle h, const double *x_atoms, int64_t n_atoms, c
     GAP_TRY(dev(launch_knm(a, L.max_tiles, s)));
     h->mark(0, true);
 
+    if (L.lp) {
+        // the factor's copy of Sigma^-1/2 K_NM from BF16 / FP16 dot products (FP32 power and sums)
+        const bool bf = p.precision == GAP_MIXED_BF16;
+        uint16_t *Xlp = h->at<uint16_t>(L.off_Xlp), *XMlp = h->at<uint16_t>(L.off_XMlp);
+        h->mark(7, false);
+        GAP_TRY(dev(launch_convert_lp(x_atoms, n_atoms, p.d, Xlp, bf, s)));
+        GAP_TRY(dev(launch_convert_lp(x_sparse, M, p.d, XMlp, bf, s)));
+        KnmLpLaunch l{};
+        l.X = Xlp;
+        l.XM = XMlp;
+        l.d = p.d;
+        l.offsets = config_offsets;
+        l.tile_start = kp.tile_start;
+        l.cfg_list = kp.cfg_list;
+        l.n_tiles_dev = kp.n_tiles;
+        l.max_tiles = L.max_tiles;
+        l.M = M;
+        l.zeta = p.zeta;
+        l.sw2 = sw2;
+        l.sigma = sigma;
+        l.out = h->at<float>(L.off_A32);
+        l.ldo = L.lda;
+        l.bf16 = bf;
+        GAP_TRY(dev(launch_knm_lp(l, s)));
+        h->mark(7, true);
+    }
+
     // K_MM + jitter (upper triangle) into rows N..N+M-1, then U = L^T in place.
     KnmArgs k{};
     k.X = x_sparse;
@@ -399,7 +457,10 @@ gap_status gap_sync(gap_handle h, gap_solve_info *info)
         return GAP_EDEVICE;
     int32_t st = 0;
     double res = 0.0;
-    if (h->ws && h->L.total) {
+    if (h->model_only && h->ws) {
+        if (hipMemcpy(&st, h->ws, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
+            return GAP_EDEVICE;
+    } else if (h->ws && h->L.total) {
         if (hipMemcpy(&st, h->status(), sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
             return GAP_EDEVICE;
         if (hipMemcpy(&res, h->misc(), sizeof(res), hipMemcpyDeviceToHost) != hipSuccess)
@@ -485,7 +546,13 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
         w.A32 = A32;
         w.W32 = h->at<float>(L.off_W32);
         h->mark(4, false);
-        GAP_TRY(dev(launch_convert_f64_f32(A, A32, L.lda * L.ncols, s)));
+        if (L.lp) {
+            // rows 0..N-1 came from the low-precision K_NM; L^T and b come from the FP64 [A | b]
+            GAP_TRY(dev(launch_convert_block_f64_f32(A, A32, L.lda, L.N, L.lda, 0, L.M, s)));
+            GAP_TRY(dev(launch_convert_block_f64_f32(A, A32, L.lda, 0, L.lda, L.M, L.M + 1, s)));
+        } else {
+            GAP_TRY(dev(launch_convert_f64_f32(A, A32, L.lda * L.ncols, s)));
+        }
         GAP_TRY(dev(launch_geqrf(w, s, (use_lookahead(h) && h->la.join) ? &h->la : nullptr)));
         h->mark(4, true);
         h->mark(5, false);
@@ -536,13 +603,20 @@ gap_status gap_predict(gap_handle h, const double *x_atoms, int64_t n_atoms, con
     const double sw2 = h->p.sigma_w * h->p.sigma_w;
     const int64_t M = h->model_only ? h->model_M : h->L.M;
     return dev(launch_predict(x_atoms, n_atoms, offsets, n_configs, h->x_sparse, M, h->p.d, h->p.zeta, sw2, c,
-                              y_out, h->stream));
+                              y_out, predict_status(h), h->stream));
 }
 
 gap_status gap_set_model(gap_handle h, const double *x_sparse, int64_t M)
 {
     if (!h || !x_sparse || M < 1)
         return GAP_EINVAL;
+    if (!h->model_only) {
+        // the handle becomes predict-only: a fit's workspace is no longer used
+        h->ws = nullptr;
+        h->ws_bytes = 0;
+        h->L = Layout();
+        h->state = ST_CREATED;
+    }
     h->x_sparse = x_sparse;
     h->model_M = M;
     h->model_only = true;
@@ -663,7 +737,7 @@ gap_status gap_fit_static(const gap_params *p, void *stream, const double *x_ato
     if (!x_atoms || !config_offsets || !x_sparse || !sigma || !y || !c_out || n_atoms < 1 || n_configs < 1 ||
         M < 1 || n_configs > INT32_MAX - 1)
         return GAP_EINVAL;
-    const size_t need = make_layout(n_configs, n_atoms, M, p->precision == GAP_MIXED_FP32).total;
+    const size_t need = make_layout(n_configs, n_atoms, M, p->precision, p->d).total;
     if (need > GAP_STATIC_SCRATCH_BYTES)
         return GAP_ENOMEM;
     gap_handle_s h;  // on the stack: no timing events, no look-ahead stream

@@ -124,6 +124,9 @@ struct RefineWork {
     TrsvSync sync;       // flags of the triangular solves
 };
 hipError_t launch_convert_f64_f32(const double *a, float *b, int64_t n, hipStream_t s);
+// Rows [r0, r1) of columns [c0, c1) of a column-major FP64 matrix into its FP32 copy (same ld).
+hipError_t launch_convert_block_f64_f32(const double *a, float *b, int64_t ld, int64_t r0, int64_t r1, int64_t c0,
+                                        int64_t c1, hipStream_t s);
 hipError_t launch_refine(const RefineWork &w, int max_iters, hipStream_t s);
 
 // ---------------------------------------------------------------- utilities

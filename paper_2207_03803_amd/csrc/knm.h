@@ -44,9 +44,33 @@ hipError_t launch_plan_tiles(const int64_t *offsets, int64_t N, int64_t n_atoms,
                              int32_t *status, hipStream_t s);
 hipError_t launch_knm(KnmArgs a, int64_t max_tiles, hipStream_t s);
 
+// ------------------------------------------------- low-precision K_NM (mixed form)
+// Descriptors rounded to BF16 or FP16 (round to nearest, ties to even) into
+// rows of knm_lp_dpad(d) elements, zero-padded.
+int knm_lp_dpad(int d);
+hipError_t launch_convert_lp(const double *x, int64_t rows, int d, uint16_t *out, bool bf16, hipStream_t s);
+struct KnmLpLaunch {
+    const uint16_t *X, *XM;     // rounded descriptors [n_atoms x dpad], sparse points [M x dpad]
+    int d;
+    const int64_t *offsets;     // CSR offsets and the tile plan of the FP64 build
+    const int32_t *tile_start, *cfg_list, *n_tiles_dev;
+    int64_t max_tiles;
+    int64_t M;
+    int zeta;
+    double sw2;
+    const double *sigma;        // [N]: rows divided by sigma
+    float *out;                 // FP32 column-major: out[col * ldo + configuration]
+    int64_t ldo;
+    bool bf16;                  // BF16 (true) or FP16 MFMA
+};
+hipError_t launch_knm_lp(const KnmLpLaunch &l, hipStream_t s);
+
 // --------------------------------------------------------------------- predict
+// Configurations whose offsets are not a range inside [0, n_atoms) (or offsets[0] != 0,
+// offsets[N] != n_atoms) get NaN energies and DST_EINVAL in *status (when non-null);
+// no descriptor outside [0, n_atoms) is read.
 hipError_t launch_predict(const double *X, int64_t n_atoms, const int64_t *offsets, int64_t N,
                           const double *XM, int64_t M, int d, int zeta, double sw2, const double *c,
-                          double *y, hipStream_t s);
+                          double *y, int32_t *status, hipStream_t s);
 
 }  // namespace gap

@@ -291,6 +291,19 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / KS::WN, wn = wave % KS::WN;
 
+    // K_MM, upper triangle only: a tile wholly below the diagonal is zero (no product)
+    if (unit && a.upper_only && t * KNM_BM > col0 + KNM_BN - 1) {
+        const int64_t r0 = t * KNM_BM;
+        const int nr = (int)((a.n_rows_unit - r0) < KNM_BM ? (a.n_rows_unit - r0) : KNM_BM);
+        for (int item = tid; item < nr * KNM_BN; item += KS::NT) {
+            const int r = item % nr, c = item / nr;
+            const int64_t colg = col0 + c;
+            if (colg < a.M)
+                a.out[colg * a.ldo + a.row_off + r0 + r] = 0.0;
+        }
+        return;
+    }
+
     // The tile's segments: rows of the unit block, or configurations from the plan.
     int n_seg;
     int64_t n_at;  // atoms in the tile
@@ -466,13 +479,15 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
 // configuration adds its atoms' energies in atom order.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256, 2) void predict_kernel(const double *__restrict__ X, const int64_t *offsets,
-                                                      int64_t N, const double *__restrict__ XM, int64_t M,
-                                                      int d, int zeta, double sw2,
-                                                      const double *__restrict__ c, double *y, int64_t C)
+                                                      int64_t N, int64_t n_atoms, const double *__restrict__ XM,
+                                                      int64_t M, int d, int zeta, double sw2,
+                                                      const double *__restrict__ c, double *y, int64_t C,
+                                                      int32_t *status)
 {
     __shared__ double lds[2 * KS::STAGE];
     __shared__ double eps[KNM_BM];
     __shared__ double part[KS::WN][KNM_BM];
+    __shared__ int bad_s;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / KS::WN, wn = wave % KS::WN;
     const int64_t cfg_lo = (int64_t)blockIdx.x * C;
@@ -481,13 +496,33 @@ __global__ __launch_bounds__(256, 2) void predict_kernel(const double *__restric
         cfg_hi = N;
     if (cfg_lo >= cfg_hi)
         return;
-    const int64_t atom_lo = offsets[cfg_lo], atom_hi = offsets[cfg_hi];
     const int ncfg = (int)(cfg_hi - cfg_lo);
+    // Validate this workgroup's offsets before any descriptor is read: each of its
+    // configurations must be a range inside [0, n_atoms) (so every row read is in
+    // bounds); offsets[0] = 0 and offsets[N] = n_atoms are checked by the first
+    // and last workgroup.  A violation gives NaN energies for the workgroup's
+    // configurations and GAP_EINVAL in the status word (when there is one).
+    if (tid == 0)
+        bad_s = 0;
+    __syncthreads();
     int64_t my_lo = 0, my_hi = 0;
     if (tid < ncfg) {
         my_lo = offsets[cfg_lo + tid];
         my_hi = offsets[cfg_lo + tid + 1];
+        if (my_lo < 0 || my_hi < my_lo || my_hi > n_atoms)
+            bad_s = 1;
     }
+    if (tid == 0 && ((cfg_lo == 0 && offsets[0] != 0) || (cfg_hi == N && offsets[N] != n_atoms)))
+        bad_s = 1;
+    __syncthreads();
+    if (bad_s) {
+        if (tid < ncfg)
+            y[cfg_lo + tid] = __builtin_nan("");
+        if (tid == 0 && status)
+            set_status(status, DST_EINVAL);
+        return;
+    }
+    const int64_t atom_lo = offsets[cfg_lo], atom_hi = offsets[cfg_hi];
     double ysum = 0.0;
     const int64_t n_ct = (M + KNM_BN - 1) / KNM_BN;
     d4 acc[KS::FM][KS::FN];
@@ -544,7 +579,7 @@ __global__ __launch_bounds__(256, 2) void predict_kernel(const double *__restric
 
 hipError_t launch_predict(const double *X, int64_t n_atoms, const int64_t *offsets, int64_t N,
                           const double *XM, int64_t M, int d, int zeta, double sw2, const double *c,
-                          double *y, hipStream_t s)
+                          double *y, int32_t *status, hipStream_t s)
 {
     if (N <= 0)
         return hipSuccess;
@@ -554,8 +589,8 @@ hipError_t launch_predict(const double *X, int64_t n_atoms, const int64_t *offse
     if (C > 256)
         C = 256;
     const int64_t grid = (N + C - 1) / C;
-    hipLaunchKernelGGL(predict_kernel, dim3((unsigned)grid), dim3(KS::NT), 0, s, X, offsets, N, XM, M, d,
-                       zeta, sw2, c, y, C);
+    hipLaunchKernelGGL(predict_kernel, dim3((unsigned)grid), dim3(KS::NT), 0, s, X, offsets, N, n_atoms, XM, M,
+                       d, zeta, sw2, c, y, C, status);
     return hipGetLastError();
 }
 

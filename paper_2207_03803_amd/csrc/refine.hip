@@ -48,6 +48,30 @@ hipError_t launch_convert_f64_f32(const double *a, float *b, int64_t n, hipStrea
     return hipGetLastError();
 }
 
+// b[r, c] = a[r, c] for rows [r0, r1) of columns [c0, c1) (column-major, ld).
+__global__ void convert_block_f64_f32_kernel(const double *__restrict__ a, float *__restrict__ b, int64_t ld,
+                                             int64_t r0, int64_t r1, int64_t c0, int64_t c1)
+{
+    const int64_t nr = r1 - r0, total = nr * (c1 - c0);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        const int64_t c = c0 + i / nr, r = r0 + i % nr;
+        b[c * ld + r] = (float)a[c * ld + r];
+    }
+}
+
+hipError_t launch_convert_block_f64_f32(const double *a, float *b, int64_t ld, int64_t r0, int64_t r1, int64_t c0,
+                                        int64_t c1, hipStream_t s)
+{
+    const int64_t total = (r1 - r0) * (c1 - c0);
+    if (total <= 0)
+        return hipSuccess;
+    int64_t g = (total + 255) / 256;
+    if (g > 65536)
+        g = 65536;
+    hipLaunchKernelGGL(convert_block_f64_f32_kernel, dim3((unsigned)g), dim3(256), 0, s, a, b, ld, r0, r1, c0, c1);
+    return hipGetLastError();
+}
+
 // Fixed-order sum of a 256-thread workgroup (identical in every workgroup for
 // identical inputs).
 __device__ __forceinline__ double block_sum(double v, double *red)

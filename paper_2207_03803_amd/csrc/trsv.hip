@@ -17,21 +17,24 @@ constexpr uint64_t TS_WAIT_TICKS = 1000000000ull;
 //
 // One launch solves the whole system.  The block rows (64 rows each) are
 // numbered in dependency order q = 0 .. nb-1 (the last block row first for
-// R x = rhs, the first one first for R^T x = rhs); workgroup g takes q = g,
-// g + G, ...  A block row first accumulates the products with the blocks of
-// every earlier block row, in order, waiting for each one's ready flag (its
+// R x = rhs, the first one first for R^T x = rhs).  A workgroup takes its next
+// item from an atomic ticket when it starts it, so items are handed out in
+// order to workgroups that are already running: every item a workgroup waits
+// on (a smaller q) belongs to a running workgroup, whatever the dispatch order
+// of the launch or the other work on the GPU, and the lowest unfinished q can
+// always proceed.  A block row first accumulates the products with the blocks
+// of every earlier block row, in order, waiting for each one's ready flag (its
 // R values are loaded before the wait), then one wave solves the diagonal
-// block and publishes x with a release and the flag.  The workgroups of one
-// solve are few (G <= 256) and all wait only on smaller q, so the lowest
-// unfinished q can always proceed.  The last workgroup to finish clears the
-// flags for the next solve (they must be zero before the first one).
-// When skip is non-null and *skip != 0 the kernel returns at once.
+// block and publishes x with a release and the flag.  The last workgroup to
+// finish clears the flags and the ticket for the next solve (they must be zero
+// before the first one).  When skip is non-null and *skip != 0 the kernel
+// returns at once.
 
 struct TrsvArgs {
     int64_t ld, n, nb;
     const double *rhs;
     double *x;
-    int32_t *flags;     // [nb + 1]: ready flag per block row; [nb] = abort
+    int32_t *flags;     // [nb + 2]: ready flag per block row; [nb] = abort; [nb + 1] = ticket
     unsigned *counter;  // arrival counter (zero between solves)
     const int32_t *skip;
     int32_t *status;
@@ -89,12 +92,20 @@ __global__ __launch_bounds__(256) void trsv_fused_kernel(const TR *__restrict__ 
     __shared__ double xs[TB];
     __shared__ int64_t ready_lds;
     __shared__ int last_lds;
+    __shared__ int32_t ticket_lds;
     if (a.skip && *a.skip)
         return;
     const int t = threadIdx.x, lane = t & 63, grp = t >> 6;
     const int64_t ld = a.ld, n = a.n, nb = a.nb;
     bool alive = true;
-    for (int64_t q = blockIdx.x; q < nb && alive; q += gridDim.x) {
+    auto take = [&]() -> int64_t {
+        __syncthreads();  // every thread is done with the previous item's shared state
+        if (t == 0)
+            ticket_lds = __hip_atomic_fetch_add(&a.flags[nb + 1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        return ticket_lds;
+    };
+    for (int64_t q = take(); q < nb && alive; q = take()) {
         const int64_t i = TRANS ? q : nb - 1 - q;
         const int64_t b0 = i * TB;
         const int bw = (int)((n - b0) < TB ? (n - b0) : TB);
@@ -208,7 +219,7 @@ __global__ __launch_bounds__(256) void trsv_fused_kernel(const TR *__restrict__ 
     // the last workgroup to finish clears the flags for the next solve
     if (!arrive_last(a.counter, gridDim.x, &last_lds))
         return;
-    for (int64_t k = t; k <= nb; k += 256)
+    for (int64_t k = t; k <= nb + 1; k += 256)
         a.flags[k] = 0;
 }
 

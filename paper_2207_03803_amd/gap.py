@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgap.so")
 
 GAP_OK, GAP_EINVAL, GAP_ENOMEM, GAP_ENOTPD, GAP_ENONFINITE, GAP_ENOCONV, GAP_EDEVICE, GAP_ESTATE, GAP_ERANK = range(9)
-GAP_FP64, GAP_MIXED_FP32 = 0, 1
+GAP_FP64, GAP_MIXED_FP32, GAP_MIXED_BF16, GAP_MIXED_FP16 = 0, 1, 2, 3
 GAP_FLAG_TIMING = 1
 
 # Every entry point include/gap.h declares.
@@ -23,7 +23,7 @@ EXPORTS = ["gap_create", "gap_workspace_bytes", "gap_bind_workspace", "gap_build
            "gap_set_tuning", "gap_set_model", "gap_set_stream", "gap_destroy", "gap_fit_static",
            "gap_static_scratch_bytes"]
 
-STAGES = ["knm", "kmm", "cholesky", "assemble_b", "qr", "trsv", "refine", "reserved"]
+STAGES = ["knm", "kmm", "cholesky", "assemble_b", "qr", "trsv", "refine", "knm_lp"]
 
 
 class GapParams(ctypes.Structure):

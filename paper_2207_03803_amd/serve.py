@@ -287,8 +287,12 @@ class Server:
             req.done = now
             req.result = out.cpu().numpy()
             req.meta["status"] = s
-            # release the workspace (the handle stays with its slot); the weights stay resident as the model
+            # release the workspace (the handle stays with its slot); the weights of a fit that
+            # ended GAP_OK stay resident as a model, those of a failed fit are released
             self.arena.release(blocks[0])
+            if s != gap.GAP_OK:
+                self.arena.release(blocks[1])
+                return False
             self.models[req.rid] = (req.meta["XM"], out, req.spec.zeta, req.spec.d, None, blocks[1])
             busy = {k for k, v in self.model_users.items() if v > 0}
             while len(self.models) > self.resident_max:

@@ -168,6 +168,54 @@ def test_bad_offsets_are_reported(orc_m):
     assert s == gap.GAP_EINVAL
 
 
+def test_predict_rejects_bad_offsets(orc_m):
+    """Malformed offsets in a predict request (swapped, past n_atoms, offsets[0] != 0)
+    give NaN energies where they occur and GAP_EINVAL, on a fit handle and on a
+    predict-only handle with a status workspace; good requests are unaffected."""
+    import torch
+
+    from paper_2207_03803_amd import gap
+
+    inp, y, ref = _case(orc_m, 600, (8, 64), 64, 40, 2, seed=9)
+    g = GpuFit(inp.X, inp.offsets, inp.XM, inp.sigma, y, 2)
+    g.build()
+    c, info = g.solve()
+    assert info.device_status == gap.GAP_OK
+    n = inp.n_configs
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    swapped = inp.offsets.copy()
+    swapped[400], swapped[401] = swapped[401], swapped[400]
+    past = inp.offsets.copy()
+    past[300:] += 10_000_000  # every range from configuration 299 on ends past the descriptors
+    shifted = inp.offsets.copy()
+    shifted[0] = 3
+    ph = gap.Handle(gap.params(64, 2, 1.0, 1e-8))
+    ph.set_model(g.XM)
+    status_ws = torch.zeros(256, dtype=torch.uint8, device="cuda")
+    ph.bind(status_ws)
+    for name, offs in (("swapped", swapped), ("past n_atoms", past), ("offsets[0] != 0", shifted)):
+        g.build()  # clears the fit handle's status word (the weights stay in g.c)
+        for h in (g.h, ph):
+            assert h.sync()[0] == gap.GAP_OK
+            out.fill_(0.0)
+            h.predict(g.X, to_dev(offs), g.c, out)
+            s, _ = h.sync()
+            got = out.cpu().numpy()
+            log(f"  predict with {name} offsets: status {gap.status_string(s)}, {np.isnan(got).sum()} NaN of {n}")
+            assert s == gap.GAP_EINVAL
+            assert np.isnan(got).any()
+        ph.bind(status_ws)  # clears the predict-only handle's status word
+    # a good request on a fresh predict-only handle: finite, status OK
+    ph2 = gap.Handle(gap.params(64, 2, 1.0, 1e-8))
+    ph2.set_model(g.XM)
+    ph2.bind(torch.zeros(256, dtype=torch.uint8, device="cuda"))
+    ph2.predict(g.X, g.offsets, g.c, out)
+    assert ph2.sync()[0] == gap.GAP_OK
+    assert np.isfinite(out.cpu().numpy()).all()
+    for h in (ph, ph2):
+        h.close()
+
+
 def test_repeat_runs_are_bitwise_identical(orc_m):
     inp, y, ref = _case(orc_m, 150, (8, 64), 64, 200, 2, seed=10)
     g = GpuFit(inp.X, inp.offsets, inp.XM, inp.sigma, y, 2)

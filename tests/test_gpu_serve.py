@@ -72,7 +72,7 @@ def test_served_results_match_alone_and_oracle(served):
                               m["sigma"].cpu().numpy(), m["y"].cpu().numpy(), r.spec.zeta, jitter=1e-8)
                 err = float(np.linalg.norm(r.result - ref.c) / np.linalg.norm(ref.c))
                 log(f"  served fit {r.rid}: N={r.spec.n_configs} M={r.spec.M} d={r.spec.d}: c rel err {err:.2e}")
-                assert err <= 1e-8
+                assert err <= 1e-10  # served in FP64 (the server's default precision)
                 checked += 1
         elif r.model >= 0:
             XM, c, zeta, d, _, _ = srv.models[r.model] if r.model in srv.models else (None,) * 6
