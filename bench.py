@@ -3,6 +3,8 @@ the realistic workload, N = 1e5 configurations of 16..64 atoms, d = 400,
 M = 1e4 sparse points, zeta = 4, FP64, beside the three forms around it:
 
   mixed  the same fit with an FP32 Householder QR and FP64 refinement of c
+  bf16   mixed, with the factored K_NM block from BF16 descriptor dot products
+  fp16   mixed, with FP16 descriptor dot products
   sweep  64 uneven fits of a hyperparameter sweep replayed as one HIP graph
          (FP32 QR + FP64 refinement), against the same fits run one after
          another in plain FP64
@@ -11,7 +13,7 @@ M = 1e4 sparse points, zeta = 4, FP64, beside the three forms around it:
 
 Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms mixed,sweep,serve | none]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms mixed,bf16,fp16,sweep,serve | none]
                   [--workload realistic_fp64|tiny_fp64] [--no-cpu-baseline]
 
 A step is one whole fit on inputs already resident in HBM; `value` is the FP64
@@ -33,7 +35,10 @@ os.environ["GPU_MAX_HW_QUEUES"] = "16"
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_MFMA = 78.6e12   # MI355X dense FP64 matrix peak, FLOP/s
+PEAK_FP32_MFMA = 157.3e12  # MI355X dense FP32 matrix peak, FLOP/s
+PEAK_BF16_MFMA = 2.5e15    # MI355X dense BF16 / FP16 matrix peak, FLOP/s
 PEAK_HBM = 8.0e12          # MI355X HBM3E, B/s
+GOLDEN = os.path.join(ROOT, "tests", "golden", "realistic_fp64_seed0.npz")
 
 
 def log(msg):
@@ -52,6 +57,19 @@ def knm_traffic():
     if source_hash() != rec.get("source_sha256"):
         return None
     return rec["traffic_bytes_per_launch"]
+
+
+def load_reference(workload, seed):
+    """The oracle's full-size reference fit (y, c, loss) for this workload and seed,
+    or None (written by tests/golden/make_reference_fits.py from the oracle alone)."""
+    import numpy as np
+
+    if workload != "realistic_fp64" or seed != 0 or not os.path.exists(GOLDEN):
+        return None
+    z = np.load(GOLDEN, allow_pickle=False)
+    ref = {k: z[k] for k in z.files if k != "meta"}
+    ref["meta"] = json.loads(str(z["meta"]))
+    return ref
 
 
 def fit_flops(n_atoms, N, M, d):
@@ -84,8 +102,9 @@ def cpu_baseline(workload, budget_note):
     orc.knm(inp.X, inp.offsets, inp.XM, zeta)
     t_knm = time.perf_counter() - t0
     f_knm_s = 2.0 * inp.n_atoms * Ms * d
-    # QR sample: m x n Householder QR with the b column
-    ms, ns = (8000, 2500) if workload != "tiny_fp64" else (w["n_configs"] + w["M"], w["M"])
+    # QR sample: m x n Householder QR with the b column, at the workload's full row count
+    # (the oracle's column steps stream the trailing matrix: their rate depends on m)
+    ms, ns = (w["n_configs"] + w["M"], 400) if workload != "tiny_fp64" else (w["n_configs"] + w["M"], w["M"])
     rng = np.random.default_rng(7)
     A = rng.standard_normal((ms, ns))
     b = rng.standard_normal(ms)
@@ -180,8 +199,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="realistic_fp64")
-    ap.add_argument("--forms", default="mixed,sweep,serve",
+    ap.add_argument("--forms", default="mixed,bf16,fp16,sweep,serve",
                     help="comma-separated forms to measure beside the FP64 fit, or none")
+    ap.add_argument("--inputs", choices=("host", "device"), default="host",
+                    help="host: numpy descriptors (the arrays the oracle's full-size reference fit used); "
+                         "device: torch's generator on the GPU (faster to draw, no oracle reference)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--serve-sweep", action="store_true",
@@ -218,14 +240,24 @@ def main():
         return
     w = dict(synth.WORKLOADS[args.workload])
     N, M, d, zeta = w["n_configs"], w["M"], w["d"], w["zeta"]
-    log(f"[bench] generating {args.workload}: N={N} M={M} d={d} zeta={zeta}")
+    log(f"[bench] generating {args.workload}: N={N} M={M} d={d} zeta={zeta} ({args.inputs})")
     t0 = time.perf_counter()
-    inp = synth.make_fit_inputs_torch(seed=args.seed, device=dev, **w)
+    ref = None
+    if args.inputs == "host":
+        # the oracle's reference fit was computed on exactly these arrays
+        inp = synth.make_fit_inputs_blocked(seed=args.seed, workers=16, log=log, **w)
+        X = torch.from_numpy(inp.X).to(dev)
+        XM = torch.from_numpy(inp.XM).to(dev)
+        inp.X = None
+        ref = load_reference(args.workload, args.seed)
+    else:
+        inp = synth.make_fit_inputs_torch(seed=args.seed, device=dev, **w)
+        X, XM = inp.X, inp.XM
     offsets = torch.from_numpy(inp.offsets).to(dev)
     sigma = torch.from_numpy(inp.sigma).to(dev)
-    X, XM = inp.X, inp.XM
     n_atoms = inp.n_atoms
-    log(f"[bench] inputs ready in {time.perf_counter() - t0:.1f}s (n_atoms={n_atoms})")
+    log(f"[bench] inputs ready in {time.perf_counter() - t0:.1f}s (n_atoms={n_atoms}; oracle reference: "
+        f"{'yes' if ref is not None else 'no'})")
     f = fit_flops(n_atoms, N, M, d)
 
     def run_fit(precision, steps, warmup, y=None):
@@ -236,8 +268,9 @@ def main():
             return _run_fit(precision, steps, warmup, y)
 
     def _run_fit(precision, steps, warmup, y=None):
+        iters = 30 if precision in (gap.GAP_FP64, gap.GAP_MIXED_FP32) else 200
         p = gap.params(d, zeta, w["sigma_w"], w["jitter"], precision=precision, flags=gap.GAP_FLAG_TIMING,
-                       max_refine_iters=30, refine_tol=1e-12)
+                       max_refine_iters=iters, refine_tol=1e-12)
         h = gap.Handle(p)
         # one fit on a stream of its own and nothing on the legacy stream meanwhile:
         # keep CUs free of the QR look-ahead stream for the panel chain
@@ -261,7 +294,8 @@ def main():
                 for k, v in st.items():
                     stage_sum[k] = stage_sum.get(k, 0.0) + v
 
-        tag = "fp64" if precision == gap.GAP_FP64 else "mixed"
+        tag = {gap.GAP_FP64: "fp64", gap.GAP_MIXED_FP32: "mixed", gap.GAP_MIXED_BF16: "mixed_bf16",
+               gap.GAP_MIXED_FP16: "mixed_fp16"}[precision]
         for i in range(warmup):
             step(False)
             log(f"[bench] {tag} warmup {i + 1}/{warmup} done")
@@ -276,16 +310,27 @@ def main():
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         s_status, info = h.sync()
-        if s_status != gap.GAP_OK:
+        if s_status != gap.GAP_OK and not (s_status == gap.GAP_ENOCONV and precision in (gap.GAP_MIXED_BF16,
+                                                                                           gap.GAP_MIXED_FP16)):
             raise RuntimeError(f"{tag} fit: device status {gap.status_string(s_status)}")
         h.close()
         del h
         torch.cuda.empty_cache()
         stages_ms = {k: v / steps for k, v in stage_sum.items() if v > 0}
         return dict(ms=1e3 * elapsed / steps, ms_median=1e3 * float(np.median(per_step)),
-                    ms_min=1e3 * min(per_step), stages_ms=stages_ms, info=info, c=c, y=y)
+                    ms_min=1e3 * min(per_step), stages_ms=stages_ms, info=info, c=c, y=y, status=s_status)
 
-    fp = run_fit(gap.GAP_FP64, args.steps, args.warmup)
+    def vs_oracle(res):
+        """c and the minimum loss of a timed fit against the oracle's reference fit."""
+        if ref is None:
+            return {}
+        c = res["c"].cpu().numpy()
+        return {"c_rel_err_vs_oracle": float(np.linalg.norm(c - ref["c"]) / np.linalg.norm(ref["c"])),
+                "loss_rel_err_vs_oracle": abs(res["info"].residual_norm2 - float(ref["loss_tail"]))
+                / float(ref["loss_tail"])}
+
+    y_ref = torch.from_numpy(ref["y"]).to(dev) if ref is not None else None
+    fp = run_fit(gap.GAP_FP64, args.steps, args.warmup, y=y_ref)
     ms_per_step = fp["ms"]
     step_stats = {"median_ms": fp["ms_median"], "min_ms": fp["ms_min"]}
     stages_ms = fp["stages_ms"]
@@ -297,21 +342,56 @@ def main():
         "cholesky_tflops": f["cholesky"] / (stages_ms["cholesky"] / 1e3) / 1e12,
         "qr_tflops": f["qr"] / (stages_ms["qr"] / 1e3) / 1e12,
     }
+    fp_oracle = vs_oracle(fp)
+    if fp_oracle:
+        log(f"[bench] fp64: c rel err vs oracle {fp_oracle['c_rel_err_vs_oracle']:.2e}")
+    rooflines = [
+        {"stage": "knm", "kernel": "knm_kernel", "bound": "mfma", "dtype": "f64",
+         "achieved": f["knm"] / knm_s / 1e12, "peak": PEAK_FP64_MFMA / 1e12},
+        {"stage": "qr", "kernel": "qr_wpart_kernel + qr_update_kernel (+ panels)", "bound": "mfma", "dtype": "f64",
+         "achieved": stage_rates["qr_tflops"], "peak": PEAK_FP64_MFMA / 1e12},
+        {"stage": "cholesky", "kernel": "chol_*", "bound": "mfma", "dtype": "f64",
+         "achieved": stage_rates["cholesky_tflops"], "peak": PEAK_FP64_MFMA / 1e12},
+    ]
     # the forms are measured around the realistic workload only
     forms = [] if args.forms == "none" or args.workload != "realistic_fp64" else args.forms.split(",")
     extra = {}
-    if "mixed" in forms:
-        mx = run_fit(gap.GAP_MIXED_FP32, args.steps, args.warmup, y=fp["y"])
+    notes = {
+        "mixed": "FP64 K_NM/Cholesky, FP32 Householder QR (FP64 reflector norms), FP64 refinement (corrected "
+                 "semi-normal equations, then R-preconditioned CGLS) to ||dc||/||c|| <= 1e-12",
+        "mixed_bf16": "as mixed, with the factored K_NM block from BF16 descriptor dot products on MFMA (FP32 "
+                      "accumulation, power and sums); the FP64 K_NM is built too, for the refinement's residuals",
+        "mixed_fp16": "as mixed_bf16 with FP16 descriptors",
+    }
+    for form, prec in (("mixed", gap.GAP_MIXED_FP32), ("bf16", gap.GAP_MIXED_BF16), ("fp16", gap.GAP_MIXED_FP16)):
+        if form not in forms:
+            continue
+        key = "mixed" if form == "mixed" else f"mixed_{form}"
+        mx = run_fit(prec, args.steps, args.warmup, y=fp["y"])
         err = float((mx["c"] - fp["c"]).norm() / fp["c"].norm())
-        extra["mixed"] = {
+        qr32 = f["qr"] / (mx["stages_ms"]["qr"] / 1e3) / 1e12
+        extra[key] = {
             "s_per_fit": mx["ms"] / 1e3, "median_ms": mx["ms_median"], "min_ms": mx["ms_min"],
             "speedup_vs_fp64": ms_per_step / mx["ms"], "stages_ms": mx["stages_ms"],
-            "qr_tflops_fp32": f["qr"] / (mx["stages_ms"]["qr"] / 1e3) / 1e12,
-            "refine_iters": mx["info"].refine_iters, "last_dc_over_c": mx["info"].grad_rel,
-            "c_rel_err_vs_fp64_path": err,
-            "note": "FP64 K_NM/Cholesky, FP32 Householder QR (FP64 reflector norms), FP64 CSNE refinement to "
-                    "||dc||/||c|| <= 1e-12"}
-        log(f"[bench] mixed: {mx['ms']:.1f} ms per fit, c rel err vs FP64 {err:.2e}")
+            "qr_tflops_fp32": qr32, "status": gap.status_string(mx["status"]),
+            "refine_iters": mx["info"].refine_iters, "cgls_iters": mx["info"].cgls_iters,
+            "last_dc_over_c": mx["info"].step_rel, "eta": mx["info"].grad_rel,
+            "c_rel_err_vs_fp64_path": err, **vs_oracle(mx), "note": notes[key]}
+        if form == "mixed":
+            rooflines.append({"stage": "qr", "kernel": "qr_wpart32 + qr_update32 (+ panels)", "bound": "mfma",
+                              "dtype": "f32", "achieved": qr32, "peak": PEAK_FP32_MFMA / 1e12})
+        else:
+            t_lp = mx["stages_ms"].get("knm_lp", 0.0) / 1e3
+            if t_lp > 0:
+                extra[key]["knm_lp_tflops"] = f["knm"] / t_lp / 1e12
+                rooflines.append({"stage": "knm_lp", "kernel": "knm_lp_kernel (+ descriptor rounding)",
+                                  "bound": "mfma", "dtype": form, "achieved": f["knm"] / t_lp / 1e12,
+                                  "peak": PEAK_BF16_MFMA / 1e12})
+        log(f"[bench] {key}: {mx['ms']:.1f} ms per fit ({gap.status_string(mx['status'])}, "
+            f"{mx['info'].refine_iters} refinement steps), c rel err vs FP64 path {err:.2e}")
+    for r in rooflines:
+        r["unit"] = "TFLOP/s"
+        r["frac"] = r["achieved"] / r["peak"]
     del fp
     torch.cuda.empty_cache()
     if "sweep" in forms or "serve" in forms:
@@ -329,6 +409,12 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         cpu = cpu_baseline(args.workload, "reported baseline, not a target")
+        if ref is not None:
+            m = ref["meta"]
+            cpu["measured_full_fit"] = {
+                "seconds": m["total_s"], "threads": m["threads"], "stages_s": {
+                    k: m[k] for k in ("knm_s", "kmm_chol_s", "qr_s") if k in m},
+                "host": "the build container's CPU (not this GPU host), by tests/golden/make_reference_fits.py"}
         log("[bench] timing host LAPACK / BLAS on a bounded sample")
         extra["cpu_lapack"] = lapack_baseline(args.workload)
     out = {
@@ -354,8 +440,12 @@ def main():
         "roofline": {"kernel": "knm_kernel", "bound": "mfma", "achieved": achieved / 1e12,
                      "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA,
                      "traffic": traffic},
+        "roofline_stages": rooflines,
         "cpu_baseline": cpu,
     }
+    if fp_oracle:
+        out["parity_vs_oracle"] = dict(fp_oracle, kappa_A=float(ref["smax"] / ref["smin"]),
+                                       kappa_u=float(ref["smax"] / ref["smin"]) * 2.0 ** -53)
     out.update(extra)
     print(json.dumps(out), flush=True)
 

@@ -95,6 +95,9 @@ typedef struct gap_params {
 
 /* Record per-stage durations with HIP events (read back by gap_stage_times). */
 #define GAP_FLAG_TIMING 1u
+/* Estimate the relative error of c (gap_solve_info.est_err): 16 steps each of
+ * power and inverse iteration on R for kappa_2(A), about 32 triangular solves. */
+#define GAP_FLAG_ERROR_ESTIMATE 2u
 
 typedef struct gap_handle_s *gap_handle;
 
@@ -103,10 +106,20 @@ typedef struct gap_solve_info {
     int32_t refine_iters;    /* mixed precision: refinement iterations done (0 in FP64) */
     double residual_norm2;   /* min of the loss at the returned c: ||(Q^T b)[M:]||^2 in FP64,
                                 ||b - A c||^2 against the FP64 A in mixed precision */
-    double grad_rel;         /* mixed precision: last step's ||dc|| / ||c||; 0 in FP64 */
+    double grad_rel;         /* normal-equation residual (zero gradient of Eq. loss, Eq. GP_sparse)
+                                of the returned c: ||A^T (b - A c)|| / (||A||_F (||A||_F ||c|| + ||b||)).
+                                Mixed precision: against the FP64 A.  FP64: in the factored basis,
+                                A^T r = R^T ((Q^T b)[0:M] - R c), which checks the back-substitution
+                                (the QR's own backward error, about u, is not included) */
     int32_t cgls_iters;      /* mixed precision: how many of refine_iters were preconditioned
                                 CGLS steps (0 when the corrected semi-normal equations converged) */
     int32_t reserved;        /* 0 */
+    double step_rel;         /* mixed precision: the last refinement step's ||dc|| / ||c||; 0 in FP64 */
+    double est_err;          /* with GAP_FLAG_ERROR_ESTIMATE: estimated relative error of c,
+                                u (kappa + kappa^2 ||r|| / (||A||_2 ||c||)), u = 2^-53, kappa =
+                                kappa_2(A) from power / inverse iteration on R (the FP32 R in mixed
+                                precision); -1 when not requested */
+    double kappa_est;        /* the kappa_2(A) estimate behind est_err (0 when not requested) */
 } gap_solve_info;
 
 /* Where the library keeps its stage outputs inside the bound workspace (host struct).
@@ -206,8 +219,9 @@ gap_status gap_layout(gap_handle h, gap_layout_info *out);
 /* Per-stage milliseconds of the last build/solve when GAP_FLAG_TIMING is set:
  * [0] K_NM kernel, [1] K_MM kernel, [2] Cholesky, [3] b assembly,
  * [4] Householder QR incl. Q^T b, [5] back-substitution, [6] refinement,
- * [7] low-precision K_NM (rounding the descriptors and the BF16/FP16 kernel).
- * Waits for the stream.  n = number of floats in ms (up to 8). */
+ * [7] low-precision K_NM (rounding the descriptors and the BF16/FP16 kernel),
+ * [8] solution diagnostics (grad_rel, and est_err when requested).
+ * Waits for the stream.  n = number of floats in ms (up to 9). */
 gap_status gap_stage_times(gap_handle h, float *ms, int n);
 
 /* Launch-shape and method knobs an autotuner may set per handle (0 = library default).

@@ -13,7 +13,7 @@ using namespace gap;
 
 namespace {
 
-constexpr int N_STAGES = 8;
+constexpr int N_STAGES = 9;
 
 enum State { ST_CREATED = 0, ST_BOUND = 1, ST_BUILT = 2, ST_SOLVED = 3 };
 
@@ -28,6 +28,7 @@ struct Layout {
     bool mixed = false;
     size_t off_A32 = 0, off_W32 = 0, off_r = 0, off_s = 0, off_z = 0, off_dc = 0, off_p = 0, off_q = 0, off_part = 0,
            off_rnorm = 0, off_flags = 0, off_stats = 0;
+    size_t off_diag = 0;  // diagnostics of the solution (eta, error estimate)
     // low-precision K_NM (GAP_MIXED_BF16 / GAP_MIXED_FP16) only: rounded descriptors
     bool lp = false;
     int dp = 0;
@@ -85,6 +86,7 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, int32_t precision, int
     L.off_wpart_s = take(sizeof(double) * (size_t)qr_max_chunks_s() * 2 * QR_NB * 2 * QR_NB);
     L.off_W_s = take(sizeof(double) * 4 * QR_NB * QR_NB);
     L.off_W32_s = take(sizeof(float) * 4 * QR_NB * QR_NB);
+    L.off_diag = take(sizeof(double) * (size_t)(14 * M + 512));
     if (mixed) {
         const int64_t ldw = (L.ncols + 63) / 64 * 64;
         L.off_A32 = take(sizeof(float) * (size_t)L.lda * (size_t)L.ncols);
@@ -138,6 +140,31 @@ struct gap_handle_s {
     double *misc() const { return at<double>(L.off_misc); }
     // flags of the one-launch triangular solves; counters()[12] is their arrival counter
     TrsvSync tsync() const { return TrsvSync{at<int32_t>(L.off_tflags), counters() + 12, status()}; }
+
+    // diagnostics area: [8M] partials, partR, t, g, x, y, z [M each], sc[4], sumsq partials[256], out[4]
+    DiagWork diag(double *g_override) const
+    {
+        double *base = at<double>(L.off_diag);
+        const int64_t M = L.M;
+        DiagWork d{};
+        d.n = M;
+        d.ld = L.lda;
+        d.part = base;
+        d.partR = base + 8 * M;
+        d.t = base + 9 * M;
+        d.g = g_override ? g_override : base + 10 * M;
+        d.x = base + 11 * M;
+        d.y = base + 12 * M;
+        d.z = base + 13 * M;
+        d.sc = base + 14 * M;
+        d.sum_part = d.sc + 4;
+        d.counter = counters() + 9;
+        d.tail2 = misc();
+        d.iters = (p.flags & GAP_FLAG_ERROR_ESTIMATE) ? 16 : 0;
+        d.sync = tsync();
+        return d;
+    }
+    double *diag_out() const { return at<double>(L.off_diag) + 14 * L.M + 4 + 256; }
 
     void mark(int stage, bool end)
     {
@@ -478,7 +505,17 @@ gap_status gap_sync(gap_handle h, gap_solve_info *info)
                 return GAP_EDEVICE;
             info->refine_iters = it[0];
             info->cgls_iters = it[1];
-            info->grad_rel = st2[1];
+            info->step_rel = st2[1];
+        }
+        if (h->ws && h->L.total && h->state == ST_SOLVED) {
+            double dg[3] = {0.0, -1.0, 0.0};
+            if (hipMemcpy(dg, h->diag_out(), sizeof(dg), hipMemcpyDeviceToHost) != hipSuccess)
+                return GAP_EDEVICE;
+            info->grad_rel = dg[0];
+            info->est_err = dg[1];
+            info->kappa_est = dg[1] >= 0.0 ? dg[2] : 0.0;
+        } else {
+            info->est_err = -1.0;
         }
     }
     return (gap_status)st;
@@ -539,6 +576,9 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
         GAP_TRY(dev(launch_trsv_upper(A, L.lda, L.M, rhs, c_out, h->tsync(), s)));
         h->mark(5, true);
         GAP_TRY(dev(launch_sumsq(qtb + L.M, L.N, h->misc(), h->misc() + 1, h->counters() + 8, s)));
+        h->mark(8, false);
+        GAP_TRY(dev(launch_diag_fp64(h->diag(nullptr), A, qtb, c_out, h->diag_out(), s)));
+        h->mark(8, true);
     } else {
         // FP32 copy of [A | b], FP32 Householder QR (FP64 reflector norms), then
         // FP64 refinement against the untouched FP64 [A | b]
@@ -586,6 +626,10 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
         h->mark(6, true);
         GAP_TRY(dev(launch_check_finite(c_out, L.M, h->status(), s)));
         hipLaunchKernelGGL(copy_kernel, dim3(1), dim3(256), 0, s, rw.stats, h->misc(), (int64_t)1);
+        // the refinement's last pass left A^T r at the returned c in rw.s
+        h->mark(8, false);
+        GAP_TRY(dev(launch_diag_mixed(h->diag(rw.s), A32, A + L.M * L.lda, L.m, rw.stats, c_out, h->diag_out(), s)));
+        h->mark(8, true);
     }
     h->state = ST_SOLVED;
     if (info)

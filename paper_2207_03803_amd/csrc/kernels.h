@@ -96,6 +96,11 @@ hipError_t launch_trsv_upper(const double *R, int64_t ld, int64_t n, const doubl
 // Same with R stored in FP32 (FP64 arithmetic).
 hipError_t launch_trsv_upper_f32(const float *R, int64_t ld, int64_t n, const double *rhs, double *x,
                                  const TrsvSync &sync, const int32_t *skip, hipStream_t s);
+// FP64 R without the finiteness check, and R^T x = rhs with the FP64 R.
+hipError_t launch_trsv_upper_nc(const double *R, int64_t ld, int64_t n, const double *rhs, double *x,
+                                const TrsvSync &sync, hipStream_t s);
+hipError_t launch_trsv_upper_t(const double *R, int64_t ld, int64_t n, const double *rhs, double *x,
+                               const TrsvSync &sync, hipStream_t s);
 // Solve R^T x = rhs (forward substitution) for the FP32-stored upper R.
 hipError_t launch_trsv_upper_t_f32(const float *R, int64_t ld, int64_t n, const double *rhs, double *x,
                                    const TrsvSync &sync, const int32_t *skip, hipStream_t s);
@@ -128,6 +133,31 @@ hipError_t launch_convert_f64_f32(const double *a, float *b, int64_t n, hipStrea
 hipError_t launch_convert_block_f64_f32(const double *a, float *b, int64_t ld, int64_t r0, int64_t r1, int64_t c0,
                                         int64_t c1, hipStream_t s);
 hipError_t launch_refine(const RefineWork &w, int max_iters, hipStream_t s);
+
+// ---------------------------------------------------------------- diagnostics
+// Normal-equation residual eta of the returned weights and (iters > 0) the
+// error estimate u (kappa + kappa^2 ||r|| / (||A||_2 ||c||)) from power and
+// inverse iteration on R.  out[0] = eta, out[1] = estimate (-1 without one),
+// out[2] = kappa estimate.
+struct DiagWork {
+    int64_t n, ld;
+    double *part;        // [8 * n] column-chunk partials of R x
+    double *partR;       // [n] column sums of R^2
+    double *t, *g;       // [n]: (Q^T b)[0:n] - R c (FP64), A^T r
+    double *x, *y, *z;   // [n]: iteration vectors
+    double *sc;          // [4] scalars
+    double *sum_part;    // [256] partials of launch_sumsq
+    unsigned *counter;   // its arrival counter (zero)
+    const double *tail2; // FP64: minimum loss ||(Q^T b)[n:]||^2 (device scalar)
+    int iters;           // steps of each iteration (0: no estimate)
+    TrsvSync sync;
+};
+hipError_t launch_diag_fp64(const DiagWork &d, const double *R, const double *qtb, const double *c, double *out,
+                            hipStream_t s);
+// Mixed precision: d.g already holds A^T r at c (FP64 A); r2 = device ||r||^2;
+// bcol = the FP64 b (m entries); R32 = the FP32 factor.
+hipError_t launch_diag_mixed(const DiagWork &d, const float *R32, const double *bcol, int64_t m, const double *r2,
+                             const double *c, double *out, hipStream_t s);
 
 // ---------------------------------------------------------------- utilities
 // b = [y / sigma ; 0] into column `col` of the column-major A (lda rows).

@@ -336,10 +336,11 @@ hipError_t launch_refine(const RefineWork &w, int max_iters, hipStream_t s)
             return e;
         hipLaunchKernelGGL(refine_update_kernel, dim3(1), dim3(256), 0, s, w, nparts);
     }
-    // final residual at the returned c
+    // final residual r = b - A c at the returned c, ||r||^2, and s = A^T r
     hipLaunchKernelGGL(refine_reset_done_kernel, dim3(1), dim3(64), 0, s, w);
     residual(w, s);
     hipLaunchKernelGGL(refine_final_kernel, dim3(1), dim3(64), 0, s, w, nparts);
+    hipLaunchKernelGGL(atr_kernel, dim3((unsigned)w.n), dim3(256), 0, s, w);
     return hipGetLastError();
 }
 

@@ -253,6 +253,18 @@ hipError_t launch_trsv_upper(const double *R, int64_t ld, int64_t n, const doubl
     return launch_check_finite(c, n, sync.status, s);
 }
 
+hipError_t launch_trsv_upper_nc(const double *R, int64_t ld, int64_t n, const double *rhs, double *x,
+                                const TrsvSync &sync, hipStream_t s)
+{
+    return trsv_fused<double, false>(R, ld, n, rhs, x, sync, nullptr, s);
+}
+
+hipError_t launch_trsv_upper_t(const double *R, int64_t ld, int64_t n, const double *rhs, double *x,
+                               const TrsvSync &sync, hipStream_t s)
+{
+    return trsv_fused<double, true>(R, ld, n, rhs, x, sync, nullptr, s);
+}
+
 hipError_t launch_trsv_upper_f32(const float *R, int64_t ld, int64_t n, const double *rhs, double *x,
                                  const TrsvSync &sync, const int32_t *skip, hipStream_t s)
 {

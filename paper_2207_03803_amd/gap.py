@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libgap.so")
 GAP_OK, GAP_EINVAL, GAP_ENOMEM, GAP_ENOTPD, GAP_ENONFINITE, GAP_ENOCONV, GAP_EDEVICE, GAP_ESTATE, GAP_ERANK = range(9)
 GAP_FP64, GAP_MIXED_FP32, GAP_MIXED_BF16, GAP_MIXED_FP16 = 0, 1, 2, 3
 GAP_FLAG_TIMING = 1
+GAP_FLAG_ERROR_ESTIMATE = 2
 
 # Every entry point include/gap.h declares.
 EXPORTS = ["gap_create", "gap_workspace_bytes", "gap_bind_workspace", "gap_build_knm", "gap_solve",
@@ -23,7 +24,7 @@ EXPORTS = ["gap_create", "gap_workspace_bytes", "gap_bind_workspace", "gap_build
            "gap_set_tuning", "gap_set_model", "gap_set_stream", "gap_destroy", "gap_fit_static",
            "gap_static_scratch_bytes"]
 
-STAGES = ["knm", "kmm", "cholesky", "assemble_b", "qr", "trsv", "refine", "knm_lp"]
+STAGES = ["knm", "kmm", "cholesky", "assemble_b", "qr", "trsv", "refine", "knm_lp", "diag"]
 
 
 class GapParams(ctypes.Structure):
@@ -36,7 +37,8 @@ class GapParams(ctypes.Structure):
 class GapSolveInfo(ctypes.Structure):
     _fields_ = [("device_status", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
                 ("residual_norm2", ctypes.c_double), ("grad_rel", ctypes.c_double),
-                ("cgls_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("cgls_iters", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("step_rel", ctypes.c_double), ("est_err", ctypes.c_double), ("kappa_est", ctypes.c_double)]
 
 
 class GapTuning(ctypes.Structure):
@@ -198,8 +200,8 @@ class Handle:
         return out
 
     def stage_times(self):
-        arr = (ctypes.c_float * 8)()
-        _check(lib().gap_stage_times(self.h, arr, 8), "gap_stage_times")
+        arr = (ctypes.c_float * len(STAGES))()
+        _check(lib().gap_stage_times(self.h, arr, len(STAGES)), "gap_stage_times")
         return dict(zip(STAGES, [float(v) for v in arr]))
 
     def A_view(self):

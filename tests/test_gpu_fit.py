@@ -45,7 +45,8 @@ def _compare_fit(orc, inp, y, ref, zeta, jitter=1e-8, check_blocks=True):
     err = rel(c, ref.c)
     pred_err = rel(ref.Knm @ c, ref.Knm @ ref.c)
     loss_err = abs(info.residual_norm2 - ref.loss_tail) / ref.loss_tail
-    log(f"  c rel err {err:.2e}; prediction-space {pred_err:.2e}; loss {loss_err:.2e}")
+    log(f"  c rel err {err:.2e}; prediction-space {pred_err:.2e}; loss {loss_err:.2e}; eta {info.grad_rel:.1e}")
+    assert info.grad_rel <= 1e-13  # back-substitution residual in the factored basis
     assert err <= TOL_C
     assert pred_err <= 1e-12
     assert loss_err <= 1e-10
@@ -327,3 +328,36 @@ def test_one_hot_descriptors_give_exact_counts(orc_m):
     g.build()
     top, _ = g.A_top_and_lower()
     assert np.array_equal(top, Knm / sigma[:, None])
+
+
+@pytest.mark.parametrize("name,args", [
+    ("tiny", (200, (8, 64), 64, 256, 2, 0)),
+    ("mid-size d=400 zeta=4", (2000, (16, 64), 400, 520, 4, 5)),
+])
+def test_error_estimate_against_the_oracle_condition_number(orc_m, name, args):
+    """GAP_FLAG_ERROR_ESTIMATE: kappa_2(A) from 16 power / inverse iteration steps on
+    the GPU's R against the oracle's converged estimate (which is pinned to LAPACK's
+    SVD); the estimated error bounds the observed difference from the oracle's c."""
+    from paper_2207_03803_amd import gap
+
+    inp, y, ref = _case(orc_m, *args)
+    zeta = args[4]
+    n = args[3]
+    smax, smin, _ = orc_m.singular_extremes(np.triu(ref.A[:n]))
+    kappa = smax / smin
+    for prec in (gap.GAP_FP64, gap.GAP_MIXED_FP32):
+        g = GpuFit(inp.X, inp.offsets, inp.XM, inp.sigma, y, zeta, precision=prec, max_refine_iters=30,
+                   refine_tol=1e-14)
+        g.h.close()
+        g.h = gap.Handle(gap.params(inp.X.shape[1], zeta, 1.0, 1e-8, precision=prec, max_refine_iters=30,
+                                    refine_tol=1e-14, flags=gap.GAP_FLAG_ERROR_ESTIMATE))
+        g.h.alloc_workspace(g.N, g.X.shape[0], g.M)
+        c, info = g.run()
+        assert info.device_status == gap.GAP_OK
+        err = rel(c, ref.c)
+        log(f"  {name} precision {prec}: kappa est {info.kappa_est:.3e} (oracle {kappa:.3e}); est_err "
+            f"{info.est_err:.2e}, observed c rel err {err:.2e}; eta {info.grad_rel:.1e}")
+        assert 0.05 * kappa <= info.kappa_est <= 1.01 * kappa
+        assert info.est_err > 0 and err <= 10 * info.est_err
+        assert info.grad_rel <= 1e-13
+        g.h.close()

@@ -145,7 +145,7 @@ def test_mixed_precision_at_full_size(full_fit):
     nA = np.linalg.norm(Amat)
     eta = np.linalg.norm(Amat.T @ r) / (nA * (nA * np.linalg.norm(cm) + np.linalg.norm(b)))
     loss = float(r @ r)
-    log(f"  mixed: {info.refine_iters} refinement steps (last |dc|/|c| {info.grad_rel:.1e}), eta {eta:.2e}, "
+    log(f"  mixed: {info.refine_iters} refinement steps (last |dc|/|c| {info.step_rel:.1e}, eta {info.grad_rel:.1e}), eta {eta:.2e}, "
         f"loss rel diff vs FP64 path {abs(loss - f['info'].residual_norm2) / loss:.2e}")
     assert eta <= 1e-12
     assert abs(loss - f["info"].residual_norm2) <= 1e-8 * loss

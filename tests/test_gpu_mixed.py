@@ -60,8 +60,10 @@ def test_mixed_refines_to_fp64_accuracy(orc_m, name, args):
     c = g.c.cpu().numpy()
     err = rel(c, ref.c)
     log(f"  {name}: c rel err after 1,2,3,5 steps {['%.1e' % e for e in errs]}; "
-        f"converged in {info.refine_iters} steps to {err:.2e} (last |dc|/|c| {info.grad_rel:.1e})")
+        f"converged in {info.refine_iters} steps to {err:.2e} (last |dc|/|c| {info.step_rel:.1e}, eta {info.grad_rel:.1e})")
     assert info.device_status == gap.GAP_OK
+    assert info.grad_rel <= 1e-13  # normal equations of the FP64 A (zero loss gradient)
+    assert info.est_err == -1.0    # not requested
     assert info.cgls_iters == 0  # well within FP32's reach: corrected semi-normal equations alone
     assert err <= TOL_MIXED
     assert abs(info.residual_norm2 - ref.loss_tail) <= 1e-8 * ref.loss_tail
@@ -89,7 +91,7 @@ def test_ill_conditioned_fit_moves_to_cgls(orc_m, sigma_per_atom):
     c = g.c.cpu().numpy()
     err = rel(c, ref.c)
     log(f"  sigma_E/atom {sigma_per_atom:g}: kappa(A) {kappa:.2e}; {info.refine_iters} steps, "
-        f"{info.cgls_iters} of them CGLS; c rel err {err:.2e} (bound {bound:.1e}); last |dc|/|c| {info.grad_rel:.1e}")
+        f"{info.cgls_iters} of them CGLS; c rel err {err:.2e} (bound {bound:.1e}); last |dc|/|c| {info.step_rel:.1e}, eta {info.grad_rel:.1e}")
     assert s == gap.GAP_OK
     assert kappa > 5e6
     assert info.cgls_iters > 0
