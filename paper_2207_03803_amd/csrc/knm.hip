@@ -177,7 +177,7 @@ using KS = TileShape<KNM_BM, KNM_BN, 8, 4, 1>;
 static_assert(KS::NT == 256, "K_NM kernel assumes 256 threads");
 static_assert(KNM_BM == 256 && KNM_BN == 64, "loader mapping assumes a 256 x 64 tile");
 
-constexpr int EPC = 16;           // epilogue columns per pass (one 16-column block)
+constexpr int EPC = 32;           // epilogue columns per pass (two 16-column blocks)
 constexpr int EPLD = EPC + 1;     // padded LDS row of the epilogue buffer
 
 // Load one BK-slice (8 descriptor components) of the atom tile (256 rows) and

@@ -76,7 +76,9 @@ __global__ __launch_bounds__(256) void convert_lp_kernel(const double *__restric
 // ---------------------------------------------------------------------------
 // Tile: the plan's tile of up to 256 atoms (whole configurations) x 128 sparse
 // points, 512 threads = 8 waves of 64 x 64 (4 along the atoms, 2 along the
-// sparse points), each a 4 x 4 grid of 16 x 16 accumulator blocks.  K runs in
+// sparse points), each a 4 x 4 grid of 16 x 16 accumulator blocks.  A
+// workgroup takes LCT consecutive column tiles of one atom tile, so the tile's
+// set-up (segment table, atom rows) is shared and the atom rows stay in L2.  K runs in
 // slices of 32 (one MFMA), staged in LDS as [row][k] with the row padded to 40
 // elements; the next slice's global loads are in flight during the MFMAs.
 //
@@ -90,6 +92,7 @@ constexpr int LBN = 128;      // sparse points per tile
 constexpr int LBK = 32;       // k per slice
 constexpr int LDSK = LBK + 8; // padded LDS row (elements)
 constexpr int LNT = 512;
+constexpr int LCT = 8;        // column tiles per workgroup (the tile's setup is shared)
 constexpr int LEPC = 32;      // epilogue columns per pass
 constexpr int LEPLD = LEPC + 1;
 constexpr int LA_ELEMS = LBM * LDSK, LB_ELEMS = LBN * LDSK, LSTAGE = LA_ELEMS + LB_ELEMS;
@@ -110,7 +113,7 @@ struct KnmLpArgs {
     const double *sigma;
     float *out;                 // column-major: out[col * ldo + configuration]
     int64_t ldo;
-    int64_t n_ct, total_pad;
+    int64_t n_ct, n_cg, total_pad;  // column tiles, groups of LCT of them
 };
 
 template <bool BF>
@@ -133,7 +136,7 @@ DEV float ipowf(float g, int zeta)
 }
 
 template <bool BF>
-__global__ __launch_bounds__(LNT) void knm_lp_kernel(KnmLpArgs a)
+__global__ __launch_bounds__(LNT) __attribute__((amdgpu_waves_per_eu(4, 4))) void knm_lp_kernel(KnmLpArgs a)
 {
     __shared__ __align__(16) unsigned char lds_raw[LDS_BYTES];
     __shared__ int32_t sstart[KNM_MAX_SEG + 1];
@@ -144,15 +147,15 @@ __global__ __launch_bounds__(LNT) void knm_lp_kernel(KnmLpArgs a)
     uint16_t *lds = reinterpret_cast<uint16_t *>(lds_raw);
 
     const int64_t n_tiles = (int64_t)*a.n_tiles_dev;
-    const int64_t total = n_tiles * a.n_ct;
+    const int64_t total = n_tiles * a.n_cg;
     const int64_t total_pad = (total + 7) & ~int64_t(7);
     if ((int64_t)blockIdx.x >= total_pad)
         return;
     const int64_t lw = xcd_remap(blockIdx.x, total_pad);
     if (lw >= total)
         return;
-    const int64_t t = lw / a.n_ct, ct = lw % a.n_ct;
-    const int64_t col0 = ct * LBN;
+    const int64_t t = lw / a.n_cg, cg = lw % a.n_cg;
+    const int64_t ct_lo = cg * LCT, ct_hi = (ct_lo + LCT) < a.n_ct ? (ct_lo + LCT) : a.n_ct;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
 
@@ -192,9 +195,10 @@ __global__ __launch_bounds__(LNT) void knm_lp_kernel(KnmLpArgs a)
         a.out[colg * a.ldo + row] = (float)((double)sum / a.sigma[row]);
     };
     if (n_at == 0) {  // only empty configurations: their sums are zero
-        for (int item = tid; item < n_seg * LBN; item += LNT) {
+        const int ncol = (int)((ct_hi - ct_lo) * LBN);
+        for (int item = tid; item < n_seg * ncol; item += LNT) {
             const int s = item % n_seg, c = item / n_seg;
-            const int64_t colg = col0 + c;
+            const int64_t colg = ct_lo * LBN + c;
             if (colg < a.M)
                 emit(s, colg, 0.0f);
         }
@@ -217,11 +221,13 @@ __global__ __launch_bounds__(LNT) void knm_lp_kernel(KnmLpArgs a)
     // this thread's two A chunks (rows ra0, ra0 + 128; part pa) and one B chunk (row rb, part pb)
     const int ra0 = tid >> 2, pa = tid & 3;
     const int rb = tid >> 2, pb = tid & 3;
-    const int64_t colb = col0 + rb;
-    const uint16_t *bsrc = (colb < a.M) ? a.XM + colb * (int64_t)a.dp + pb * 8 : nullptr;
     const int nk = a.dp / LBK;
 
     f4 acc[4][4];
+    for (int64_t ct = ct_lo; ct < ct_hi; ++ct) {
+    const int64_t col0 = ct * LBN;
+    const int64_t colb = col0 + rb;
+    const uint16_t *bsrc = (colb < a.M) ? a.XM + colb * (int64_t)a.dp + pb * 8 : nullptr;
     for (int64_t cs = 0; cs < n_at; cs += LBM) {
         const bool first = (cs == 0), last = (cs + LBM >= n_at);
         const uint16_t *asrc[2];
@@ -336,6 +342,7 @@ __global__ __launch_bounds__(LNT) void knm_lp_kernel(KnmLpArgs a)
             __syncthreads();
         }
     }
+    }  // column tiles of the group
 }
 
 int knm_lp_dpad(int d) { return (d + LBK - 1) / LBK * LBK; }
@@ -372,7 +379,8 @@ hipError_t launch_knm_lp(const KnmLpLaunch &l, hipStream_t s)
     a.out = l.out;
     a.ldo = l.ldo;
     a.n_ct = (l.M + LBN - 1) / LBN;
-    const int64_t total = l.max_tiles * a.n_ct;
+    a.n_cg = (a.n_ct + LCT - 1) / LCT;
+    const int64_t total = l.max_tiles * a.n_cg;
     a.total_pad = (total + 7) & ~int64_t(7);
     if (a.total_pad == 0)
         return hipSuccess;

@@ -66,3 +66,65 @@ def test_sweep_is_batch_invariant_and_replays_identically(small_sweep):
         c = torch.empty_like(f.c)
         f.handle.solve(f.y, c)
         assert np.array_equal(c.cpu().numpy(), c_graph), f.spec
+
+
+def test_full_recipe_sweep_fits_match_oracle():
+    """Three fits of the benchmark's 64-fit sweep at full recipe size (the largest M,
+    the one with M > N_c, the smallest N_c at sigma_E = 1e-4 per atom) over host-drawn
+    pools, captured as graphs with the tuning table's launch shape and replayed on
+    their streams, against the oracle's reference fits
+    (tests/golden/sweep_fits_seed0.npz): c within 1e-8, or within the FP64
+    perturbation bound u (kappa + kappa^2 ||r|| / (||A|| ||c||)) of an
+    ill-conditioned fit; the same fits in plain FP64, eagerly, within 1e-10 or that
+    bound."""
+    import json
+    import os
+
+    import torch
+
+    from paper_2207_03803_amd import gap, sweep
+
+    z = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sweep_fits_seed0.npz"),
+                allow_pickle=False)
+    meta = json.loads(str(z["meta"]))
+    specs = sweep.make_sweep(seed=0)
+    pinned = [specs[m["idx"]] for m in meta["fits"]]
+    log("full-recipe sweep fits: " + ", ".join(f"{s.idx} (N={s.n_configs} M={s.M} d={s.d})" for s in pinned))
+    pools = sweep.make_pools(pinned, seed=0, min_configs=meta["pool_configs"], host=True)
+    pools = {d: sweep.Pool(d, p.offsets, torch.from_numpy(p.X).cuda()) for d, p in pools.items()}
+    targets = {s.idx: z[f"fit{s.idx}_y"] for s in pinned}
+    tune = sweep.load_table()[sweep.bucket(specs)]
+    u = 2.0 ** -53
+
+    def bound(idx, floor):
+        smax, smin = float(z[f"fit{idx}_smax"]), float(z[f"fit{idx}_smin"])
+        kappa = smax / smin
+        c = z[f"fit{idx}_c"]
+        rn = np.sqrt(float(z[f"fit{idx}_loss_tail"]))
+        return max(floor, 32 * u * (kappa + kappa ** 2 * rn / (smax * np.linalg.norm(c)))), kappa
+
+    sw = sweep.Sweep(pinned, pools, precision=gap.GAP_MIXED_FP32, streams=tune["streams"],
+                     split_wgs=tune["split_wgs"], lookahead=tune.get("lookahead", 0), max_refine_iters=60,
+                     refine_tol=1e-12, targets=targets)
+    sw.capture()
+    sw.replay(1)
+    st = sw.statuses()
+    for f, c, s in zip(sw.fits, sw.weights(), st):
+        idx = f.spec.idx
+        b, kappa = bound(idx, 1e-8)
+        err = rel(c, z[f"fit{idx}_c"])
+        log(f"  graph, mixed: fit {idx}: kappa(A) {kappa:.2e}; {gap.status_string(s)}; c rel err {err:.2e} "
+            f"(allowed {b:.1e})")
+        assert s == gap.GAP_OK
+        assert err <= b
+    sw.close()
+    seq = sweep.Sweep(pinned, pools, precision=gap.GAP_FP64, streams=1, targets=targets)
+    seq.run_eager()
+    for f, c, s in zip(seq.fits, seq.weights(), seq.statuses()):
+        idx = f.spec.idx
+        b, kappa = bound(idx, 1e-10)
+        err = rel(c, z[f"fit{idx}_c"])
+        log(f"  eager, FP64: fit {idx}: c rel err {err:.2e} (allowed {b:.1e})")
+        assert s == gap.GAP_OK
+        assert err <= b
+    seq.close()
