@@ -135,15 +135,16 @@ class Sweep:
         self.streams = [torch.cuda.Stream() for _ in range(streams)]
         self.root = torch.cuda.Stream()
         self.fits = []
-        order = sorted(specs, key=lambda s: -s.flops())
+        # positions in `specs` (and in self.fits), stream by stream
+        order = sorted(range(len(specs)), key=lambda i: -specs[i].flops())
         loads = [0.0] * streams
         self.assign = [[] for _ in range(streams)]
-        for s in order:  # longest processing time first, onto the least-loaded stream
+        for i in order:  # longest processing time first, onto the least-loaded stream
             k = int(np.argmin(loads))
-            loads[k] += s.flops()
-            self.assign[k].append(s.idx)
+            loads[k] += specs[i].flops()
+            self.assign[k].append(i)
         stream_of = {i: k for k, lst in enumerate(self.assign) for i in lst}
-        for s in specs:
+        for pos, s in enumerate(specs):
             pool = pools[s.d]
             dr = draw_fit(s, pool.offsets)
             n_atoms = dr["n_atoms"]
@@ -155,7 +156,7 @@ class Sweep:
             f.host = dict(c_true=dr["c_true"], noise=dr["noise"], sparse_idx=dr["sparse_idx"], sigma=dr["sigma"])
             p = gap.params(s.d, s.zeta, 1.0, 1e-8, precision=precision, max_refine_iters=max_refine_iters,
                            refine_tol=refine_tol)
-            f.handle = gap.Handle(p, stream=self.streams[stream_of[s.idx]])
+            f.handle = gap.Handle(p, stream=self.streams[stream_of[pos]])
             if split_wgs or lookahead:
                 f.handle.set_tuning(qr_split_wgs=split_wgs, qr_lookahead=lookahead)
             f.ws = f.handle.alloc_workspace(s.n_configs, n_atoms, s.M)
