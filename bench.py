@@ -456,11 +456,11 @@ def bench_sweep(gap, sweep, specs, pools, replays=2):
     import torch
 
     table = sweep.load_table()
-    tune = table.get(sweep.bucket(specs), dict(streams=16, split_wgs=1024, lookahead=1))
+    tune = table.get(sweep.bucket(specs), dict(streams=16, grouped=False))
     total_flops = sum(s.flops() for s in specs)
-    sw = sweep.Sweep(specs, pools, precision=gap.GAP_MIXED_FP32, streams=tune["streams"],
-                     split_wgs=tune["split_wgs"], lookahead=tune.get("lookahead", 0), max_refine_iters=30,
-                     refine_tol=1e-12)
+    prec = gap.GAP_MIXED_FP32
+    sw = sweep.Sweep(specs, pools, precision=prec, streams=tune["streams"], grouped=tune.get("grouped", False),
+                     shapes=lambda s: sweep.shape_for(s, prec, table), max_refine_iters=30, refine_tol=1e-12)
     sw.capture(log=log)
     log("[bench] sweep: every fit's graph captured; first replay")
     sw.replay(1)
@@ -489,8 +489,8 @@ def bench_sweep(gap, sweep, specs, pools, replays=2):
     log(f"[bench] sweep: graph {t_graph * 1e3:.0f} ms, sequential FP64 {t_seq * 1e3:.0f} ms")
     return {"n_fits": len(specs), "fits_per_s": len(specs) / t_graph, "s_per_sweep": t_graph,
             "fp64_sequential_fits_per_s": len(specs) / t_seq, "speedup_vs_fp64_sequential": t_seq / t_graph,
-            "launch_shape": {"streams": tune["streams"], "qr_split_wgs": tune["split_wgs"],
-                             "qr_lookahead": tune.get("lookahead", 0),
+            "launch_shape": {"streams": tune["streams"], "grouped_knm": bool(tune.get("grouped", False)),
+                             "per_fit_shapes": sum(1 for s in specs if sweep.shape_for(s, prec, table)),
                              "from_tuning_table": sweep.bucket(specs) in table},
             "tflops_effective": total_flops / t_graph / 1e12,
             "all_ok": all(s == gap.GAP_OK for s in st) and all(s == gap.GAP_OK for s in st64),

@@ -34,8 +34,9 @@
  *    may run concurrently on different streams.
  *  - Call order: gap_create -> gap_bind_workspace -> gap_build_knm ->
  *    gap_solve -> gap_predict*; gap_build_knm may be called again to start a
- *    new fit in the same handle.  A predict-only handle: gap_create ->
- *    gap_set_model -> gap_predict*.
+ *    new fit in the same handle.  Batched: gap_build_knm_batch over several
+ *    handles, then gap_build_kmm on each, then gap_solve.  A predict-only
+ *    handle: gap_create -> gap_set_model -> gap_predict*.
  *  - Descriptors are used as given: the covariance assumes unit-L2 rows but
  *    does not renormalise them.
  */
@@ -172,6 +173,35 @@ gap_status gap_build_knm(gap_handle h, const double *x_atoms, int64_t n_atoms,
                          const int64_t *config_offsets, int64_t n_configs,
                          const double *x_sparse, int64_t M, const double *sigma);
 
+/* One fit's inputs for gap_build_knm_batch (device pointers, as in gap_build_knm). */
+typedef struct gap_batch_fit {
+    const double *x_atoms;
+    int64_t n_atoms;
+    const int64_t *config_offsets;
+    int64_t n_configs;
+    const double *x_sparse;
+    int64_t M;
+    const double *sigma;
+} gap_batch_fit;
+
+/*
+ * The K_NM (Sec. Theory, definition of K_MN) of n fits -- a batch of independent
+ * fits such as a hyperparameter sweep -- enqueued on `stream` (a hipStream_t or
+ * NULL) as grouped launches: each launch covers the tiles of up to 16 fits in one
+ * grid.  Each fit's tile plan and K_NM are what gap_build_knm computes for it
+ * (bit for bit).  handles[i] (distinct, each with a bound workspace) takes
+ * fits[i]; afterwards each handle needs gap_build_kmm, which runs the rest of its
+ * build (K_MM, jitter, Cholesky; the low-precision K_NM in GAP_MIXED_BF16/FP16)
+ * on the handle's own stream: the caller orders each handle's stream after
+ * `stream` (an event).  GAP_EINVAL / GAP_ENOMEM / GAP_ESTATE as gap_build_knm,
+ * before anything is enqueued.  Stage 0 of gap_stage_times is not timed.
+ */
+gap_status gap_build_knm_batch(gap_handle *handles, int32_t n, const gap_batch_fit *fits, void *stream);
+
+/* The rest of a batched build on the handle's stream (see gap_build_knm_batch).
+ * GAP_ESTATE unless the handle's last call was a batched K_NM. */
+gap_status gap_build_kmm(gap_handle h);
+
 /*
  * Solve for the weights (Sec. Theory: b = [Sigma^-1/2 y ; 0], Householder QR of
  * [A | b] giving R and Q^T b, back-substitution c = R^-1 (Q^T b)[0:M]).
@@ -247,13 +277,17 @@ gap_status gap_stage_times(gap_handle h, float *ms, int n);
  *                 the legacy stream meanwhile; a captured graph does not keep
  *                 the mask.  Takes effect at the next gap_build_knm (which
  *                 replaces the stream after its last work); results are
- *                 unchanged. */
+ *                 unchanged.
+ *   knm_bn        K_NM column tile: 64 sparse points (0 or 64, default) or 32.
+ *                 Each entry's arithmetic does not depend on it: results are
+ *                 bitwise unchanged. */
 typedef struct gap_tuning {
     int32_t qr_split_wgs;
     int32_t qr_panel;
     int32_t qr_lookahead;
     int32_t qr_free_cus;
-    int32_t reserved[4];
+    int32_t knm_bn;
+    int32_t reserved[3];
 } gap_tuning;
 
 /* Set the handle's launch-shape knobs (host-only; affects later calls).  GAP_EINVAL on

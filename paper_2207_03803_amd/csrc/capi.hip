@@ -15,7 +15,7 @@ namespace {
 
 constexpr int N_STAGES = 9;
 
-enum State { ST_CREATED = 0, ST_BOUND = 1, ST_BUILT = 2, ST_SOLVED = 3 };
+enum State { ST_CREATED = 0, ST_BOUND = 1, ST_KNM = 2, ST_BUILT = 3, ST_SOLVED = 4 };
 
 struct Layout {
     int64_t N = 0, M = 0, n_atoms = 0, m = 0, lda = 0, ncols = 0, max_tiles = 0;
@@ -123,6 +123,8 @@ struct gap_handle_s {
     Layout L;
     const double *x_sparse = nullptr;
     const double *sigma = nullptr;
+    const double *x_atoms = nullptr;      // inputs of the current build
+    const int64_t *offsets = nullptr;
     int64_t model_M = 0;      // set by gap_set_model
     bool model_only = false;  // predict-only handle (no workspace)
     hipEvent_t ev[2 * N_STAGES] = {};
@@ -360,8 +362,10 @@ static bool create_lookahead(gap_handle h)
     return true;
 }
 
-gap_status gap_build_knm(gap_handle h, const double *x_atoms, int64_t n_atoms, const int64_t *config_offsets,
-                         int64_t n_configs, const double *x_sparse, int64_t M, const double *sigma)
+// Checks, layout and input pointers of a build; creates the look-ahead stream
+// when the fit uses one.
+static gap_status build_prepare(gap_handle h, const double *x_atoms, int64_t n_atoms, const int64_t *config_offsets,
+                                int64_t n_configs, const double *x_sparse, int64_t M, const double *sigma)
 {
     if (!h)
         return GAP_EINVAL;
@@ -374,6 +378,8 @@ gap_status gap_build_knm(gap_handle h, const double *x_atoms, int64_t n_atoms, c
     if (L.total > h->ws_bytes)
         return GAP_ENOMEM;
     h->L = L;
+    h->x_atoms = x_atoms;
+    h->offsets = config_offsets;
     h->x_sparse = x_sparse;
     h->sigma = sigma;
     h->model_only = false;
@@ -385,95 +391,163 @@ gap_status gap_build_knm(gap_handle h, const double *x_atoms, int64_t n_atoms, c
     }
     if (use_lookahead(h) && !h->la.side && !create_lookahead(h))
         return GAP_EDEVICE;
-    hipStream_t s = h->stream;
-    const gap_params &p = h->p;
-    const double sw2 = p.sigma_w * p.sigma_w;
+    return GAP_OK;
+}
 
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, h->counters(), 16);
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned *>(h->status()), 4);
-    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(256), 0, s, h->at<int32_t>(L.off_tflags), L.n_tflags);
+static KnmPlan plan_of(gap_handle h)
+{
+    const Layout &L = h->L;
     int32_t *tiles = h->at<int32_t>(L.off_tiles);
     int32_t *plan = h->at<int32_t>(L.off_plan);
     KnmPlan kp;
     kp.tile_start = tiles;
     kp.n_tiles = tiles + L.max_tiles + 1;
     kp.cfg_list = plan;
-    kp.lstart = plan + n_configs;
-    kp.lcount = kp.lstart + knm_plan_chunks(n_configs) * 2049;
-    GAP_TRY(dev(launch_plan_tiles(config_offsets, n_configs, n_atoms, kp, L.max_tiles, h->status(), s)));
+    kp.lstart = plan + L.N;
+    kp.lcount = kp.lstart + knm_plan_chunks(L.N) * 2049;
+    return kp;
+}
 
-    KnmArgs a{};
-    a.X = x_atoms;
-    a.offsets = config_offsets;
-    a.tile_start = kp.tile_start;
-    a.cfg_list = kp.cfg_list;
-    a.n_tiles_dev = kp.n_tiles;
-    a.XM = x_sparse;
-    a.M = M;
-    a.d = p.d;
-    a.zeta = p.zeta;
-    a.sw2 = sw2;
-    a.sigma = sigma;
-    a.out = h->A();
-    a.ldo = L.lda;
-    a.row_off = 0;
-    a.status = h->status();
-    h->mark(0, false);
-    GAP_TRY(dev(launch_knm(a, L.max_tiles, s)));
-    h->mark(0, true);
+// On stream s: clear the counters, status and flags, and plan the K_NM tiles;
+// *a = the fit's K_NM launch arguments.
+static gap_status build_setup(gap_handle h, hipStream_t s, KnmArgs *a)
+{
+    const Layout &L = h->L;
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, h->counters(), 16);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned *>(h->status()), 4);
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(256), 0, s, h->at<int32_t>(L.off_tflags), L.n_tflags);
+    const KnmPlan kp = plan_of(h);
+    GAP_TRY(dev(launch_plan_tiles(h->offsets, L.N, L.n_atoms, kp, L.max_tiles, h->status(), s)));
+    *a = KnmArgs{};
+    a->X = h->x_atoms;
+    a->offsets = h->offsets;
+    a->tile_start = kp.tile_start;
+    a->cfg_list = kp.cfg_list;
+    a->n_tiles_dev = kp.n_tiles;
+    a->XM = h->x_sparse;
+    a->M = L.M;
+    a->d = h->p.d;
+    a->zeta = h->p.zeta;
+    a->sw2 = h->p.sigma_w * h->p.sigma_w;
+    a->sigma = h->sigma;
+    a->out = h->A();
+    a->ldo = L.lda;
+    a->row_off = 0;
+    a->status = h->status();
+    a->bn = h->tuning.knm_bn;
+    return GAP_OK;
+}
 
+// On the handle's stream, after the K_NM: the low-precision K_NM (mixed BF16 /
+// FP16), K_MM + jitter (upper triangle) into rows N..N+M-1, then U = L^T in place.
+static gap_status build_rest(gap_handle h)
+{
+    const Layout &L = h->L;
+    hipStream_t s = h->stream;
+    const gap_params &p = h->p;
+    const double sw2 = p.sigma_w * p.sigma_w;
     if (L.lp) {
         // the factor's copy of Sigma^-1/2 K_NM from BF16 / FP16 dot products (FP32 power and sums)
         const bool bf = p.precision == GAP_MIXED_BF16;
         uint16_t *Xlp = h->at<uint16_t>(L.off_Xlp), *XMlp = h->at<uint16_t>(L.off_XMlp);
+        const KnmPlan kp = plan_of(h);
         h->mark(7, false);
-        GAP_TRY(dev(launch_convert_lp(x_atoms, n_atoms, p.d, Xlp, bf, s)));
-        GAP_TRY(dev(launch_convert_lp(x_sparse, M, p.d, XMlp, bf, s)));
+        GAP_TRY(dev(launch_convert_lp(h->x_atoms, L.n_atoms, p.d, Xlp, bf, s)));
+        GAP_TRY(dev(launch_convert_lp(h->x_sparse, L.M, p.d, XMlp, bf, s)));
         KnmLpLaunch l{};
         l.X = Xlp;
         l.XM = XMlp;
         l.d = p.d;
-        l.offsets = config_offsets;
+        l.offsets = h->offsets;
         l.tile_start = kp.tile_start;
         l.cfg_list = kp.cfg_list;
         l.n_tiles_dev = kp.n_tiles;
         l.max_tiles = L.max_tiles;
-        l.M = M;
+        l.M = L.M;
         l.zeta = p.zeta;
         l.sw2 = sw2;
-        l.sigma = sigma;
+        l.sigma = h->sigma;
         l.out = h->at<float>(L.off_A32);
         l.ldo = L.lda;
         l.bf16 = bf;
         GAP_TRY(dev(launch_knm_lp(l, s)));
         h->mark(7, true);
     }
-
-    // K_MM + jitter (upper triangle) into rows N..N+M-1, then U = L^T in place.
     KnmArgs k{};
-    k.X = x_sparse;
+    k.X = h->x_sparse;
     k.offsets = nullptr;
-    k.n_rows_unit = M;
-    k.XM = x_sparse;
-    k.M = M;
+    k.n_rows_unit = L.M;
+    k.XM = h->x_sparse;
+    k.M = L.M;
     k.d = p.d;
     k.zeta = p.zeta;
     k.sw2 = sw2;
     k.sigma = nullptr;
     k.out = h->A();
     k.ldo = L.lda;
-    k.row_off = n_configs;
+    k.row_off = L.N;
     k.jitter = p.jitter;
     k.upper_only = 1;
     k.status = h->status();
     h->mark(1, false);
-    GAP_TRY(dev(launch_knm(k, (M + KNM_BM - 1) / KNM_BM, s)));
+    GAP_TRY(dev(launch_knm(k, (L.M + KNM_BM - 1) / KNM_BM, s)));
     h->mark(1, true);
     h->mark(2, false);
-    GAP_TRY(dev(launch_potrf_upper(h->A() + n_configs, L.lda, M, h->status(), s)));
+    GAP_TRY(dev(launch_potrf_upper(h->A() + L.N, L.lda, L.M, h->status(), s)));
     h->mark(2, true);
     h->state = ST_BUILT;
     return GAP_OK;
+}
+
+gap_status gap_build_knm(gap_handle h, const double *x_atoms, int64_t n_atoms, const int64_t *config_offsets,
+                         int64_t n_configs, const double *x_sparse, int64_t M, const double *sigma)
+{
+    GAP_TRY(build_prepare(h, x_atoms, n_atoms, config_offsets, n_configs, x_sparse, M, sigma));
+    KnmArgs a;
+    GAP_TRY(build_setup(h, h->stream, &a));
+    h->mark(0, false);
+    GAP_TRY(dev(launch_knm(a, h->L.max_tiles, h->stream)));
+    h->mark(0, true);
+    return build_rest(h);
+}
+
+gap_status gap_build_knm_batch(gap_handle *handles, int32_t n, const gap_batch_fit *fits, void *stream)
+{
+    if (!handles || !fits || n < 1 || n > 4096)
+        return GAP_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    for (int32_t i = 0; i < n; ++i) {
+        const gap_batch_fit &f = fits[i];
+        GAP_TRY(build_prepare(handles[i], f.x_atoms, f.n_atoms, f.config_offsets, f.n_configs, f.x_sparse, f.M,
+                              f.sigma));
+        for (int32_t j = 0; j < i; ++j)
+            if (handles[j] == handles[i])
+                return GAP_EINVAL;
+    }
+    KnmArgs args[KNM_GROUP];
+    int64_t max_tiles[KNM_GROUP];
+    for (int32_t i0 = 0; i0 < n; i0 += KNM_GROUP) {
+        const int g = (n - i0) < KNM_GROUP ? (n - i0) : KNM_GROUP;
+        for (int i = 0; i < g; ++i) {
+            GAP_TRY(build_setup(handles[i0 + i], s, &args[i]));
+            max_tiles[i] = handles[i0 + i]->L.max_tiles;
+        }
+        GAP_TRY(dev(launch_knm_group(args, max_tiles, g, s)));
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        handles[i]->timed[0] = false;
+        handles[i]->state = ST_KNM;
+    }
+    return GAP_OK;
+}
+
+gap_status gap_build_kmm(gap_handle h)
+{
+    if (!h)
+        return GAP_EINVAL;
+    if (h->state != ST_KNM)
+        return GAP_ESTATE;
+    return build_rest(h);
 }
 
 gap_status gap_sync(gap_handle h, gap_solve_info *info)
@@ -721,6 +795,8 @@ gap_status gap_set_tuning(gap_handle h, const gap_tuning *t)
     if (t->qr_lookahead < 0 || t->qr_lookahead > 2)
         return GAP_EINVAL;
     if (t->qr_free_cus < 0 || t->qr_free_cus > 128)
+        return GAP_EINVAL;
+    if (t->knm_bn != 0 && t->knm_bn != 32 && t->knm_bn != 64)
         return GAP_EINVAL;
     h->tuning = *t;
     return GAP_OK;

@@ -31,6 +31,7 @@ struct KnmArgs {
     int upper_only;            // unit segments: write 0 where segment > column
     int64_t n_ct, total_pad;   // filled by launch_knm
     int32_t *status;
+    int bn;                    // column tile: 64 sparse points (0 or 64) or 32
 };
 
 int64_t knm_max_tiles(int64_t N, int64_t n_atoms);
@@ -43,6 +44,16 @@ struct KnmPlan {
 hipError_t launch_plan_tiles(const int64_t *offsets, int64_t N, int64_t n_atoms, const KnmPlan &p, int64_t max_tiles,
                              int32_t *status, hipStream_t s);
 hipError_t launch_knm(KnmArgs a, int64_t max_tiles, hipStream_t s);
+// The K_NM of n fits as grouped launches (up to KNM_GROUP fits per launch, the
+// table passed as the kernel argument); each fit's tiles compute exactly what
+// launch_knm computes for it.
+constexpr int KNM_GROUP = 16;
+struct KnmGroup {
+    int n;
+    int64_t base[KNM_GROUP + 1];  // first workgroup of each fit (multiples of 8)
+    KnmArgs f[KNM_GROUP];
+};
+hipError_t launch_knm_group(const KnmArgs *fits, const int64_t *max_tiles, int n, hipStream_t s);
 
 // ------------------------------------------------- low-precision K_NM (mixed form)
 // Descriptors rounded to BF16 or FP16 (round to nearest, ties to even) into

@@ -171,26 +171,32 @@ int64_t knm_max_tiles(int64_t N, int64_t n_atoms)
     return bound < N ? bound : N;
 }
 
-// 256 threads, 4 waves of 64 x 64, BK = 8: about 45 KB of LDS, so two or three
-// workgroups share a CU and cover each other's barriers.
-using KS = TileShape<KNM_BM, KNM_BN, 8, 4, 1>;
+// 256 threads, 4 waves of 64 x BN (BN = 64 by default, 32 as a tuning choice),
+// BK = 8: two workgroups share a CU and cover each other's barriers.
+template <int BN>
+using KSB = TileShape<KNM_BM, BN, 8, 4, 1>;
+using KS = KSB<KNM_BN>;
 static_assert(KS::NT == 256, "K_NM kernel assumes 256 threads");
-static_assert(KNM_BM == 256 && KNM_BN == 64, "loader mapping assumes a 256 x 64 tile");
+static_assert(KNM_BM == 256 && KNM_BN == 64, "loader mapping assumes 256-atom tiles");
 
 constexpr int EPC = 32;           // epilogue columns per pass (two 16-column blocks)
 constexpr int EPLD = EPC + 1;     // padded LDS row of the epilogue buffer
 
 // Load one BK-slice (8 descriptor components) of the atom tile (256 rows) and
-// the sparse tile (64 rows) into registers.  Rows past the valid range and k
-// past d read as zero.
+// the sparse tile (BN rows) into registers.  Rows past the valid range and k
+// past d read as zero.  Each thread loads 8 k of its atom row and BN / 32 k of
+// sparse row tid / (256 / BN).
+template <int BN>
 struct KnmLoads {
     double a[8];
-    double b[2];
+    double b[BN / 32];
 };
 
-DEV void knm_load(KnmLoads &r, const double *__restrict__ xr, const double *__restrict__ XM, int64_t col0, int64_t M,
-                  int d, int k0)
+template <int BN>
+DEV void knm_load(KnmLoads<BN> &r, const double *__restrict__ xr, const double *__restrict__ XM, int64_t col0,
+                  int64_t M, int d, int k0)
 {
+    constexpr int TPR = 256 / BN, VB = BN / 32;  // threads per sparse row, k per thread
     const int tid = threadIdx.x;
     {
         // xr: this thread's atom row (nullptr past the tile's atoms)
@@ -206,70 +212,85 @@ DEV void knm_load(KnmLoads &r, const double *__restrict__ xr, const double *__re
         }
     }
     {
-        const int64_t row = col0 + (tid >> 2);
-        const int kb = k0 + (tid & 3) * 2;
+        const int64_t row = col0 + tid / TPR;
+        const int kb = k0 + (tid % TPR) * VB;
         const bool rv = row < M;
         const double *p = XM + row * (int64_t)d + kb;
-        if (rv && kb + 2 <= d) {
-            r.b[0] = p[0];
-            r.b[1] = p[1];
+        if (rv && kb + VB <= d) {
+#pragma unroll
+            for (int e = 0; e < VB; ++e)
+                r.b[e] = p[e];
         } else {
 #pragma unroll
-            for (int e = 0; e < 2; ++e)
+            for (int e = 0; e < VB; ++e)
                 r.b[e] = (rv && kb + e < d) ? p[e] : 0.0;
         }
     }
 }
 
-DEV void knm_store(const KnmLoads &r, double *As, double *Bs)
+template <int BN>
+DEV void knm_store(const KnmLoads<BN> &r, double *As, double *Bs)
 {
+    using S = KSB<BN>;
+    constexpr int TPR = 256 / BN, VB = BN / 32;
     const int tid = threadIdx.x;
     {
         const int row = tid;
 #pragma unroll
         for (int e = 0; e < 8; ++e)
-            As[e * KS::LDA + row] = r.a[e];
+            As[e * S::LDA + row] = r.a[e];
     }
     {
-        const int row = tid >> 2, kb = (tid & 3) * 2;
+        const int row = tid / TPR, kb = (tid % TPR) * VB;
 #pragma unroll
-        for (int e = 0; e < 2; ++e)
-            Bs[(kb + e) * KS::LDB + row] = r.b[e];
+        for (int e = 0; e < VB; ++e)
+            Bs[(kb + e) * S::LDB + row] = r.b[e];
     }
 }
 
-// G = (the tile's 256 atom rows, thread t's row at xr) . XM[col0 : col0+64)^T,
+// G = (the tile's 256 atom rows, thread t's row at xr) . XM[col0 : col0+BN)^T,
 // accumulated in registers.
-DEV void knm_gemm(d4 (&acc)[KS::FM][KS::FN], double *lds, const double *__restrict__ xr,
+template <int BN>
+DEV void knm_gemm(d4 (&acc)[KSB<BN>::FM][KSB<BN>::FN], double *lds, const double *__restrict__ xr,
                   const double *__restrict__ XM, int64_t col0, int64_t M, int d)
 {
+    using S = KSB<BN>;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave / KS::WN, wn = wave % KS::WN;
-    zero_acc<KS>(acc);
-    const int nk = (d + KS::BK - 1) / KS::BK;
-    KnmLoads r;
-    knm_load(r, xr, XM, col0, M, d, 0);
-    knm_store(r, lds, lds + KS::A_ELEMS);
+    const int wm = wave / S::WN, wn = wave % S::WN;
+    zero_acc<S>(acc);
+    const int nk = (d + S::BK - 1) / S::BK;
+    KnmLoads<BN> r;
+    knm_load<BN>(r, xr, XM, col0, M, d, 0);
+    knm_store<BN>(r, lds, lds + S::A_ELEMS);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
-        double *cur = lds + (kt & 1) * KS::STAGE;
-        double *nxt = lds + ((kt + 1) & 1) * KS::STAGE;
+        double *cur = lds + (kt & 1) * S::STAGE;
+        double *nxt = lds + ((kt + 1) & 1) * S::STAGE;
         const bool more = kt + 1 < nk;
         if (more)
-            knm_load(r, xr, XM, col0, M, d, (kt + 1) * KS::BK);
-        mma_stage<KS>(cur, cur + KS::A_ELEMS, acc, wm, wn, lane);
+            knm_load<BN>(r, xr, XM, col0, M, d, (kt + 1) * S::BK);
+        mma_stage<S>(cur, cur + S::A_ELEMS, acc, wm, wn, lane);
         if (more)
-            knm_store(r, nxt, nxt + KS::A_ELEMS);
+            knm_store<BN>(r, nxt, nxt + S::A_ELEMS);
         __syncthreads();
     }
 }
 
-constexpr int KNM_LDS_DOUBLES =
-    (2 * KS::STAGE > KNM_BM * EPLD) ? 2 * KS::STAGE : KNM_BM * EPLD;
-
-__global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
+template <int BN>
+constexpr int knm_lds_doubles()
 {
-    __shared__ double lds[KNM_LDS_DOUBLES];
+    return (2 * KSB<BN>::STAGE > KNM_BM * EPLD) ? 2 * KSB<BN>::STAGE : KNM_BM * EPLD;
+}
+
+// One workgroup's tile; bid = the workgroup's index within this K_NM's own grid
+// (a multiple-of-8 offset into a grouped grid keeps bid's XCD the hardware's).
+template <int BN>
+DEV void knm_body(const KnmArgs &a, int64_t bid)
+{
+    using KS = KSB<BN>;
+    constexpr int KNM_BN = BN;
+    static_assert(BN == 32 || BN == 64, "column tile of 32 or 64 sparse points");
+    __shared__ double lds[knm_lds_doubles<BN>()];
     __shared__ int32_t sstart[KNM_MAX_SEG + 1];  // atom offset of each segment within the tile
     __shared__ int64_t sbase[KNM_MAX_SEG];       // first atom (row of X) of each segment
     __shared__ int32_t srow[KNM_MAX_SEG];        // output row of each segment
@@ -281,9 +302,9 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
     const int64_t n_tiles = unit ? (a.n_rows_unit + KNM_BM - 1) / KNM_BM : (int64_t)*a.n_tiles_dev;
     const int64_t total = n_tiles * a.n_ct;
     const int64_t total_pad = (total + 7) & ~int64_t(7);
-    if ((int64_t)blockIdx.x >= total_pad)
+    if (bid >= total_pad)
         return;
-    const int64_t lw = xcd_remap(blockIdx.x, total_pad);
+    const int64_t lw = xcd_remap(bid, total_pad);
     if (lw >= total)
         return;
     const int64_t t = lw / a.n_ct, ct = lw % a.n_ct;
@@ -393,7 +414,7 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
         const double *xr = multi ? ((cs + tid < n_at) ? a.X + (sbase[0] + cs + tid) * (int64_t)a.d : nullptr)
                                  : xr_packed;
         __syncthreads();
-        knm_gemm(acc, lds, xr, a.XM, col0, a.M, a.d);
+        knm_gemm<BN>(acc, lds, xr, a.XM, col0, a.M, a.d);
 
         // k = sigma_w^2 g^zeta, in registers.
 #pragma unroll
@@ -405,7 +426,7 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
                     acc[i][j][e] = a.sw2 * ipow(acc[i][j][e], a.zeta);
 
         double *E = lds;  // [256][EPLD], reused after the GEMM
-        for (int p = 0; p < KNM_BN / EPC; ++p) {
+        for (int p = 0; p < (KNM_BN + EPC - 1) / EPC; ++p) {
             // waves owning columns [p*16, p*16+16) park their values in LDS
             if (wn == (p * EPC) / KS::TN) {
 #pragma unroll
@@ -471,6 +492,20 @@ __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a)
     }
 }
 
+template <int BN>
+__global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a) { knm_body<BN>(a, blockIdx.x); }
+
+// The K_NM of several fits in one grid: fit i owns workgroups [base[i], base[i+1]).
+template <int BN>
+__global__ __launch_bounds__(256, 2) void knm_group_kernel(KnmGroup g)
+{
+    const int64_t b = blockIdx.x;
+    int i = 0;
+    while (i + 1 < g.n && b >= g.base[i + 1])
+        ++i;
+    knm_body<BN>(g.f[i], b - g.base[i]);
+}
+
 // ---------------------------------------------------------------------------
 // Prediction (Eqs. 1-2): y_A = sum_{i in A} sum_j c_j sigma_w^2 (x_i . x_j)^zeta.
 // Workgroup w owns configurations [w*C, (w+1)*C); it walks their atoms in
@@ -533,7 +568,8 @@ __global__ __launch_bounds__(256, 2) void predict_kernel(const double *__restric
         for (int64_t ct = 0; ct < n_ct; ++ct) {
             const int64_t col0 = ct * KNM_BN;
             __syncthreads();
-            knm_gemm(acc, lds, (cs + tid < atom_hi) ? X + (cs + tid) * (int64_t)d : nullptr, XM, col0, M, d);
+            knm_gemm<KNM_BN>(acc, lds, (cs + tid < atom_hi) ? X + (cs + tid) * (int64_t)d : nullptr, XM, col0, M,
+                             d);
             double cw[KS::FN][4];
 #pragma unroll
             for (int j = 0; j < KS::FN; ++j)
@@ -605,14 +641,50 @@ hipError_t launch_plan_tiles(const int64_t *offsets, int64_t N, int64_t n_atoms,
     return hipGetLastError();
 }
 
+static int bn_of(const KnmArgs &a) { return a.bn == 32 ? 32 : 64; }
+
+hipError_t launch_knm_group(const KnmArgs *fits, const int64_t *max_tiles, int n, hipStream_t s)
+{
+    for (int bn : {64, 32}) {  // one grid per column-tile width
+        KnmGroup g{};
+        auto flush = [&]() {
+            if (g.n > 0 && g.base[g.n] > 0) {
+                if (bn == 64)
+                    hipLaunchKernelGGL(knm_group_kernel<64>, dim3((unsigned)g.base[g.n]), dim3(256), 0, s, g);
+                else
+                    hipLaunchKernelGGL(knm_group_kernel<32>, dim3((unsigned)g.base[g.n]), dim3(256), 0, s, g);
+            }
+            g = KnmGroup{};
+        };
+        for (int i = 0; i < n; ++i) {
+            if (bn_of(fits[i]) != bn)
+                continue;
+            KnmArgs a = fits[i];
+            a.n_ct = (a.M + bn - 1) / bn;
+            const int64_t total = max_tiles[i] * a.n_ct;
+            a.total_pad = (total + 7) & ~int64_t(7);
+            g.f[g.n] = a;
+            g.base[g.n + 1] = g.base[g.n] + a.total_pad;
+            if (++g.n == KNM_GROUP)
+                flush();
+        }
+        flush();
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_knm(KnmArgs a, int64_t max_tiles, hipStream_t s)
 {
-    a.n_ct = (a.M + KNM_BN - 1) / KNM_BN;
+    const int bn = bn_of(a);
+    a.n_ct = (a.M + bn - 1) / bn;
     const int64_t total = max_tiles * a.n_ct;
     a.total_pad = (total + 7) & ~int64_t(7);
     if (a.total_pad == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(knm_kernel, dim3((unsigned)a.total_pad), dim3(KS::NT), 0, s, a);
+    if (bn == 64)
+        hipLaunchKernelGGL(knm_kernel<64>, dim3((unsigned)a.total_pad), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(knm_kernel<32>, dim3((unsigned)a.total_pad), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

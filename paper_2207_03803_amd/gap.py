@@ -22,7 +22,7 @@ GAP_FLAG_ERROR_ESTIMATE = 2
 EXPORTS = ["gap_create", "gap_workspace_bytes", "gap_bind_workspace", "gap_build_knm", "gap_solve",
            "gap_predict", "gap_sync", "gap_layout", "gap_stage_times", "gap_status_string",
            "gap_set_tuning", "gap_set_model", "gap_set_stream", "gap_destroy", "gap_fit_static",
-           "gap_static_scratch_bytes"]
+           "gap_static_scratch_bytes", "gap_build_knm_batch", "gap_build_kmm"]
 
 STAGES = ["knm", "kmm", "cholesky", "assemble_b", "qr", "trsv", "refine", "knm_lp", "diag"]
 
@@ -41,9 +41,15 @@ class GapSolveInfo(ctypes.Structure):
                 ("step_rel", ctypes.c_double), ("est_err", ctypes.c_double), ("kappa_est", ctypes.c_double)]
 
 
+class GapBatchFit(ctypes.Structure):
+    _fields_ = [("x_atoms", ctypes.c_void_p), ("n_atoms", ctypes.c_int64), ("config_offsets", ctypes.c_void_p),
+                ("n_configs", ctypes.c_int64), ("x_sparse", ctypes.c_void_p), ("M", ctypes.c_int64),
+                ("sigma", ctypes.c_void_p)]
+
+
 class GapTuning(ctypes.Structure):
     _fields_ = [("qr_split_wgs", ctypes.c_int32), ("qr_panel", ctypes.c_int32), ("qr_lookahead", ctypes.c_int32),
-                ("qr_free_cus", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("qr_free_cus", ctypes.c_int32), ("knm_bn", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class GapLayoutInfo(ctypes.Structure):
@@ -91,6 +97,10 @@ def lib():
     L.gap_fit_static.restype = I32
     L.gap_static_scratch_bytes.argtypes = []
     L.gap_static_scratch_bytes.restype = ctypes.c_size_t
+    L.gap_build_knm_batch.argtypes = [ctypes.POINTER(P), I32, ctypes.POINTER(GapBatchFit), P]
+    L.gap_build_knm_batch.restype = I32
+    L.gap_build_kmm.argtypes = [P]
+    L.gap_build_kmm.restype = I32
     for n in ("gap_create", "gap_bind_workspace", "gap_build_knm", "gap_solve", "gap_predict", "gap_sync",
               "gap_layout", "gap_stage_times", "gap_set_tuning", "gap_set_model", "gap_set_stream",
               "gap_destroy"):
@@ -133,6 +143,25 @@ def fit_static(p: GapParams, X, offsets, XM, sigma, y, c_out, info=True, stream=
                              ctypes.byref(inf) if info else None)
     _check(s, "gap_fit_static")
     return inf
+
+
+def build_knm_batch(handles, inputs, stream=None):
+    """gap_build_knm_batch: the K_NM of every fit as grouped launches on `stream`
+    (torch stream, default: the current one).  inputs[i] = (X, offsets, XM, sigma)
+    for handles[i]; each handle keeps its tensors alive until its next build.
+    Each handle then needs build_kmm() on its own stream, ordered after `stream`."""
+    import torch
+
+    st = stream if stream is not None else torch.cuda.current_stream()
+    n = len(handles)
+    fits = (GapBatchFit * n)()
+    hs = (ctypes.c_void_p * n)()
+    for i, (h, (X, offsets, XM, sigma)) in enumerate(zip(handles, inputs)):
+        h._inputs = (X, offsets, XM, sigma)
+        hs[i] = h.h
+        fits[i] = GapBatchFit(X.data_ptr(), X.shape[0], offsets.data_ptr(), offsets.numel() - 1, XM.data_ptr(),
+                              XM.shape[0], sigma.data_ptr())
+    _check(lib().gap_build_knm_batch(hs, n, fits, ctypes.c_void_p(st.cuda_stream)), "gap_build_knm_batch")
 
 
 def static_scratch_bytes() -> int:
@@ -178,6 +207,9 @@ class Handle:
         self._inputs = (X, offsets, XM, sigma)
         _check(lib().gap_build_knm(self.h, _ptr(X), X.shape[0], _ptr(offsets), offsets.numel() - 1,
                                    _ptr(XM), XM.shape[0], _ptr(sigma)), "gap_build_knm")
+
+    def build_kmm(self):
+        _check(lib().gap_build_kmm(self.h), "gap_build_kmm")
 
     def solve(self, y, c_out, info=True):
         inf = GapSolveInfo() if info else None
@@ -232,13 +264,15 @@ class Handle:
         off = lay.tau - self.ws.data_ptr()
         return self.ws[off:off + 8 * lay.M].view(torch.float64)
 
-    def set_tuning(self, qr_split_wgs=0, qr_panel=0, qr_lookahead=0, qr_free_cus=0):
-        """qr_lookahead: 0 automatic, 1 off, 2 on; qr_free_cus: CUs kept from the look-ahead stream (0 none)."""
+    def set_tuning(self, qr_split_wgs=0, qr_panel=0, qr_lookahead=0, qr_free_cus=0, knm_bn=0):
+        """qr_lookahead: 0 automatic, 1 off, 2 on; qr_free_cus: CUs kept from the look-ahead stream (0 none);
+        knm_bn: K_NM column tile (0 = 64, or 32)."""
         t = GapTuning()
         t.qr_split_wgs = int(qr_split_wgs)
         t.qr_panel = int(qr_panel)
         t.qr_lookahead = int(qr_lookahead)
         t.qr_free_cus = int(qr_free_cus)
+        t.knm_bn = int(knm_bn)
         _check(lib().gap_set_tuning(self.h, ctypes.byref(t)), "gap_set_tuning")
 
     def set_model(self, XM):

@@ -11,9 +11,15 @@ stream, so the fits of different streams overlap on the device.  Each fit
 keeps its own handle and workspace; the library's kernels are deterministic,
 so a fit's weights are bitwise the same alone, in a replay, or on any stream.
 
-The autotuner times whole-sweep replays over a small grid of launch shapes
-(stream count, split-K workgroup target of the QR, QR look-ahead) and keeps a
-table keyed by the sweep's shape bucket.  Run it as a program of its own
+The autotuner has two levels.  Per fit, it times one representative fit of
+each shape bucket (d, M and N_c rounded down to powers of two, precision) under
+every candidate tile / launch shape (K_NM column tile, the QR's split-K
+workgroup target, panel factorisation, look-ahead) and keeps the fastest; a
+fit's shape depends only on its own bucket, so it is the same alone and in any
+batch.  Per sweep, it times whole-sweep replays over the stream count and over
+grouped K_NM launches (every fit's K_NM in grouped launches on one stream,
+gap_build_knm_batch, then each fit's K_MM, Cholesky and solve on its stream)
+against one build per fit, and keeps a table keyed by the sweep's bucket.  Run it as a program of its own
 (`python -m paper_2207_03803_amd.sweep`); it sets 16 hardware queues, like
 the benchmark.
 """
@@ -119,17 +125,22 @@ class Fit:
     c: object = None
     X: object = None
     host: dict = field(default_factory=dict)
+    shape: dict = field(default_factory=dict)
 
 
 class Sweep:
     """The fits of one sweep with their inputs resident on the device."""
 
     def __init__(self, specs, pools, precision=gap.GAP_MIXED_FP32, streams=8, split_wgs=0, lookahead=0,
-                 max_refine_iters=20, refine_tol=1e-12, targets=None):
+                 max_refine_iters=20, refine_tol=1e-12, targets=None, grouped=False, shapes=None):
         import torch
 
         self.specs = specs
         self.pools = pools
+        # grouped: every fit's K_NM as grouped launches on one stream (gap_build_knm_batch),
+        # then each fit's K_MM, Cholesky and solve on its stream
+        self.grouped = grouped
+        self.g_build = None
         self.precision = precision
         self.n_streams = streams
         self.streams = [torch.cuda.Stream() for _ in range(streams)]
@@ -157,8 +168,10 @@ class Sweep:
             p = gap.params(s.d, s.zeta, 1.0, 1e-8, precision=precision, max_refine_iters=max_refine_iters,
                            refine_tol=refine_tol)
             f.handle = gap.Handle(p, stream=self.streams[stream_of[pos]])
-            if split_wgs or lookahead:
-                f.handle.set_tuning(qr_split_wgs=split_wgs, qr_lookahead=lookahead)
+            shp = shapes(s) if shapes else dict(qr_split_wgs=split_wgs, qr_lookahead=lookahead)
+            if any(shp.values()):
+                f.handle.set_tuning(**shp)
+            f.shape = shp
             f.ws = f.handle.alloc_workspace(s.n_configs, n_atoms, s.M)
             f.c = torch.empty(s.M, dtype=torch.float64, device="cuda")
             self.fits.append(f)
@@ -182,18 +195,31 @@ class Sweep:
                 f.y = y
         torch.cuda.synchronize()
 
+    def _batch_build(self):
+        """The grouped K_NM of every fit on the current stream."""
+        gap.build_knm_batch([f.handle for f in self.fits], [(f.X, f.offsets, f.XM, f.sigma) for f in self.fits])
+
+    def _fit_work(self, f):
+        if self.grouped:
+            f.handle.build_kmm()
+        else:
+            f.handle.build_knm(f.X, f.offsets, f.XM, f.sigma)
+        f.handle.solve(f.y, f.c, info=False)
+
     def enqueue(self):
-        """Every fit's build + solve on its stream (no host synchronisation)."""
+        """Every fit's build + solve on its stream (no host synchronisation); with
+        grouped=True the K_NM of all fits first, on the current stream (the caller
+        orders the fits' streams after it)."""
         for k, lst in enumerate(self.assign):
             for i in lst:
-                f = self.fits[i]
-                f.handle.build_knm(f.X, f.offsets, f.XM, f.sigma)
-                f.handle.solve(f.y, f.c, info=False)
+                self._fit_work(self.fits[i])
 
     def run_eager(self):
         import torch
 
         torch.cuda.synchronize()
+        if self.grouped:
+            self._batch_build()
         for st in self.streams:
             st.wait_stream(torch.cuda.current_stream())
         self.enqueue()
@@ -207,6 +233,14 @@ class Sweep:
 
         torch.cuda.synchronize()
         self.graphs = [None] * len(self.fits)
+        if self.grouped:
+            if log:
+                log(f"[sweep] capturing the grouped K_NM of {len(self.fits)} fits")
+            self.g_build = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(self.root):
+                self.g_build.capture_begin()
+                self._batch_build()
+                self.g_build.capture_end()
         for k, lst in enumerate(self.assign):
             st = self.streams[k]
             for i in lst:
@@ -216,8 +250,7 @@ class Sweep:
                 g = torch.cuda.CUDAGraph()
                 with torch.cuda.stream(st):
                     g.capture_begin()
-                    f.handle.build_knm(f.X, f.offsets, f.XM, f.sigma)
-                    f.handle.solve(f.y, f.c, info=False)
+                    self._fit_work(f)
                     g.capture_end()
                 self.graphs[i] = g
         torch.cuda.synchronize()
@@ -231,6 +264,8 @@ class Sweep:
         cur = torch.cuda.current_stream()
         t0 = time.perf_counter()
         for _ in range(n):
+            if self.g_build is not None:
+                self.g_build.replay()  # on cur
             for st in self.streams:
                 st.wait_stream(cur)
             for k, lst in enumerate(self.assign):
@@ -253,6 +288,77 @@ class Sweep:
             f.handle.close()
 
 
+# Per-fit launch / tile shapes the autotuner chooses from: K_NM column tile,
+# the QR's split-K workgroup target (row-chunk height of its Y^T C products)
+# and its panel factorisation (0 shifted CholeskyQR3, 1 TSQR).  Look-ahead stays
+# off in a sweep: there the other fits' streams fill the GPU while a fit's panel
+# chain runs, and a look-ahead stream per fit would oversubscribe the hardware
+# queues (measured: tuned alone with look-ahead as a choice, the 64-fit sweep
+# took 1.89 s instead of 1.67 s).
+SHAPE_CANDIDATES = [dict(knm_bn=bn, qr_split_wgs=w, qr_panel=pn, qr_lookahead=1)
+                    for bn in (64, 32) for w in (1024, 2048, 4096) for pn in (0, 1)]
+
+
+def fit_bucket(spec, precision):
+    """Shape bucket of one fit: d, M and N_c rounded down to powers of two, precision.
+    A fit's shape depends on its own bucket only, so it is the same alone and in
+    any batch."""
+    def p2(v):
+        return 1 << max(0, int(v).bit_length() - 1)
+    return f"d{spec.d}_M{p2(spec.M)}_N{p2(spec.n_configs)}_p{int(precision)}"
+
+
+def shape_for(spec, precision, table=None):
+    """The tuned per-fit shape of a fit's bucket ({} = the library's defaults)."""
+    table = load_table() if table is None else table
+    return {k: v for k, v in table.get("shapes", {}).get(fit_bucket(spec, precision), {}).items()
+            if k in ("knm_bn", "qr_split_wgs", "qr_panel", "qr_lookahead")}
+
+
+def autotune_shapes(specs, pools, precision=gap.GAP_MIXED_FP32, candidates=None, reps=2, path=TUNING_TABLE,
+                    log=print):
+    """Time one representative fit per bucket (the bucket's median-flops fit) under
+    every candidate shape, alone on a stream; keep the fastest that ends GAP_OK.
+    Stores {bucket: shape} under "shapes" in the table at `path`."""
+    import torch
+
+    candidates = candidates or SHAPE_CANDIDATES
+    groups = {}
+    for s in specs:
+        groups.setdefault(fit_bucket(s, precision), []).append(s)
+    table = load_table(path)
+    shapes = table.setdefault("shapes", {})
+    for key, members in sorted(groups.items()):
+        rep = sorted(members, key=lambda s: s.flops())[len(members) // 2]
+        one = Sweep([rep], pools, precision=precision, streams=1, max_refine_iters=30, refine_tol=1e-12)
+        f = one.fits[0]
+        best = None
+        for cand in candidates:
+            f.handle.set_tuning(**cand)
+            st = f.handle.stream
+            with torch.cuda.stream(st):
+                one._fit_work(f)  # warm (creates the look-ahead stream when it is used)
+                t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                t0.record(st)
+                for _ in range(reps):
+                    one._fit_work(f)
+                t1.record(st)
+            t1.synchronize()
+            ms = t0.elapsed_time(t1) / reps
+            status = f.handle.sync()[0]
+            if status == gap.GAP_OK and (best is None or ms < best[1]):
+                best = (cand, ms)
+        one.close()
+        del one
+        torch.cuda.empty_cache()
+        if best is not None:
+            shapes[key] = dict(best[0], ms=best[1], fit=dict(N=rep.n_configs, M=rep.M, d=rep.d))
+            log(f"[autotune] {key}: {best[0]} -> {best[1]:.2f} ms (fit N={rep.n_configs} M={rep.M})")
+    with open(path, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    return shapes
+
+
 def bucket(specs):
     """Shape bucket of a sweep for the tuning table."""
     n = len(specs)
@@ -269,17 +375,19 @@ def load_table(path=TUNING_TABLE):
 
 def autotune(specs, pools, precision=gap.GAP_MIXED_FP32, candidates=None, replays=1, path=TUNING_TABLE,
              log=print):
-    """Time whole-sweep graph replays for each candidate launch shape and keep the best.
+    """Time whole-sweep graph replays for each candidate sweep-level launch shape
+    (stream count; grouped K_NM launches or one build per fit) with every fit in
+    its tuned per-fit shape, and keep the best.
 
     Returns (best, results); stores {bucket: best} in the table at `path`.
     """
-    candidates = candidates or [dict(streams=s, split_wgs=w, lookahead=la) for s in (8, 16) for w in (1024, 2048)
-                                for la in (0, 1)]
+    candidates = candidates or [dict(streams=s, grouped=g) for s in (8, 16) for g in (False, True)]
+    table0 = load_table(path)
     results = []
     for cand in candidates:
         log(f"[autotune] building {cand}")
-        sw = Sweep(specs, pools, precision=precision, streams=cand["streams"], split_wgs=cand["split_wgs"],
-                   lookahead=cand.get("lookahead", 0))
+        sw = Sweep(specs, pools, precision=precision, streams=cand["streams"], grouped=cand.get("grouped", False),
+                   shapes=lambda s: shape_for(s, precision, table0))
         sw.capture()
         log(f"[autotune] captured {len(specs)} fit graphs; first replay")
         sw.replay(1)
@@ -290,9 +398,8 @@ def autotune(specs, pools, precision=gap.GAP_MIXED_FP32, candidates=None, replay
         del sw
     best = min(results, key=lambda r: r["seconds"])
     table = load_table(path)
-    table[bucket(specs)] = dict(streams=best["streams"], split_wgs=best["split_wgs"],
-                                lookahead=best.get("lookahead", 0), seconds=best["seconds"],
-                                precision=int(precision))
+    table[bucket(specs)] = dict(streams=best["streams"], grouped=bool(best.get("grouped", False)),
+                                per_fit_shapes=True, seconds=best["seconds"], precision=int(precision))
     with open(path, "w") as fh:
         json.dump(table, fh, indent=1, sort_keys=True)
     return best, results
@@ -307,10 +414,13 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--n-fits", type=int, default=SWEEP_RECIPE["n_fits"])
     ap.add_argument("--replays", type=int, default=1)
+    ap.add_argument("--table", default=TUNING_TABLE, help="tuning table to update (JSON)")
     args = ap.parse_args()
     specs = make_sweep(seed=args.seed, n_fits=args.n_fits)
     pools = make_pools(specs, seed=args.seed, min_configs=SWEEP_RECIPE["pool_configs"])
-    best, results = autotune(specs, pools, replays=args.replays, log=lambda m: print(m, flush=True))
+    say = lambda m: print(m, flush=True)  # noqa: E731
+    autotune_shapes(specs, pools, log=say, path=args.table)
+    best, results = autotune(specs, pools, replays=args.replays, log=say, path=args.table)
     print(json.dumps(dict(bucket=bucket(specs), best=best, results=results)), flush=True)
 
 

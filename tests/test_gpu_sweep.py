@@ -93,7 +93,8 @@ def test_full_recipe_sweep_fits_match_oracle():
     pools = sweep.make_pools(pinned, seed=0, min_configs=meta["pool_configs"], host=True)
     pools = {d: sweep.Pool(d, p.offsets, torch.from_numpy(p.X).cuda()) for d, p in pools.items()}
     targets = {s.idx: z[f"fit{s.idx}_y"] for s in pinned}
-    tune = sweep.load_table()[sweep.bucket(specs)]
+    table = sweep.load_table()
+    tune = table.get(sweep.bucket(specs), dict(streams=16, grouped=False))
     u = 2.0 ** -53
 
     def bound(idx, floor):
@@ -103,9 +104,10 @@ def test_full_recipe_sweep_fits_match_oracle():
         rn = np.sqrt(float(z[f"fit{idx}_loss_tail"]))
         return max(floor, 32 * u * (kappa + kappa ** 2 * rn / (smax * np.linalg.norm(c)))), kappa
 
-    sw = sweep.Sweep(pinned, pools, precision=gap.GAP_MIXED_FP32, streams=tune["streams"],
-                     split_wgs=tune["split_wgs"], lookahead=tune.get("lookahead", 0), max_refine_iters=60,
-                     refine_tol=1e-12, targets=targets)
+    prec = gap.GAP_MIXED_FP32
+    sw = sweep.Sweep(pinned, pools, precision=prec, streams=tune["streams"], grouped=tune.get("grouped", False),
+                     shapes=lambda s: sweep.shape_for(s, prec, table), max_refine_iters=60, refine_tol=1e-12,
+                     targets=targets)
     sw.capture()
     sw.replay(1)
     st = sw.statuses()
@@ -113,8 +115,8 @@ def test_full_recipe_sweep_fits_match_oracle():
         idx = f.spec.idx
         b, kappa = bound(idx, 1e-8)
         err = rel(c, z[f"fit{idx}_c"])
-        log(f"  graph, mixed: fit {idx}: kappa(A) {kappa:.2e}; {gap.status_string(s)}; c rel err {err:.2e} "
-            f"(allowed {b:.1e})")
+        log(f"  graph, mixed: fit {idx} shape {f.shape}: kappa(A) {kappa:.2e}; {gap.status_string(s)}; "
+            f"c rel err {err:.2e} (allowed {b:.1e})")
         assert s == gap.GAP_OK
         assert err <= b
     sw.close()
@@ -128,3 +130,52 @@ def test_full_recipe_sweep_fits_match_oracle():
         assert s == gap.GAP_OK
         assert err <= b
     seq.close()
+
+
+def test_grouped_knm_and_tile_shapes_leave_results_bitwise_unchanged():
+    """The K_NM of every fit in grouped launches (gap_build_knm_batch + gap_build_kmm)
+    against one gap_build_knm per fit, and the K_NM column tile of 32 against 64:
+    every fit's stacked matrix and weights are the same bit for bit; the batch
+    also matches the oracle."""
+    import torch
+
+    from paper_2207_03803_amd import gap, sweep
+
+    specs = sweep.make_sweep(seed=4, n_fits=10, scale=0.05)
+    pools = sweep.make_pools(specs, seed=4)
+    runs = {}
+    for name, grouped, bn in (("per-fit", False, 64), ("grouped", True, 64), ("grouped bn32", True, 32)):
+        sw = sweep.Sweep(specs, pools, precision=gap.GAP_FP64, streams=4, grouped=grouped,
+                         shapes=lambda s, bn=bn: dict(knm_bn=bn))
+        sw.capture()
+        sw.replay(2)
+        assert all(st == gap.GAP_OK for st in sw.statuses())
+        runs[name] = sw.weights()
+        # the stacked matrix of the first fit, from an eager rebuild in this mode
+        f = sw.fits[0]
+        if grouped:
+            gap.build_knm_batch([f.handle], [(f.X, f.offsets, f.XM, f.sigma)])
+            torch.cuda.synchronize()
+            f.handle.build_kmm()
+        else:
+            f.handle.build_knm(f.X, f.offsets, f.XM, f.sigma)
+        torch.cuda.synchronize()  # the rebuild ran on the fit's stream
+        Av, lay = f.handle.A_view()  # [column, row]; rows past N + M are padding
+        runs[name + " A"] = Av[:lay.M, :lay.N + lay.M].cpu().numpy()
+        sw.close()
+    for name in ("grouped", "grouped bn32"):
+        a, b = runs[name + " A"], runs["per-fit A"]
+        diff = np.argwhere(a != b)
+        assert len(diff) == 0, (name, diff[:5], a.shape)
+        for a, b in zip(runs[name], runs["per-fit"]):
+            assert np.array_equal(a, b), name
+    orc = oracle.Oracle()
+    sw = sweep.Sweep(specs[:3], pools, precision=gap.GAP_FP64, streams=2, grouped=True)
+    sw.run_eager()
+    for f, c in zip(sw.fits, sw.weights()):
+        ref = orc.fit(f.X.cpu().numpy(), f.offsets.cpu().numpy(), f.XM.cpu().numpy(), f.host["sigma"],
+                      f.y.cpu().numpy(), f.spec.zeta, jitter=1e-8)
+        err = rel(c, ref.c)
+        log(f"  grouped build, fit {f.spec.idx}: c rel err vs oracle {err:.2e}")
+        assert err <= 1e-10
+    sw.close()
