@@ -149,6 +149,7 @@ def test_predict_equals_knm_c_at_full_size(full):
     N, M = f["N"], f["M"]
     out = torch.empty(N, dtype=torch.float64, device="cuda")
     f["h"].predict(f["X"], f["offsets"], f["c_dev"], out)
+    assert f["h"].sync()[0] == 0  # waits for the handle's stream
     expect = inp.sigma * (A[:M, :N].T @ f["c"])
     got = out.cpu().numpy()
     err = np.linalg.norm(got - expect) / np.linalg.norm(expect)
