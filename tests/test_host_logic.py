@@ -173,7 +173,7 @@ def test_traffic_record_scales_the_knm_launch_by_the_copy_calibration(tmp_path):
 
     from paper_2207_03803_amd import profiling
 
-    knm = "void gap::knm_kernel(gap::KnmArgs)"
+    knm = "void gap::knm_kernel<64>(gap::KnmArgs)"
     copy = "__amd_rocclr_copyBuffer"
     paths = {}
     for key, counter, rows in (
@@ -187,7 +187,7 @@ def test_traffic_record_scales_the_knm_launch_by_the_copy_calibration(tmp_path):
         paths[key] = str(d / "counter_collection.csv")
         _counter_csv(paths[key], rows)
     out = str(tmp_path / "rec")
-    profiling.traffic(argparse.Namespace(out=out, **paths))
+    profiling.traffic(argparse.Namespace(out=out, bench_args="--steps 1 --forms none", **paths))
     rec = json.load(open(out + ".json"))
     ff = profiling.COPY_BYTES / (5.2e5 * 1024)  # the median copy launch, the largest K_NM dispatch
     wf = profiling.COPY_BYTES / (1.1e6 * 1024)
@@ -199,6 +199,7 @@ def test_traffic_record_scales_the_knm_launch_by_the_copy_calibration(tmp_path):
     assert rec["source_sha256"] == profiling.source_hash()
     md = open(out + ".md").read()
     assert f"-d {tmp_path / 'fit_fetch'} -o fit" in md and f"-d {tmp_path / 'copy_write'} -o copy" in md
+    assert "python3 bench.py --steps 1 --forms none" in md
 
 
 def test_committed_traffic_record_is_consistent():
