@@ -62,11 +62,11 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, int32_t precision, int
     };
     L.off_A = take(sizeof(double) * (size_t)L.lda * (size_t)L.ncols);
     L.off_tau = take(sizeof(double) * (size_t)M);
-    L.off_wpart = take(sizeof(double) * (size_t)qr_max_chunks() * 2 * QR_NB * (size_t)L.ncols);
-    L.off_T = take(sizeof(double) * 4 * QR_NB * QR_NB);
+    L.off_wpart = take(sizeof(double) * (size_t)qr_max_chunks() * 4 * QR_NB * (size_t)L.ncols);
+    L.off_T = take(sizeof(double) * 16 * QR_NB * QR_NB);
     L.off_Tin = take(sizeof(double) * 2 * QR_NB * QR_NB);
     L.off_U = take(sizeof(double) * QR_NB * QR_NB);
-    L.off_W = take(sizeof(double) * 2 * QR_NB * (size_t)((L.ncols + 63) / 64 * 64));
+    L.off_W = take(sizeof(double) * 4 * QR_NB * (size_t)((L.ncols + 63) / 64 * 64));
     L.off_ts_tiles = take(sizeof(double) * (size_t)L.tree.tiles_doubles);
     L.off_ts_X = take(sizeof(double) * (size_t)L.tree.tiles_doubles);
     L.off_ts_tau = take(sizeof(double) * (size_t)L.tree.tau_doubles);
@@ -82,15 +82,15 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, int32_t precision, int
     L.off_cq_part = take(sizeof(double) * (size_t)CQ_MAX_CHUNKS * QR_NB * QR_NB);
     L.off_cq_G = take(sizeof(double) * 4 * QR_NB * QR_NB);
     L.off_cq_R = take(sizeof(double) * 4 * QR_NB * QR_NB);
-    L.off_T2 = take(sizeof(double) * 4 * QR_NB * QR_NB);
-    L.off_wpart_s = take(sizeof(double) * (size_t)qr_max_chunks_s() * 2 * QR_NB * 2 * QR_NB);
-    L.off_W_s = take(sizeof(double) * 4 * QR_NB * QR_NB);
-    L.off_W32_s = take(sizeof(float) * 4 * QR_NB * QR_NB);
+    L.off_T2 = take(sizeof(double) * 16 * QR_NB * QR_NB);
+    L.off_wpart_s = take(sizeof(double) * (size_t)qr_max_chunks_s() * 4 * QR_NB * 2 * QR_NB);
+    L.off_W_s = take(sizeof(double) * 16 * QR_NB * QR_NB);
+    L.off_W32_s = take(sizeof(float) * 16 * QR_NB * QR_NB);
     L.off_diag = take(sizeof(double) * (size_t)(14 * M + 512));
     if (mixed) {
         const int64_t ldw = (L.ncols + 63) / 64 * 64;
         L.off_A32 = take(sizeof(float) * (size_t)L.lda * (size_t)L.ncols);
-        L.off_W32 = take(sizeof(float) * 2 * QR_NB * (size_t)ldw);
+        L.off_W32 = take(sizeof(float) * 4 * QR_NB * (size_t)ldw);
         L.off_r = take(sizeof(double) * (size_t)L.m);
         L.off_s = take(sizeof(double) * (size_t)M);
         L.off_z = take(sizeof(double) * (size_t)M);

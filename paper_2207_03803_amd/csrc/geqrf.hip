@@ -29,8 +29,8 @@ constexpr int TILE = TR * NB;  // doubles per tile
 constexpr int NPART = 8;           // threads per tile column
 constexpr int TS_NT = NB * NPART;  // threads of the TSQR kernels
 constexpr int SLOTS = TR / NPART;  // rows held per thread (row = NPART * slot + part)
-constexpr int64_t MAX_CHUNKS = 64;     // row chunks of the split-K products into the bulk buffer
-constexpr int64_t MAX_CHUNKS_S = 256;  // into the look-ahead's small buffer (at most 2 QR_NB columns)
+constexpr int64_t MAX_CHUNKS = 32;     // row chunks of the split-K products into the bulk buffer
+constexpr int64_t MAX_CHUNKS_S = 256;  // into the small buffer at 2 QR_NB columns (half that at 4 QR_NB)
 
 int64_t qr_max_chunks() { return MAX_CHUNKS; }
 int64_t qr_max_chunks_s() { return MAX_CHUNKS_S; }
@@ -404,19 +404,20 @@ DEV bool update_tile(int64_t n_rb, int64_t n_cb, int64_t &rb, int64_t &cb)
 }
 
 // Row-block split of a trailing update: PART 0 every row block, 1 the interior
-// ones (1 .. n_rb - 2: full rows, below Y's unit triangle, loaded without
-// checks), 2 the two edge ones (0 and n_rb - 1).
+// ones (n_head .. n_rb - 2: full rows, below Y's unit triangle, loaded without
+// checks), 2 the edge ones (the n_head row blocks that meet Y's triangle, and
+// n_rb - 1).
 template <int PART>
-DEV bool update_tile_part(int64_t n_rb, int64_t n_cb, int64_t &rb, int64_t &cb)
+DEV bool update_tile_part(int64_t n_rb, int64_t n_cb, int n_head, int64_t &rb, int64_t &cb)
 {
     if constexpr (PART == 1) {
-        if (!update_tile(n_rb - 2, n_cb, rb, cb))
+        if (!update_tile(n_rb - n_head - 1, n_cb, rb, cb))
             return false;
-        rb += 1;
+        rb += n_head;
     } else if constexpr (PART == 2) {
-        if (!update_tile(n_rb > 1 ? 2 : 1, n_cb, rb, cb))
+        if (!update_tile(n_head + 1, n_cb, rb, cb))
             return false;
-        if (rb == 1)
+        if (rb == n_head)
             rb = n_rb - 1;
     } else {
         if (!update_tile(n_rb, n_cb, rb, cb))
@@ -425,7 +426,8 @@ DEV bool update_tile_part(int64_t n_rb, int64_t n_cb, int64_t &rb, int64_t &cb)
     return true;
 }
 
-constexpr int OB = 2 * NB;                 // outer block: two TSQR panels
+constexpr int OB = 2 * NB;                 // a TSQR panel pair (one factor_block)
+constexpr int OB2 = 2 * OB;                // outer block of the trailing update: two panel pairs
 using WS = TileShape<OB, 128, 16, 2, 2>;   // P = Y^T C over a row chunk
 using US = TileShape<128, 128, 16, 2, 2>;  // C^T -= W^T Y^T (rows of C along the MFMA N axis)
 
@@ -437,6 +439,12 @@ __global__ __launch_bounds__(256, 2) void qr_wpart_kernel(QrWork w, int64_t j0, 
                                                           int ymode, int64_t r0, int64_t chunk)
 {
     __shared__ double lds[2 * WS::STAGE];
+    // blockIdx.z: which 128-column half of a block of up to 256 (rows OB z .. of P)
+    const int prow0 = OB * (int)blockIdx.z;
+    j0 += prow0;
+    pw = (pw - prow0) < OB ? (pw - prow0) : OB;
+    if (pw <= 0)
+        return;
     const int64_t ch = blockIdx.y;
     const int64_t q0 = (int64_t)blockIdx.x * WS::BN;
     const int64_t rlo = r0 + ch * chunk;
@@ -489,7 +497,7 @@ __global__ __launch_bounds__(256, 2) void qr_wpart_kernel(QrWork w, int64_t j0, 
     gemm_tile_runs<WS, true, true, false>(acc, lds, rhi - rlo, fa, fb);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WS::WN, wn = wave % WS::WN;
-    double *P = w.wpart + ch * OB * w.wp_ld;
+    double *P = w.wpart + (ch * OB2 + prow0) * w.wp_ld;
 #pragma unroll
     for (int i = 0; i < WS::FM; ++i)
 #pragma unroll
@@ -510,7 +518,7 @@ __global__ __launch_bounds__(256, 2) void qr_wpart_kernel(QrWork w, int64_t j0, 
 // two sums); T is staged in LDS as its packed upper triangle.
 template <class TW>
 __global__ __launch_bounds__(256) void qr_wred_kernel(QrWork w, const double *__restrict__ T, int tld, int pw,
-                                                      int64_t nch, int64_t nt, TW *__restrict__ Wout)
+                                                      int64_t nch, int64_t nt, TW *__restrict__ Wout, int prow0)
 {
     __shared__ double Pm[OB][64 + 1];
     __shared__ double Tt[OB * (OB + 1) / 2];  // column p at p (p + 1) / 2 holds T[0..p][p]
@@ -534,8 +542,8 @@ __global__ __launch_bounds__(256) void qr_wred_kernel(QrWork w, const double *__
     for (int p = part; p < pw; p += 4) {
         double s0 = 0.0, s1 = 0.0;
         if (q < nt) {
-            const double *src = w.wpart + p * w.wp_ld + q;
-            const int64_t step = (int64_t)OB * w.wp_ld;
+            const double *src = w.wpart + (prow0 + p) * w.wp_ld + q;
+            const int64_t step = (int64_t)OB2 * w.wp_ld;
             int64_t ch = 0;
             for (; ch + 1 < nch; ch += 2) {
                 s0 += src[ch * step];
@@ -554,7 +562,7 @@ __global__ __launch_bounds__(256) void qr_wred_kernel(QrWork w, const double *__
         double s = 0.0;
         for (int r = 0; r <= p; ++r)
             s += tc[r] * Pm[r][ql];
-        Wout[p * w.ldw + q] = (TW)s;
+        Wout[(prow0 + p) * w.ldw + q] = (TW)s;
     }
 }
 
@@ -570,7 +578,7 @@ __global__ __launch_bounds__(256) void qr_psum_kernel(QrWork w, int pw, int64_t 
         return;
     const int64_t p = e / nt, q = e % nt;
     double *src = w.wpart + p * w.wp_ld + q;
-    const int64_t step = (int64_t)OB * w.wp_ld;
+    const int64_t step = (int64_t)OB2 * w.wp_ld;
     double s0 = 0.0, s1 = 0.0;
     int64_t ch = 0;
 #pragma unroll 4
@@ -583,17 +591,19 @@ __global__ __launch_bounds__(256) void qr_psum_kernel(QrWork w, int pw, int64_t 
     src[0] = s0 + s1;
 }
 
-// G = Y_A^T Y_B from the chunk partials (grid 16: one entry per thread, rows
-// p < 64 of the partials, columns q < pwb; chunks summed in the same fixed
-// order as qr_wred_kernel).
-__global__ __launch_bounds__(256) void qr_gsum_kernel(QrWork w, int pwb, int64_t nch, double *__restrict__ G)
+// G = Y_A^T Y_B from the chunk partials (one entry per thread: ld x ld
+// entries, rows p < ld of the partials, columns q < pwb, G row-major with leading
+// dimension ld; chunks summed in the same fixed order as qr_wred_kernel).
+__global__ __launch_bounds__(256) void qr_gsum_kernel(QrWork w, int pwb, int64_t nch, double *__restrict__ G, int ld)
 {
     const int e = blockIdx.x * 256 + threadIdx.x;
-    const int p = e / NB, q = e % NB;
+    if (e >= ld * ld)
+        return;
+    const int p = e / ld, q = e % ld;
     double s0 = 0.0, s1 = 0.0;
     if (q < pwb) {
         const double *src = w.wpart + p * w.wp_ld + q;
-        const int64_t step = (int64_t)OB * w.wp_ld;
+        const int64_t step = (int64_t)OB2 * w.wp_ld;
         int64_t ch = 0;
         for (; ch + 1 < nch; ch += 2) {
             s0 += src[ch * step];
@@ -657,16 +667,92 @@ __global__ __launch_bounds__(256) void qr_tcombine_kernel(QrWork w, const double
     }
 }
 
+// ---------------------------------------------------------------------------
+// A trailing-update block of two panel pairs a | b (up to 256 columns).  Its
+// compact-WY factor is T = [[T_a, -T_a G T_b], [0, T_b]] with G = Y_a^T Y_b, so
+// W = T^T P for P = Y^T C splits into W_a = T_a^T P_a and
+// W_b = T_b^T (P_b - H^T P_a) with H = T_a G: the two 128-row halves reuse the
+// 128-column reduction, and the update C -= Y W runs once with depth 256.
+// ---------------------------------------------------------------------------
+
+// H = T_a G (T_a upper triangular pwa x pwa, row-major ld tld; G and H
+// row-major, leading dimension OB; columns q < pwb).  Grid OB: workgroup i
+// forms row i, one column per thread.
+__global__ __launch_bounds__(OB) void qr_hmat_kernel(const double *__restrict__ Ta, int tld, int pwa,
+                                                     const double *__restrict__ G, int pwb, double *__restrict__ H)
+{
+    const int i = blockIdx.x, j = threadIdx.x;
+    double v = 0.0;
+    if (i < pwa && j < pwb)
+        for (int k = i; k < pwa; ++k)
+            v += Ta[i * tld + k] * G[k * OB + j];
+    H[i * OB + j] = v;
+}
+
+// P_b -= H^T P_a on the summed partials (chunk 0): P rows OB + p, p < pwb, columns
+// q < nt.  Workgroup (x, y) takes 64 columns and the 32 rows p of quarter y, with
+// P_a (rows s < pwa) and H's 32 columns staged in LDS; thread (q, part) forms
+// rows p = 32 y + 8 part .. + 7.
+constexpr int PC_ROWS = 32;
+__global__ __launch_bounds__(256) void qr_pcorr_kernel(QrWork w, const double *__restrict__ H, int pwa, int pwb,
+                                                       int64_t nt)
+{
+    __shared__ double Pa[OB][64];
+    __shared__ double Hs[OB][PC_ROWS];
+    const int t = threadIdx.x, ql = t & 63, part = t >> 6;
+    const int p0 = PC_ROWS * (int)blockIdx.y;
+    if (p0 >= pwb)
+        return;
+    const int64_t q = (int64_t)blockIdx.x * 64 + ql;
+    for (int sr = part; sr < OB; sr += 4)
+        Pa[sr][ql] = (sr < pwa && q < nt) ? w.wpart[sr * w.wp_ld + q] : 0.0;
+    for (int e = t; e < OB * PC_ROWS; e += 256) {
+        const int sr = e / PC_ROWS, pp = e % PC_ROWS;
+        Hs[sr][pp] = sr < pwa ? H[sr * OB + p0 + pp] : 0.0;
+    }
+    __syncthreads();
+    if (q >= nt)
+        return;
+    double acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        acc[u] = 0.0;
+    for (int sr = 0; sr < pwa; ++sr) {
+        const double a = Pa[sr][ql];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            acc[u] += Hs[sr][8 * part + u] * a;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int p = p0 + 8 * part + u;
+        if (p < pwb)
+            w.wpart[(OB + p) * w.wp_ld + q] -= acc[u];
+    }
+}
+
+// Copy a pw x pw row-major T (leading dimension sld) into dst (leading dimension OB).
+__global__ __launch_bounds__(256) void qr_tcopy_kernel(const double *__restrict__ src, int sld, int pw,
+                                                       double *__restrict__ dst)
+{
+    for (int e = threadIdx.x; e < OB * OB; e += 256) {
+        const int i = e / OB, j = e % OB;
+        dst[e] = (i < pw && j < pw) ? src[i * sld + j] : 0.0;
+    }
+}
+
 // C[r][q] -= sum_p Y[r][p] W[p][q] for rows j0.. and columns c0 .. c0+nt; the
 // tile is computed transposed so that consecutive lanes write consecutive rows.
 // The accumulators start from the C tile (its loads in flight with the first
 // operand slices) and take -W, so the epilogue is a plain store.
 template <int PART>
-__global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt)
+__global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt,
+                                                          int n_head)
 {
     __shared__ double lds[2 * US::STAGE];
     int64_t rb, cb;
-    if (!update_tile_part<PART>((w.m - j0 + US::BN - 1) / US::BN, (nt + US::BM - 1) / US::BM, rb, cb))
+    if (!update_tile_part<PART>((w.m - j0 + US::BN - 1) / US::BN, (nt + US::BM - 1) / US::BM, n_head, rb,
+                                cb))
         return;
     const int64_t q0 = cb * US::BM;
     const int64_t r0 = j0 + rb * US::BN;
@@ -745,6 +831,11 @@ __global__ __launch_bounds__(256, 2) void qr_wpart32_kernel(QrWork w, int64_t j0
                                                             int ymode, int64_t r0, int64_t chunk)
 {
     __shared__ float lds[2 * WS32::STAGE];
+    const int prow0 = OB * (int)blockIdx.z;
+    j0 += prow0;
+    pw = (pw - prow0) < OB ? (pw - prow0) : OB;
+    if (pw <= 0)
+        return;
     const int64_t ch = blockIdx.y;
     const int64_t q0 = (int64_t)blockIdx.x * WS32::BN;
     const int64_t rlo = r0 + ch * chunk;
@@ -797,7 +888,7 @@ __global__ __launch_bounds__(256, 2) void qr_wpart32_kernel(QrWork w, int64_t j0
     gemm_tile_runs32<WS32, true, true>(acc, lds, rhi - rlo, fa, fb);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WS32::WN, wn = wave % WS32::WN;
-    double *P = w.wpart + ch * OB * w.wp_ld;
+    double *P = w.wpart + (ch * OB2 + prow0) * w.wp_ld;
 #pragma unroll
     for (int i = 0; i < WS32::FM; ++i)
 #pragma unroll
@@ -812,11 +903,13 @@ __global__ __launch_bounds__(256, 2) void qr_wpart32_kernel(QrWork w, int64_t j0
 }
 
 template <int PART>
-__global__ __launch_bounds__(256, 2) void qr_update32_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt)
+__global__ __launch_bounds__(256, 2) void qr_update32_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt,
+                                                          int n_head)
 {
     __shared__ float lds[2 * US32::STAGE];
     int64_t rb, cb;
-    if (!update_tile_part<PART>((w.m - j0 + US32::BN - 1) / US32::BN, (nt + US32::BM - 1) / US32::BM, rb, cb))
+    if (!update_tile_part<PART>((w.m - j0 + US32::BN - 1) / US32::BN, (nt + US32::BM - 1) / US32::BM, n_head, rb,
+                                cb))
         return;
     const int64_t q0 = cb * US32::BM;
     const int64_t r0 = j0 + rb * US32::BN;
@@ -927,63 +1020,100 @@ static void factor_panel(const QrWork &w, int64_t j0, int pw, double *Tout, hipS
 // P = Y^T C (split over row chunks) for the block at (j0, j0) of width pw.
 template <class T>
 static void launch_wpart(const QrWork &w, int64_t j0, int pw, int64_t c0, int64_t nt, int ymode, int64_t r0,
-                         int64_t chunk, int64_t ncb, int64_t nch, hipStream_t s)
+                         int64_t chunk, int64_t ncb, int64_t nch, int halves, hipStream_t s)
 {
     if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL(qr_wpart_kernel, dim3((unsigned)ncb, (unsigned)nch), dim3(256), 0, s, w, j0, pw, c0,
-                           nt, ymode, r0, chunk);
+        hipLaunchKernelGGL(qr_wpart_kernel, dim3((unsigned)ncb, (unsigned)nch, (unsigned)halves), dim3(256), 0, s, w,
+                           j0, pw, c0, nt, ymode, r0, chunk);
     else
-        hipLaunchKernelGGL(qr_wpart32_kernel, dim3((unsigned)ncb, (unsigned)nch), dim3(256), 0, s, w, j0, pw,
-                           c0, nt, ymode, r0, chunk);
+        hipLaunchKernelGGL(qr_wpart32_kernel, dim3((unsigned)ncb, (unsigned)nch, (unsigned)halves), dim3(256), 0, s,
+                           w, j0, pw, c0, nt, ymode, r0, chunk);
 }
 
-// C := (I - Y T Y^T)^T C for the columns c0 .. c0+nt, Y the block at (j0, j0) of width pw.
+// The compact-WY data of a trailing-update block at column J: panel pair a
+// (pwa <= OB columns, T_a) and, when present, pair b (pwb columns, T_b) with
+// H = T_a Y_a^T Y_b.  Storage: four OB x OB row-major matrices (Ta, Tb, G, H).
+struct BlockT {
+    double *store;
+    int pwa = 0, pwb = 0;
+    const double *ta = nullptr;  // T_a as apply_block reads it (row-major, ld tld); null: Ta()
+    int tld = OB;
+    double *Ta() const { return store; }
+    double *Tb() const { return store + OB * OB; }
+    double *G() const { return store + 2 * OB * OB; }
+    double *H() const { return store + 3 * OB * OB; }
+    int pw() const { return pwa + pwb; }
+};
+
+// C := (I - Y T Y^T)^T C for the columns c0 .. c0+nt, Y the block at (J, J).
 template <class T>
-static void apply_block(const QrWork &w, int64_t j0, int pw, const double *Tm, int tld, int64_t c0, int64_t nt,
-                        hipStream_t s)
+static void apply_block(const QrWork &w, int64_t J, const BlockT &bt, int64_t c0, int64_t nt, hipStream_t s)
 {
     if (nt <= 0)
         return;
-    const int64_t rows = w.m - j0;
+    const int pw = bt.pw();
+    const int64_t rows = w.m - J;
     const int64_t ncb = (nt + WS::BN - 1) / WS::BN;
     int64_t chunk, nch;
-    chunking(rows, ncb, chunk, nch, w.max_chunks, w.split_wgs > 0 ? w.split_wgs : 2048);
-    launch_wpart<T>(w, j0, pw, c0, nt, 0, j0, chunk, ncb, nch, s);
+    const int halves = bt.pwb > 0 ? 2 : 1;  // 128-row halves of P, one grid layer each
+    chunking(rows, ncb * halves, chunk, nch, w.max_chunks, w.split_wgs > 0 ? w.split_wgs : 2048);
+    launch_wpart<T>(w, J, pw, c0, nt, 0, J, chunk, ncb, nch, halves, s);
     if (nch > 1) {
         hipLaunchKernelGGL(qr_psum_kernel, dim3((unsigned)(((int64_t)pw * nt + 255) / 256)), dim3(256), 0, s, w, pw,
                            nch, nt);
         nch = 1;
     }
+    const unsigned gq = (unsigned)((nt + 63) / 64);
+    const double *ta = bt.ta ? bt.ta : bt.Ta();
+    const int tld = bt.ta ? bt.tld : OB;
     if constexpr (sizeof(T) == 8) {
-        hipLaunchKernelGGL(qr_wred_kernel<double>, dim3((unsigned)((nt + 63) / 64)), dim3(256), 0, s, w, Tm, tld,
-                           pw, nch, nt, w.W);
-        const int64_t nrb = (rows + US::BN - 1) / US::BN, ncb_u = (nt + US::BM - 1) / US::BM;
-        auto grid = [](int64_t tiles) { return dim3((unsigned)((tiles + 7) & ~int64_t(7))); };
-        if (nrb > 2) {  // interior row blocks without checks, then the two edge ones
-            hipLaunchKernelGGL(qr_update_kernel<1>, grid((nrb - 2) * ncb_u), dim3(256), 0, s, w, j0, pw, c0, nt);
-            hipLaunchKernelGGL(qr_update_kernel<2>, grid(2 * ncb_u), dim3(256), 0, s, w, j0, pw, c0, nt);
-        } else {
-            hipLaunchKernelGGL(qr_update_kernel<0>, grid(nrb * ncb_u), dim3(256), 0, s, w, j0, pw, c0, nt);
+        hipLaunchKernelGGL(qr_wred_kernel<double>, dim3(gq), dim3(256), 0, s, w, ta, tld, bt.pwa, nch, nt, w.W, 0);
+        if (bt.pwb > 0) {
+            hipLaunchKernelGGL(qr_pcorr_kernel, dim3(gq, OB / PC_ROWS), dim3(256), 0, s, w, (const double *)bt.H(),
+                               bt.pwa, bt.pwb, nt);
+            hipLaunchKernelGGL(qr_wred_kernel<double>, dim3(gq), dim3(256), 0, s, w, (const double *)bt.Tb(), OB,
+                               bt.pwb, nch, nt, w.W, OB);
         }
     } else {
-        hipLaunchKernelGGL(qr_wred_kernel<float>, dim3((unsigned)((nt + 63) / 64)), dim3(256), 0, s, w, Tm, tld,
-                           pw, nch, nt, w.W32);
-        const int64_t nrb = (rows + US32::BN - 1) / US32::BN, ncb_u = (nt + US32::BM - 1) / US32::BM;
-        auto grid = [](int64_t tiles) { return dim3((unsigned)((tiles + 7) & ~int64_t(7))); };
-        if (nrb > 2) {
-            hipLaunchKernelGGL(qr_update32_kernel<1>, grid((nrb - 2) * ncb_u), dim3(256), 0, s, w, j0, pw, c0, nt);
-            hipLaunchKernelGGL(qr_update32_kernel<2>, grid(2 * ncb_u), dim3(256), 0, s, w, j0, pw, c0, nt);
+        hipLaunchKernelGGL(qr_wred_kernel<float>, dim3(gq), dim3(256), 0, s, w, ta, tld, bt.pwa, nch, nt, w.W32,
+                           0);
+        if (bt.pwb > 0) {
+            hipLaunchKernelGGL(qr_pcorr_kernel, dim3(gq, OB / PC_ROWS), dim3(256), 0, s, w, (const double *)bt.H(),
+                               bt.pwa, bt.pwb, nt);
+            hipLaunchKernelGGL(qr_wred_kernel<float>, dim3(gq), dim3(256), 0, s, w, (const double *)bt.Tb(), OB,
+                               bt.pwb, nch, nt, w.W32, OB);
+        }
+    }
+    const int n_head = (pw + 127) / 128;  // row blocks of 128 that meet Y's unit triangle
+    auto grid = [](int64_t tiles) { return dim3((unsigned)((tiles + 7) & ~int64_t(7))); };
+    if constexpr (sizeof(T) == 8) {
+        const int64_t nrb = (rows + US::BN - 1) / US::BN, ncb_u = (nt + US::BM - 1) / US::BM;
+        if (nrb > n_head + 1) {  // interior row blocks without checks, then the edge ones
+            hipLaunchKernelGGL(qr_update_kernel<1>, grid((nrb - n_head - 1) * ncb_u), dim3(256), 0, s, w, J, pw, c0,
+                               nt, n_head);
+            hipLaunchKernelGGL(qr_update_kernel<2>, grid((n_head + 1) * ncb_u), dim3(256), 0, s, w, J, pw, c0, nt,
+                               n_head);
         } else {
-            hipLaunchKernelGGL(qr_update32_kernel<0>, grid(nrb * ncb_u), dim3(256), 0, s, w, j0, pw, c0, nt);
+            hipLaunchKernelGGL(qr_update_kernel<0>, grid(nrb * ncb_u), dim3(256), 0, s, w, J, pw, c0, nt, n_head);
+        }
+    } else {
+        const int64_t nrb = (rows + US32::BN - 1) / US32::BN, ncb_u = (nt + US32::BM - 1) / US32::BM;
+        if (nrb > n_head + 1) {
+            hipLaunchKernelGGL(qr_update32_kernel<1>, grid((nrb - n_head - 1) * ncb_u), dim3(256), 0, s, w, J, pw,
+                               c0, nt, n_head);
+            hipLaunchKernelGGL(qr_update32_kernel<2>, grid((n_head + 1) * ncb_u), dim3(256), 0, s, w, J, pw, c0, nt,
+                               n_head);
+        } else {
+            hipLaunchKernelGGL(qr_update32_kernel<0>, grid(nrb * ncb_u), dim3(256), 0, s, w, J, pw, c0, nt, n_head);
         }
     }
 }
 
-// Factor the block of up to two panels at column J (main-stream scratch in w):
-// panel A, its update of panel B, panel B, and the combined compact-WY T into
-// Tout (row-major, ld OB).  Returns the block's width; *Tm / *tld describe its T.
+// Factor the panel pair at column J (main-stream scratch in w): panel A, its
+// update of panel B, panel B, and the pair's compact-WY T (row-major, copied
+// to Tdst with leading dimension OB).  Returns the pair's width.
 template <class T>
-static int factor_block(const QrWork &w, int64_t J, double *Tout, const double **Tm, int *tld, hipStream_t s)
+static int factor_pair(const QrWork &w, int64_t J, double *Tdst, hipStream_t s)
 {
     double *Ta = w.Tin, *Tb = w.Tin + NB * NB;
     const int pwa = (int)((w.n - J) < NB ? (w.n - J) : NB);
@@ -991,68 +1121,94 @@ static int factor_block(const QrWork &w, int64_t J, double *Tout, const double *
     const int64_t jb = J + pwa;
     const int pwb = (int)((w.n - jb) < NB ? (w.n - jb) : NB);
     if (pwb <= 0) {
-        *Tm = Ta;
-        *tld = NB;
+        hipLaunchKernelGGL(qr_tcopy_kernel, dim3(1), dim3(256), 0, s, (const double *)Ta, NB, pwa, Tdst);
         return pwa;
     }
-    apply_block<T>(w, J, pwa, Ta, NB, jb, pwb, s);
+    BlockT pa{nullptr, pwa, 0, Ta, NB};  // panel A alone
+    apply_block<T>(w, J, pa, jb, pwb, s);
     factor_panel<T>(w, jb, pwb, Tb, s);
     const int64_t rows = w.m - jb;
     int64_t chunk, nch;
     chunking(rows, 1, chunk, nch, w.max_chunks);
-    launch_wpart<T>(w, J, pwa, jb, (int64_t)pwb, 1, jb, chunk, 1, nch, s);
-    hipLaunchKernelGGL(qr_gsum_kernel, dim3(NB * NB / 256), dim3(256), 0, s, w, pwb, nch, w.cq_G);
-    hipLaunchKernelGGL(qr_tcombine_kernel, dim3(1), dim3(256), 0, s, w, (const double *)w.cq_G, Tout);
-    *Tm = Tout;
-    *tld = OB;
+    launch_wpart<T>(w, J, pwa, jb, (int64_t)pwb, 1, jb, chunk, 1, nch, 1, s);
+    hipLaunchKernelGGL(qr_gsum_kernel, dim3(NB * NB / 256), dim3(256), 0, s, w, pwb, nch, w.cq_G, NB);
+    hipLaunchKernelGGL(qr_tcombine_kernel, dim3(1), dim3(256), 0, s, w, (const double *)w.cq_G, Tdst);
     return pwa + pwb;
+}
+
+// Factor the trailing-update block at column J: panel pair a, its update of
+// pair b's columns, pair b, then G = Y_a^T Y_b and H = T_a G.  bt.store holds the
+// results; returns the block's width (up to OB2).
+template <class T>
+static int factor_block(const QrWork &w, int64_t J, BlockT &bt, hipStream_t s)
+{
+    bt.pwa = factor_pair<T>(w, J, bt.Ta(), s);
+    bt.pwb = 0;
+    const int64_t jb = J + bt.pwa;
+    const int pwb_max = (int)((w.n - jb) < OB ? (w.n - jb) : OB);
+    if (bt.pwa < OB || pwb_max <= 0)
+        return bt.pwa;
+    BlockT a{bt.store, bt.pwa, 0};
+    apply_block<T>(w, J, a, jb, pwb_max, s);
+    bt.pwb = factor_pair<T>(w, jb, bt.Tb(), s);
+    const int64_t rows = w.m - jb;
+    int64_t chunk, nch;
+    chunking(rows, 1, chunk, nch, w.max_chunks);
+    launch_wpart<T>(w, J, bt.pwa, jb, (int64_t)bt.pwb, 1, jb, chunk, 1, nch, 1, s);
+    hipLaunchKernelGGL(qr_gsum_kernel, dim3(OB * OB / 256), dim3(256), 0, s, w, bt.pwb, nch, bt.G(), OB);
+    hipLaunchKernelGGL(qr_hmat_kernel, dim3(OB), dim3(OB), 0, s, (const double *)bt.Ta(), OB, bt.pwa,
+                       (const double *)bt.G(), bt.pwb, bt.H());
+    return bt.pw();
 }
 
 template <class T>
 static void geqrf(const QrWork &w, hipStream_t s, const QrAsync *la)
 {
-    // small-scratch view for the narrow products (at most two blocks' columns):
-    // the next block's update and the work inside a block
-    QrWork wm = w;
-    wm.wpart = w.wpart_s;
-    wm.wp_ld = OB;
-    wm.W = w.W_s;
-    wm.W32 = w.W32_s;
-    wm.ldw = OB;
-    wm.max_chunks = MAX_CHUNKS_S;  // more row chunks keep the panel chain's GEMMs wide
+    // small-scratch views: wn for the products inside a block (at most OB rows
+    // and columns of P), wm for the main stream's update of the next block (OB2)
+    QrWork wn = w;
+    wn.wpart = w.wpart_s;
+    wn.wp_ld = OB;
+    wn.W = w.W_s;
+    wn.W32 = w.W32_s;
+    wn.ldw = OB;
+    wn.max_chunks = MAX_CHUNKS_S;  // more row chunks keep the panel chain's GEMMs wide
+    QrWork wm = wn;
+    wm.wp_ld = OB2;
+    wm.ldw = OB2;
+    wm.max_chunks = MAX_CHUNKS_S / 2;  // same buffer
     if (!la) {
-        for (int64_t J = 0; J < w.n; J += OB) {
-            const double *Tm;
-            int tld;
-            const int pw = factor_block<T>(wm, J, w.T, &Tm, &tld, s);
-            apply_block<T>(w, J, pw, Tm, tld, J + pw, w.ncols - (J + pw), s);
+        BlockT bt{w.T};
+        for (int64_t J = 0; J < w.n; J += bt.pw()) {
+            factor_block<T>(wn, J, bt, s);
+            apply_block<T>(w, J, bt, J + bt.pw(), w.ncols - (J + bt.pw()), s);
         }
         return;
     }
-    double *Tbuf[2] = {w.T, w.T2};
+    BlockT bt[2] = {BlockT{w.T}, BlockT{w.T2}};
     (void)hipEventRecord(la->fork, s);
     (void)hipStreamWaitEvent(la->side, la->fork, 0);
-    const double *Tm;
-    int tld;
-    int pw = factor_block<T>(wm, 0, Tbuf[0], &Tm, &tld, s);
+    factor_block<T>(wn, 0, bt[0], s);
     (void)hipEventRecord(la->t_ready, s);
     int64_t k = 0;
-    for (int64_t J = 0; J < w.n; J += pw, ++k) {
-        pw = (int)((w.n - J) < OB ? (w.n - J) : OB);
-        const int64_t cn = J + pw;                              // first column of block k+1
-        const int64_t nn = (w.n - cn) < OB ? (w.n - cn) : OB;   // its width (0 after the last block)
+    for (int64_t J = 0; J < w.n; ++k) {
+        const BlockT &cur = bt[k & 1];
+        const int64_t cn = J + cur.pw();                          // first column of block k+1
+        const int64_t nn = (w.n - cn) < OB2 ? (w.n - cn) : OB2;   // its width (0 after the last block)
         // side: block k's update of everything right of block k+1 (b included)
         (void)hipStreamWaitEvent(la->side, la->t_ready, 0);
-        apply_block<T>(w, J, pw, Tm, tld, cn + nn, w.ncols - (cn + nn), la->side);
+        apply_block<T>(w, J, cur, cn + nn, w.ncols - (cn + nn), la->side);
         (void)hipEventRecord(la->bulk[k & 1], la->side);
         if (nn <= 0)
             break;
-        // main: block k+1's columns need every earlier block's update first
+        // main: block k+1's columns need every earlier block's update first; its
+        // T buffer is the one block k-1's side update read
         if (k > 0)
             (void)hipStreamWaitEvent(s, la->bulk[(k - 1) & 1], 0);
-        apply_block<T>(wm, J, pw, Tm, tld, cn, nn, s);
-        factor_block<T>(wm, cn, Tbuf[(k + 1) & 1], &Tm, &tld, s);
+        apply_block<T>(wm, J, cur, cn, nn, s);
+        factor_block<T>(wn, cn, bt[(k + 1) & 1], s);
         (void)hipEventRecord(la->t_ready, s);
+        J = cn;
     }
     (void)hipEventRecord(la->join, la->side);
     (void)hipStreamWaitEvent(s, la->join, 0);

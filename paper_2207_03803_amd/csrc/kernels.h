@@ -40,16 +40,16 @@ struct QrWork {
     int64_t lda, m, n, ncols;
     int64_t ldw;      // leading dimension of W (ncols rounded up to 64)
     double *tau;      // [n]
-    double *wpart;    // [max_chunks * 2 QR_NB * wp_ld] split-K partials of Y^T C
+    double *wpart;    // [max_chunks * 4 QR_NB * wp_ld] split-K partials of Y^T C
     int64_t wp_ld;    // row stride of the partials (>= the widest column range updated)
-    double *T;        // [2 QR_NB * 2 QR_NB] compact-WY T of the current two-panel block (row-major)
+    double *T;        // [16 QR_NB^2] compact-WY data of the current four-panel block (T_a, T_b, G, H)
     double *T2;       // second T buffer (look-ahead: the side stream reads one while the next is formed)
-    double *wpart_s;  // [qr_max_chunks_s() * 2 QR_NB * 2 QR_NB] partials of the main stream's small updates
-    double *W_s;      // [2 QR_NB * 2 QR_NB] W of the main stream's small updates (ld 2 QR_NB)
+    double *wpart_s;  // [qr_max_chunks_s() * 4 QR_NB * 2 QR_NB] partials of the main stream's small updates
+    double *W_s;      // [4 QR_NB * 4 QR_NB] W of the main stream's small updates (ld 2 or 4 QR_NB)
     float *W32_s;     // FP32 version
     double *Tin;      // [2 * QR_NB * QR_NB] T of the block's two panels (row-major, ld QR_NB)
     double *U;        // [QR_NB * QR_NB] LU factor of (Q - S) of the current panel
-    double *W;        // [2 QR_NB * ldw] T^T Y^T C, row-major by block column
+    double *W;        // [4 QR_NB * ldw] T^T Y^T C, row-major by block column
     float *W32;       // same for the FP32 factorisation
     double *ts_tiles; // TsqrTree::tiles_doubles
     double *ts_X;     // TsqrTree::tiles_doubles
