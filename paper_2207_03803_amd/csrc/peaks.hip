@@ -1,10 +1,12 @@
 // Microbenchmarks for the roofline denominators on this GPU: FP64 MFMA
-// (16x16x4 and 4x4x4), FP64 VALU FMA, and a device-to-device streaming copy.
+// (16x16x4 and 4x4x4), INT8 MFMA (16x16x64), FP64 VALU FMA, and a
+// device-to-device streaming copy.
 // Every kernel keeps its results live and writes one value per thread.
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef int v4i __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void mfma16_kernel(double *out, int iters, double a0)
 {
@@ -37,6 +39,23 @@ __global__ __launch_bounds__(256) void mfma4_kernel(double *out, int iters, doub
     double s = 0.0;
     for (int i = 0; i < 16; ++i)
         s += acc[i];
+    out[blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void mfma_i8_kernel(int *out, int iters, int a0)
+{
+    v4i acc[16];
+    for (int i = 0; i < 16; ++i)
+        acc[i] = v4i{0, 0, 0, 0};
+    const v4i a = v4i{a0 + (int)threadIdx.x, a0, a0 ^ 0x01010101, a0}, b = v4i{a0, a0 - (int)threadIdx.x, a0, a0 + 3};
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            acc[i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[i], 0, 0, 0);
+    }
+    int s = 0;
+    for (int i = 0; i < 16; ++i)
+        s += acc[i][0] + acc[i][1] + acc[i][2] + acc[i][3];
     out[blockIdx.x * 256 + threadIdx.x] = s;
 }
 
@@ -104,6 +123,18 @@ int main()
         // four 4x4x4 products per instruction: 512 flops
         printf("v_mfma_f64_4x4x4_4b_f64, %d wave(s)/SIMD: %.1f TFLOP/s\n", wps,
                (double)blocks * 4 * iters * 16 * 512.0 / ms / 1e9);
+    }
+    for (int wps = 1; wps <= 2; ++wps) {
+        const int blocks = cus * wps, iters = 2000;
+        hipLaunchKernelGGL(mfma_i8_kernel, dim3(blocks), dim3(256), 0, 0, (int *)out, 10, 0x01020304);
+        CHECK(hipEventRecord(e0));
+        hipLaunchKernelGGL(mfma_i8_kernel, dim3(blocks), dim3(256), 0, 0, (int *)out, iters, 0x01020304);
+        CHECK(hipEventRecord(e1));
+        CHECK(hipEventSynchronize(e1));
+        CHECK(hipEventElapsedTime(&ms, e0, e1));
+        // 16 x 16 x 64 multiply-adds per instruction: 32768 operations
+        printf("v_mfma_i32_16x16x64_i8, %d wave(s)/SIMD: %.1f TOP/s\n", wps,
+               (double)blocks * 4 * iters * 16 * 32768.0 / ms / 1e9);
     }
     for (int wps = 1; wps <= 8; wps *= 2) {
         const int blocks = cus * wps, iters = 10000;

@@ -145,6 +145,40 @@ def test_predict_parity(orc_m):
     assert rel(out.cpu().numpy(), ref.Knm @ c) <= 1e-13
 
 
+def test_predict_at_the_serving_shape(orc_m):
+    """A served model's shape (d=400, zeta=4, M=4,000) on a predict-only handle
+    (gap_set_model), 4,096 configurations of 8..64 atoms: 256 sampled
+    configurations against the oracle one by one.  Weights of both signs, so the
+    error is measured against the sum of absolute terms (the oracle's predict
+    with |c|; descriptors are non-negative, so every kernel value is)."""
+    import torch
+
+    from paper_2207_03803_amd import gap
+
+    d, zeta, M, n = 400, 4, 4000, 4096
+    q = synth.make_fit_inputs(n_configs=n, atoms=(8, 64), d=d, M=M, seed=31)
+    c = np.random.default_rng(32).standard_normal(M)
+    log(f"predict at serving shape: {n} configs ({q.n_atoms} atoms), d={d}, M={M}, zeta={zeta}")
+    h = gap.Handle(gap.params(d, zeta))
+    XM = to_dev(q.XM)
+    h.set_model(XM)
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.predict(to_dev(q.X), to_dev(q.offsets), to_dev(c), out)
+    status, _ = h.sync()
+    assert status == gap.GAP_OK
+    got = out.cpu().numpy()
+    h.close()
+    pick = np.sort(np.random.default_rng(33).choice(n, 256, replace=False))
+    rows = np.concatenate([np.arange(q.offsets[a], q.offsets[a + 1]) for a in pick])
+    offs = np.concatenate([[0], np.cumsum(np.diff(q.offsets)[pick])]).astype(np.int64)
+    expect = orc_m.predict(q.X[rows], offs, q.XM, c, zeta)
+    scale = orc_m.predict(q.X[rows], offs, q.XM, np.abs(c), zeta)
+    e = np.max(np.abs(got[pick] - expect) / scale)
+    log(f"  max |error| / sum of |terms| {e:.2e}")
+    assert e <= 1e-14 * np.sqrt(M)
+    assert np.all(np.isfinite(got))
+
+
 def test_not_positive_definite_is_reported(orc_m):
     inp, y, ref = _case(orc_m, 60, (8, 16), 16, 40, 2, seed=7)
     XM = np.vstack([inp.XM[:39], inp.XM[:1]])  # duplicated sparse point, no jitter
