@@ -5,15 +5,17 @@ M = 1e4 sparse points, zeta = 4, FP64, beside the three forms around it:
   mixed  the same fit with an FP32 Householder QR and FP64 refinement of c
   bf16   mixed, with the factored K_NM block from BF16 descriptor dot products
   fp16   mixed, with FP16 descriptor dot products
-  sweep  64 uneven fits of a hyperparameter sweep replayed as one HIP graph
-         (FP32 QR + FP64 refinement), against the same fits run one after
-         another in plain FP64
+  int8   the FP64 fit with its K_NM dot products emulated on INT8 MFMA
+         (Ozaki scheme: 7 slices per value, 28 exact slice products)
+  sweep  64 uneven fits of a hyperparameter sweep, one HIP graph per fit
+         replayed on several streams (FP32 QR + FP64 refinement), against the
+         same fits run one after another in plain FP64
   serve  Poisson fit/predict requests through the continuous-batching loop:
          p50/p99 latency and fits/s, mixed precision and plain FP64
 
 Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms mixed,bf16,fp16,sweep,serve | none]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms mixed,bf16,fp16,int8,sweep,serve | none]
                   [--workload realistic_fp64|tiny_fp64] [--no-cpu-baseline]
 
 A step is one whole fit on inputs already resident in HBM; `value` is the FP64
@@ -37,6 +39,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_MFMA = 78.6e12   # MI355X dense FP64 matrix peak, FLOP/s
 PEAK_FP32_MFMA = 157.3e12  # MI355X dense FP32 matrix peak, FLOP/s
 PEAK_BF16_MFMA = 2.5e15    # MI355X dense BF16 / FP16 matrix peak, FLOP/s
+PEAK_INT8_MFMA = 5.0e15    # MI355X dense INT8 matrix peak, OP/s
 PEAK_HBM = 8.0e12          # MI355X HBM3E, B/s
 GOLDEN = os.path.join(ROOT, "tests", "golden", "realistic_fp64_seed0.npz")
 
@@ -199,7 +202,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="realistic_fp64")
-    ap.add_argument("--forms", default="mixed,bf16,fp16,sweep,serve",
+    ap.add_argument("--forms", default="mixed,bf16,fp16,int8,sweep,serve",
                     help="comma-separated forms to measure beside the FP64 fit, or none")
     ap.add_argument("--inputs", choices=("host", "device"), default="host",
                     help="host: numpy descriptors (the arrays the oracle's full-size reference fit used); "
@@ -260,16 +263,16 @@ def main():
         f"{'yes' if ref is not None else 'no'})")
     f = fit_flops(n_atoms, N, M, d)
 
-    def run_fit(precision, steps, warmup, y=None):
+    def run_fit(precision, steps, warmup, y=None, flags=0):
         """Time `steps` whole fits (build + solve) after `warmup` untimed ones, on a
         stream of the fit's own (beside it the QR look-ahead keeps CUs free for the
         panel chain)."""
         with torch.cuda.stream(torch.cuda.Stream()):
-            return _run_fit(precision, steps, warmup, y)
+            return _run_fit(precision, steps, warmup, y, flags)
 
-    def _run_fit(precision, steps, warmup, y=None):
+    def _run_fit(precision, steps, warmup, y=None, flags=0):
         iters = 30 if precision in (gap.GAP_FP64, gap.GAP_MIXED_FP32) else 200
-        p = gap.params(d, zeta, w["sigma_w"], w["jitter"], precision=precision, flags=gap.GAP_FLAG_TIMING,
+        p = gap.params(d, zeta, w["sigma_w"], w["jitter"], precision=precision, flags=gap.GAP_FLAG_TIMING | flags,
                        max_refine_iters=iters, refine_tol=1e-12)
         h = gap.Handle(p)
         # one fit on a stream of its own and nothing on the legacy stream meanwhile:
@@ -295,7 +298,7 @@ def main():
                     stage_sum[k] = stage_sum.get(k, 0.0) + v
 
         tag = {gap.GAP_FP64: "fp64", gap.GAP_MIXED_FP32: "mixed", gap.GAP_MIXED_BF16: "mixed_bf16",
-               gap.GAP_MIXED_FP16: "mixed_fp16"}[precision]
+               gap.GAP_MIXED_FP16: "mixed_fp16"}[precision] + ("_int8" if flags & gap.GAP_FLAG_KNM_INT8 else "")
         for i in range(warmup):
             step(False)
             log(f"[bench] {tag} warmup {i + 1}/{warmup} done")
@@ -389,8 +392,26 @@ def main():
                                   "peak": PEAK_BF16_MFMA / 1e12})
         log(f"[bench] {key}: {mx['ms']:.1f} ms per fit ({gap.status_string(mx['status'])}, "
             f"{mx['info'].refine_iters} refinement steps), c rel err vs FP64 path {err:.2e}")
+    if "int8" in forms:
+        # the FP64 fit with its K_NM from INT8 slice products (Ozaki scheme)
+        oz = run_fit(gap.GAP_FP64, args.steps, args.warmup, y=fp["y"], flags=gap.GAP_FLAG_KNM_INT8)
+        t_oz = oz["stages_ms"]["knm"] / 1e3
+        dpad = (d + 63) // 64 * 64
+        int8_ops = 28 * 2.0 * n_atoms * M * dpad  # 28 slice products over the padded rows
+        extra["fp64_int8"] = {
+            "s_per_fit": oz["ms"] / 1e3, "median_ms": oz["ms_median"], "min_ms": oz["ms_min"],
+            "speedup_vs_fp64": ms_per_step / oz["ms"], "stages_ms": oz["stages_ms"],
+            "knm_int8_tops": int8_ops / t_oz / 1e12, "knm_fp64_equivalent_tflops": f["knm"] / t_oz / 1e12,
+            "c_rel_err_vs_fp64_path": float((oz["c"] - fp["c"]).norm() / fp["c"].norm()), **vs_oracle(oz),
+            "note": "FP64 fit whose K_NM dot products come from 7 signed 8-bit slices per value, 28 slice "
+                    "products on v_mfma_i32_16x16x64_i8 summed exactly in INT32 and combined in FP64"}
+        rooflines.append({"stage": "knm_int8", "kernel": "knm_oz_kernel (+ slicing)", "bound": "mfma",
+                          "dtype": "i8", "achieved": int8_ops / t_oz / 1e12, "peak": PEAK_INT8_MFMA / 1e12,
+                          "unit": "TOP/s"})
+        log(f"[bench] fp64_int8: {oz['ms']:.1f} ms per fit, K_NM {1e3 * t_oz:.1f} ms")
+        del oz
     for r in rooflines:
-        r["unit"] = "TFLOP/s"
+        r.setdefault("unit", "TFLOP/s")
         r["frac"] = r["achieved"] / r["peak"]
     del fp
     torch.cuda.empty_cache()

@@ -99,6 +99,16 @@ typedef struct gap_params {
 /* Estimate the relative error of c (gap_solve_info.est_err): 16 steps each of
  * power and inverse iteration on R for kappa_2(A), about 32 triangular solves. */
 #define GAP_FLAG_ERROR_ESTIMATE 2u
+/* Build the FP64 K_NM from descriptor dot products emulated on INT8 MFMA
+ * (Ozaki scheme; the K_MN definition of Sec. Theory): every descriptor and
+ * sparse row is scaled by a power of two and rounded to a 54-bit integer, split
+ * into 7 signed 8-bit slices, and the 28 leading slice products are summed
+ * exactly in INT32 and combined in FP64 (the power, segment sums and row scale
+ * in FP64 as in the FP64 build).  The dot products carry about FP64's rounding
+ * error.  Applies to every precision (the FP64 A of the mixed forms included);
+ * K_MM keeps the FP64 build.  The workspace grows by 7 bytes per descriptor
+ * entry (rows padded to a multiple of 64) plus 4 bytes per row. */
+#define GAP_FLAG_KNM_INT8 4u
 
 typedef struct gap_handle_s *gap_handle;
 

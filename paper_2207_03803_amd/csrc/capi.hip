@@ -33,6 +33,10 @@ struct Layout {
     bool lp = false;
     int dp = 0;
     size_t off_Xlp = 0, off_XMlp = 0;
+    // INT8-emulated FP64 K_NM (GAP_FLAG_KNM_INT8) only: descriptor slices and row exponents
+    bool oz = false;
+    int dpo = 0;
+    size_t off_Xoz = 0, off_XMoz = 0, off_xe = 0, off_xme = 0;
 };
 
 bool is_mixed(int32_t precision) { return precision != GAP_FP64; }
@@ -40,7 +44,7 @@ bool is_lp(int32_t precision) { return precision == GAP_MIXED_BF16 || precision 
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, int32_t precision, int d)
+Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, int32_t precision, int d, uint32_t flags)
 {
     Layout L;
     const bool mixed = is_mixed(precision);
@@ -106,6 +110,15 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, int32_t precision, int
         L.dp = knm_lp_dpad(d);
         L.off_Xlp = take(sizeof(uint16_t) * (size_t)n_atoms * (size_t)L.dp);
         L.off_XMlp = take(sizeof(uint16_t) * (size_t)M * (size_t)L.dp);
+    }
+    if (flags & GAP_FLAG_KNM_INT8) {
+        L.oz = true;
+        L.dpo = knm_oz_dpad(d);
+        const size_t sl = (size_t)knm_oz_slices();
+        L.off_Xoz = take(sl * (size_t)n_atoms * (size_t)L.dpo);
+        L.off_XMoz = take(sl * (size_t)M * (size_t)L.dpo);
+        L.off_xe = take(sizeof(int32_t) * (size_t)n_atoms);
+        L.off_xme = take(sizeof(int32_t) * (size_t)M);
     }
     L.total = o;
     return L;
@@ -251,7 +264,7 @@ size_t gap_workspace_bytes(const gap_params *p, int64_t n_configs, int64_t n_ato
 {
     if (!valid_params(p) || n_configs < 1 || n_atoms < 0 || M < 1)
         return 0;
-    return make_layout(n_configs, n_atoms, M, p->precision, p->d).total;
+    return make_layout(n_configs, n_atoms, M, p->precision, p->d, p->flags).total;
 }
 
 // Release a handle's events and side stream (those created so far) and the handle.
@@ -374,7 +387,7 @@ static gap_status build_prepare(gap_handle h, const double *x_atoms, int64_t n_a
     if (!x_atoms || !config_offsets || !x_sparse || !sigma || n_atoms < 1 || n_configs < 1 || M < 1 ||
         n_configs > INT32_MAX - 1)
         return GAP_EINVAL;
-    const Layout L = make_layout(n_configs, n_atoms, M, h->p.precision, h->p.d);
+    const Layout L = make_layout(n_configs, n_atoms, M, h->p.precision, h->p.d, h->p.flags);
     if (L.total > h->ws_bytes)
         return GAP_ENOMEM;
     h->L = L;
@@ -436,6 +449,37 @@ static gap_status build_setup(gap_handle h, hipStream_t s, KnmArgs *a)
     a->status = h->status();
     a->bn = h->tuning.knm_bn;
     return GAP_OK;
+}
+
+// The FP64 K_NM from INT8 slice products (GAP_FLAG_KNM_INT8), after build_setup's plan.
+static gap_status launch_knm_int8(gap_handle h, hipStream_t s)
+{
+    const Layout &L = h->L;
+    const gap_params &p = h->p;
+    int8_t *Xoz = h->at<int8_t>(L.off_Xoz), *XMoz = h->at<int8_t>(L.off_XMoz);
+    int32_t *xe = h->at<int32_t>(L.off_xe), *xme = h->at<int32_t>(L.off_xme);
+    GAP_TRY(dev(launch_oz_split(h->x_atoms, L.n_atoms, p.d, Xoz, xe, s)));
+    GAP_TRY(dev(launch_oz_split(h->x_sparse, L.M, p.d, XMoz, xme, s)));
+    const KnmPlan kp = plan_of(h);
+    KnmOzLaunch l{};
+    l.X = Xoz;
+    l.XM = XMoz;
+    l.xe = xe;
+    l.xme = xme;
+    l.n_atoms = L.n_atoms;
+    l.d = p.d;
+    l.offsets = h->offsets;
+    l.tile_start = kp.tile_start;
+    l.cfg_list = kp.cfg_list;
+    l.n_tiles_dev = kp.n_tiles;
+    l.max_tiles = L.max_tiles;
+    l.M = L.M;
+    l.zeta = p.zeta;
+    l.sw2 = p.sigma_w * p.sigma_w;
+    l.sigma = h->sigma;
+    l.out = h->A();
+    l.ldo = L.lda;
+    return dev(launch_knm_oz(l, s));
 }
 
 // On the handle's stream, after the K_NM: the low-precision K_NM (mixed BF16 /
@@ -506,7 +550,10 @@ gap_status gap_build_knm(gap_handle h, const double *x_atoms, int64_t n_atoms, c
     KnmArgs a;
     GAP_TRY(build_setup(h, h->stream, &a));
     h->mark(0, false);
-    GAP_TRY(dev(launch_knm(a, h->L.max_tiles, h->stream)));
+    if (h->L.oz)
+        GAP_TRY(launch_knm_int8(h, h->stream));
+    else
+        GAP_TRY(dev(launch_knm(a, h->L.max_tiles, h->stream)));
     h->mark(0, true);
     return build_rest(h);
 }
@@ -524,16 +571,25 @@ gap_status gap_build_knm_batch(gap_handle *handles, int32_t n, const gap_batch_f
             if (handles[j] == handles[i])
                 return GAP_EINVAL;
     }
+    // FP64-MFMA fits in groups of up to KNM_GROUP per launch; INT8-emulated ones launch alone
     KnmArgs args[KNM_GROUP];
     int64_t max_tiles[KNM_GROUP];
-    for (int32_t i0 = 0; i0 < n; i0 += KNM_GROUP) {
-        const int g = (n - i0) < KNM_GROUP ? (n - i0) : KNM_GROUP;
-        for (int i = 0; i < g; ++i) {
-            GAP_TRY(build_setup(handles[i0 + i], s, &args[i]));
-            max_tiles[i] = handles[i0 + i]->L.max_tiles;
+    int g = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        gap_handle hi = handles[i];
+        GAP_TRY(build_setup(hi, s, &args[g]));
+        if (hi->L.oz) {
+            GAP_TRY(launch_knm_int8(hi, s));
+            continue;
         }
-        GAP_TRY(dev(launch_knm_group(args, max_tiles, g, s)));
+        max_tiles[g] = hi->L.max_tiles;
+        if (++g == KNM_GROUP) {
+            GAP_TRY(dev(launch_knm_group(args, max_tiles, g, s)));
+            g = 0;
+        }
     }
+    if (g > 0)
+        GAP_TRY(dev(launch_knm_group(args, max_tiles, g, s)));
     for (int32_t i = 0; i < n; ++i) {
         handles[i]->timed[0] = false;
         handles[i]->state = ST_KNM;
@@ -857,7 +913,7 @@ gap_status gap_fit_static(const gap_params *p, void *stream, const double *x_ato
     if (!x_atoms || !config_offsets || !x_sparse || !sigma || !y || !c_out || n_atoms < 1 || n_configs < 1 ||
         M < 1 || n_configs > INT32_MAX - 1)
         return GAP_EINVAL;
-    const size_t need = make_layout(n_configs, n_atoms, M, p->precision, p->d).total;
+    const size_t need = make_layout(n_configs, n_atoms, M, p->precision, p->d, p->flags).total;
     if (need > GAP_STATIC_SCRATCH_BYTES)
         return GAP_ENOMEM;
     gap_handle_s h;  // on the stack: no timing events, no look-ahead stream

@@ -76,6 +76,29 @@ struct KnmLpLaunch {
 };
 hipError_t launch_knm_lp(const KnmLpLaunch &l, hipStream_t s);
 
+// ------------------------------------------ FP64-accurate K_NM on INT8 MFMA
+// Descriptor rows split into knm_oz_slices() signed 8-bit slices of
+// knm_oz_dpad(d) bytes per row (slice-major: slice t of row r at
+// out + (t * rows + r) * dpad) and one exponent per row.
+int knm_oz_dpad(int d);
+int knm_oz_slices();
+hipError_t launch_oz_split(const double *x, int64_t rows, int d, int8_t *out, int32_t *ex, hipStream_t s);
+struct KnmOzLaunch {
+    const int8_t *X, *XM;       // slices of the descriptors [n_atoms rows] and sparse points [M rows]
+    const int32_t *xe, *xme;    // their row exponents
+    int64_t n_atoms;
+    int d;
+    const int64_t *offsets;     // CSR offsets and the tile plan of the FP64 build
+    const int32_t *tile_start, *cfg_list, *n_tiles_dev;
+    int64_t max_tiles;
+    int64_t M;
+    int zeta;
+    double sw2;
+    const double *sigma;        // [N]: rows divided by sigma
+    double *out;                // FP64 column-major: out[col * ldo + configuration]
+    int64_t ldo;
+};
+hipError_t launch_knm_oz(const KnmOzLaunch &l, hipStream_t s);
 // --------------------------------------------------------------------- predict
 // Configurations whose offsets are not a range inside [0, n_atoms) (or offsets[0] != 0,
 // offsets[N] != n_atoms) get NaN energies and DST_EINVAL in *status (when non-null);

@@ -17,6 +17,7 @@ GAP_OK, GAP_EINVAL, GAP_ENOMEM, GAP_ENOTPD, GAP_ENONFINITE, GAP_ENOCONV, GAP_EDE
 GAP_FP64, GAP_MIXED_FP32, GAP_MIXED_BF16, GAP_MIXED_FP16 = 0, 1, 2, 3
 GAP_FLAG_TIMING = 1
 GAP_FLAG_ERROR_ESTIMATE = 2
+GAP_FLAG_KNM_INT8 = 4
 
 # Every entry point include/gap.h declares.
 EXPORTS = ["gap_create", "gap_workspace_bytes", "gap_bind_workspace", "gap_build_knm", "gap_solve",

@@ -22,13 +22,13 @@ class GpuFit:
     """Build + solve one fit on the GPU; keeps the handle and the A copy."""
 
     def __init__(self, X, offsets, XM, sigma, y, zeta, sigma_w=1.0, jitter=1e-8, keep_A=False,
-                 timing=False, precision=0, max_refine_iters=20, refine_tol=1e-12):
+                 timing=False, precision=0, max_refine_iters=20, refine_tol=1e-12, flags=0):
         import torch
 
         from paper_2207_03803_amd import gap
 
         self.gap = gap
-        flags = gap.GAP_FLAG_TIMING if timing else 0
+        flags = flags | (gap.GAP_FLAG_TIMING if timing else 0)
         self.X = X if isinstance(X, torch.Tensor) else to_dev(X)
         self.XM = XM if isinstance(XM, torch.Tensor) else to_dev(XM)
         self.offsets = to_dev(np.asarray(offsets, dtype=np.int64))

@@ -191,3 +191,40 @@ def test_mixed_forms_match_the_oracle_at_full_size(full, ref, form):
         assert info.grad_rel <= 1e-12
     else:
         assert s == gap.GAP_ENOCONV
+
+
+def test_int8_knm_fit_at_full_size(full, ref):
+    """The FP64 fit with its K_NM from INT8 slice products (GAP_FLAG_KNM_INT8) at the
+    realistic size: every K_NM entry of 500 sampled columns within 1e-13 of the FP64
+    build's, sampled entries against the oracle, c within 1e-10 of the oracle's."""
+    import torch
+
+    from paper_2207_03803_amd import gap
+
+    f = full
+    w, N, M = f["w"], f["N"], f["M"]
+    with torch.cuda.stream(torch.cuda.Stream()):
+        h = gap.Handle(gap.params(w["d"], w["zeta"], w["sigma_w"], w["jitter"], flags=gap.GAP_FLAG_KNM_INT8))
+        h.set_tuning(qr_free_cus=32)
+        h.alloc_workspace(N, f["inp"].n_atoms, M)
+        h.build_knm(f["X"], f["offsets"], f["XM"], f["sigma"])
+        cols = np.sort(np.random.default_rng(3).choice(M, 500, replace=False))
+        Av, _ = h.A_view()
+        got = Av[torch.from_numpy(cols).cuda(), :N].cpu().numpy()
+        c = torch.empty(M, dtype=torch.float64, device="cuda")
+        info = h.solve(f["y"], c)
+    h.close()
+    fp64 = f["A"][cols, :N]
+    dk = np.max(np.abs(got - fp64) / np.abs(fp64))
+    inp = f["inp"]
+    rng = np.random.default_rng(4)
+    cfgs = np.sort(rng.choice(N, 32, replace=False))
+    rows = np.concatenate([np.arange(inp.offsets[a], inp.offsets[a + 1]) for a in cfgs])
+    offs = np.concatenate([[0], np.cumsum(np.diff(inp.offsets)[cfgs])]).astype(np.int64)
+    K = oracle.Oracle().knm(inp.X[rows], offs, inp.XM[cols[:32]], w["zeta"], w["sigma_w"])
+    ko = np.max(np.abs(got[:32][:, cfgs].T - K / inp.sigma[cfgs][:, None]) / np.abs(K / inp.sigma[cfgs][:, None]))
+    err = rel(c.cpu().numpy(), ref["c"])
+    log(f"  INT8 K_NM: vs FP64 build max rel diff {dk:.2e}, vs oracle {ko:.2e}; c rel err vs oracle {err:.2e}")
+    assert info.device_status == gap.GAP_OK
+    assert dk <= 1e-13 and ko <= 1e-13
+    assert err <= 1e-10
