@@ -49,9 +49,10 @@ def _bind(lib):
     lib.oracle_fit.argtypes = [P, P, I64, P, I64, I64, ctypes.c_int, ctypes.c_double,
                                ctypes.c_double, P, P, P, P, P, P, P, P, P, P]
     lib.oracle_singular_extremes.argtypes = [P, I64, I64, ctypes.c_int, ctypes.c_double, P, P, P]
+    lib.oracle_cur_leverage.argtypes = [P, I64, I64, P]
     for name in ("oracle_knm", "oracle_kmm", "oracle_cholesky", "oracle_stack",
                  "oracle_householder_qr", "oracle_back_substitution", "oracle_predict",
-                 "oracle_gradient", "oracle_fit", "oracle_singular_extremes"):
+                 "oracle_gradient", "oracle_fit", "oracle_singular_extremes", "oracle_cur_leverage"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -155,6 +156,32 @@ class Oracle:
                                                self._p(smin), self._p(its))
         assert rc == ORACLE_OK, rc
         return float(smax[0]), float(smin[0]), (int(its[0]), int(its[1]))
+
+    def cur_leverage(self, X):
+        """Leverage of every row of X over its row space (CUR sparse-point selection,
+        Sec. Implementation): lev[i] = x_i^T (X^T X)^-1 x_i.  Raises on a rank-deficient X."""
+        X = self._f64(X)
+        lev = np.empty(X.shape[0])
+        rc = self.lib.oracle_cur_leverage(self._p(X), X.shape[0], X.shape[1], self._p(lev))
+        if rc != ORACLE_OK:
+            raise np.linalg.LinAlgError(f"oracle_cur_leverage: status {rc}")
+        return lev
+
+    def cur_select(self, X, M, draws=None, lev=None):
+        """The M sparse points CUR selection takes from the rows of X, ascending.
+
+        Without draws: the M rows of largest leverage.  With draws (one Exp(1)
+        variate per row, drawn by the caller): M rows sampled without replacement
+        with probability proportional to the leverage, by the exponential-key
+        method of Efraimidis & Spirakis (the M smallest draws[i] / lev[i]).  The
+        key is draws[i] / lev[i] (1 / lev[i] without draws); equal keys are taken
+        in row order.  Returns (indices, keys, lev)."""
+        if lev is None:
+            lev = self.cur_leverage(X)
+        with np.errstate(divide="ignore"):
+            keys = (np.asarray(draws, dtype=np.float64) if draws is not None else np.ones(len(lev))) / lev
+        order = np.argsort(keys, kind="stable")  # library sort; ties keep row order
+        return np.sort(order[:M]), keys, lev
 
     def predict(self, X, offsets, XM, c, zeta, sigma_w=1.0):
         X, XM, c, offsets = self._f64(X), self._f64(XM), self._f64(c), self._i64(offsets)

@@ -8,8 +8,9 @@
  * It computes, slowly and in the order the paper states, what the GPU path
  * computes: the kernel matrices, the Cholesky factor of K_MM, the stacked
  * least-squares problem, an unblocked Householder QR with Q^T b carried along,
- * back-substitution for the weights, the loss and its gradient, and the
- * prediction of total energies.  Every floating-point sum runs in a fixed
+ * back-substitution for the weights, the loss and its gradient, the
+ * prediction of total energies, and the row leverages behind CUR sparse-point
+ * selection.  Every floating-point sum runs in a fixed
  * sequential order, so the result does not depend on the thread count.
  *
  * Matrices are dense, row-major: element (i, j) of an r x c matrix is at
@@ -526,5 +527,61 @@ done:
     free(A);
     free(b);
     free(tau);
+    return rc;
+}
+
+/*
+ * Statistical leverage of every descriptor row for CUR sparse-point selection
+ * (Sec. Implementation: sparse points chosen by CUR-based methods, after
+ * Mahoney & Drineas 2009).  With X the n x d matrix of descriptor rows, the
+ * leverage of row i over the row space of X is the i-th diagonal element of
+ * the hat matrix X (X^T X)^-1 X^T:
+ *   lev[i] = x_i^T (X^T X)^-1 x_i = ||z_i||^2,  L z_i = x_i,  X^T X = L L^T.
+ * The Gram matrix is summed over the rows in order, factored by the Cholesky
+ * above, and z_i found by forward substitution.  Returns ORACLE_ENOTPD when
+ * X^T X is not positive definite (X of rank below d).
+ */
+int oracle_cur_leverage(const double *X, int64_t n, int64_t d, double *lev)
+{
+    if (n < 1 || d < 1)
+        return ORACLE_EINVAL;
+    double *G = (double *)calloc((size_t)(d * d), sizeof(double));
+    double *L = (double *)malloc(sizeof(double) * (size_t)(d * d));
+    if (!G || !L) {
+        free(G);
+        free(L);
+        return ORACLE_ENOMEM;
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t p = 0; p < d; ++p)
+        for (int64_t q = 0; q <= p; ++q) {
+            double s = 0.0;
+            for (int64_t r = 0; r < n; ++r)
+                s += X[r * d + p] * X[r * d + q];
+            G[p * d + q] = s;
+            G[q * d + p] = s;
+        }
+    int rc = oracle_cholesky(G, d, L, NULL);
+    if (rc == ORACLE_OK) {
+#pragma omp parallel
+        {
+            double *z = (double *)malloc(sizeof(double) * (size_t)d);
+#pragma omp for schedule(static)
+            for (int64_t i = 0; i < n; ++i) {
+                double s2 = 0.0;
+                for (int64_t p = 0; p < d; ++p) {
+                    double t = X[i * d + p];
+                    for (int64_t k = 0; k < p; ++k)
+                        t -= L[p * d + k] * z[k];
+                    z[p] = t / L[p * d + p];
+                    s2 += z[p] * z[p];
+                }
+                lev[i] = s2;
+            }
+            free(z);
+        }
+    }
+    free(G);
+    free(L);
     return rc;
 }
