@@ -7,6 +7,8 @@ M = 1e4 sparse points, zeta = 4, FP64, beside the three forms around it:
   fp16   mixed, with FP16 descriptor dot products
   int8   the FP64 fit with its K_NM dot products emulated on INT8 MFMA
          (Ozaki scheme: 7 slices per value, 28 exact slice products)
+  cur    CUR sparse-point selection of M rows from the descriptor rows
+         (leverages on FP64 MFMA, sampling by exponential keys)
   sweep  64 uneven fits of a hyperparameter sweep, one HIP graph per fit
          replayed on several streams (FP32 QR + FP64 refinement), against the
          same fits run one after another in plain FP64
@@ -15,7 +17,7 @@ M = 1e4 sparse points, zeta = 4, FP64, beside the three forms around it:
 
 Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms mixed,bf16,fp16,int8,sweep,serve | none]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms mixed,bf16,fp16,int8,cur,sweep,serve | none]
                   [--workload realistic_fp64|tiny_fp64] [--no-cpu-baseline]
 
 A step is one whole fit on inputs already resident in HBM; `value` is the FP64
@@ -73,6 +75,43 @@ def load_reference(workload, seed):
     ref = {k: z[k] for k in z.files if k != "meta"}
     ref["meta"] = json.loads(str(z["meta"]))
     return ref
+
+
+def bench_cur(args, X, n, d, M, host_inputs):
+    """CUR sparse-point selection over the workload's descriptor rows: M rows
+    sampled in proportion to their leverage (gap_cur_select), timed with HIP events
+    on the current stream over --steps calls after --warmup; with the host-drawn
+    inputs the selection is compared with the oracle's
+    (tests/golden/cur_realistic_seed0.npz)."""
+    import numpy as np
+    import torch
+
+    from paper_2207_03803_amd import gap, synth
+
+    draws = torch.from_numpy(synth.cur_draws(n, args.seed)).cuda()
+    ws = torch.empty(gap.cur_workspace_bytes(n, d), dtype=torch.uint8, device="cuda")
+    for _ in range(args.warmup):
+        gap.cur_select(X, M, draws=draws, workspace=ws)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        idx, lev = gap.cur_select(X, M, draws=draws, leverage=True, workspace=ws, wait=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    flops = 2.0 * n * d * d  # Gram (symmetric) and the triangular projection: n d^2 each
+    out = {"ms": ms, "n_rows": n, "d": d, "M": M, "tflops": flops / (ms / 1e3) / 1e12,
+           "sum_leverage": float(lev.sum().item()),
+           "note": "leverages x_i^T (X^T X)^-1 x_i (Gram and projection on FP64 MFMA, Cholesky, triangular "
+                   "inverse), M rows sampled in proportion to leverage by exponential keys (radix select)"}
+    golden = os.path.join(ROOT, "tests", "golden", "cur_realistic_seed0.npz")
+    if host_inputs and args.seed == 0 and os.path.exists(golden):
+        z = np.load(golden, allow_pickle=False)
+        out["rows_differing_from_oracle_selection"] = int(len(np.setxor1d(idx.cpu().numpy(), z["sampled_idx"])))
+        out["oracle_seconds"] = json.loads(str(z["meta"]))["leverage_s"]
+    log(f"[bench] cur: {ms:.2f} ms per selection ({out['tflops']:.1f} TFLOP/s)")
+    return out
 
 
 def fit_flops(n_atoms, N, M, d):
@@ -202,7 +241,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="realistic_fp64")
-    ap.add_argument("--forms", default="mixed,bf16,fp16,int8,sweep,serve",
+    ap.add_argument("--forms", default="mixed,bf16,fp16,int8,cur,sweep,serve",
                     help="comma-separated forms to measure beside the FP64 fit, or none")
     ap.add_argument("--inputs", choices=("host", "device"), default="host",
                     help="host: numpy descriptors (the arrays the oracle's full-size reference fit used); "
@@ -415,6 +454,12 @@ def main():
         r["frac"] = r["achieved"] / r["peak"]
     del fp
     torch.cuda.empty_cache()
+    if "cur" in forms:
+        extra["cur"] = bench_cur(args, X, n_atoms, d, M, ref is not None)
+        r = extra["cur"]
+        rooflines.append({"stage": "cur", "kernel": "cur_gram_kernel + cur_proj_kernel (+ selection)",
+                          "bound": "mfma", "dtype": "f64", "achieved": r["tflops"], "peak": PEAK_FP64_MFMA / 1e12,
+                          "unit": "TFLOP/s", "frac": r["tflops"] / (PEAK_FP64_MFMA / 1e12)})
     if "sweep" in forms or "serve" in forms:
         from paper_2207_03803_amd import serve, sweep
 

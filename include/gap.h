@@ -330,6 +330,36 @@ gap_status gap_fit_static(const gap_params *p, void *stream, const double *x_ato
 /* GAP_STATIC_SCRATCH_BYTES (for callers that load the library dynamically). */
 size_t gap_static_scratch_bytes(void);
 
+/*
+ * CUR sparse-point selection (Sec. Implementation: the sparse points are chosen
+ * from the descriptor rows by CUR-based methods, after Mahoney & Drineas 2009).
+ * For the n_rows x d matrix X of descriptor rows (device FP64, row-major), the
+ * leverage of row i over the row space of X is
+ *   lev_i = x_i^T (X^T X)^-1 x_i   (the hat matrix's diagonal; sum_i lev_i = d).
+ * exp_draws == NULL: the M rows of largest leverage.  Otherwise exp_draws[i] is
+ * an Exp(1) variate per row, drawn by the caller, and the M rows of smallest
+ * key exp_draws[i] / lev_i are taken: a sample without replacement with
+ * probabilities proportional to the leverage (Efraimidis & Spirakis).  Keys
+ * are formed in FP64; equal keys are taken in row order; rows with lev_i = 0
+ * get an infinite key.
+ *   selected      [M] device int64: the selected row indices, ascending.
+ *   leverage      [n_rows] device FP64 or NULL: lev_i.
+ *   workspace     device scratch of gap_cur_workspace_bytes(n_rows, d) bytes,
+ *                 caller-owned; its first 64 bytes hold the device status.
+ * Enqueued on `stream`.  wait != 0: synchronise the stream and return the
+ * device status (GAP_ENOTPD when a pivot of the Cholesky factorisation of
+ * X^T X is not positive, e.g. X has a zero column: the output is then
+ * meaningless; a rank deficiency that rounding hides is not detected, and the
+ * leverages carry an error of about kappa(X)^2 u); wait == 0: return GAP_OK
+ * after enqueueing.  GAP_EINVAL on NULL x/selected/workspace, n_rows < d,
+ * d < 1 or d > 4096, M < 1 or M > n_rows; GAP_ENOMEM when workspace_bytes is
+ * too small.  Inputs are not modified.
+ */
+size_t gap_cur_workspace_bytes(int64_t n_rows, int32_t d);
+gap_status gap_cur_select(const double *x, int64_t n_rows, int32_t d, const double *exp_draws, int64_t M,
+                          int64_t *selected, double *leverage, void *workspace, size_t workspace_bytes,
+                          void *stream, int32_t wait);
+
 /* Human-readable name of a status code (static string). */
 const char *gap_status_string(gap_status s);
 

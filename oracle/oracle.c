@@ -552,15 +552,24 @@ int oracle_cur_leverage(const double *X, int64_t n, int64_t d, double *lev)
         free(L);
         return ORACLE_ENOMEM;
     }
-#pragma omp parallel for schedule(dynamic, 4)
-    for (int64_t p = 0; p < d; ++p)
-        for (int64_t q = 0; q <= p; ++q) {
-            double s = 0.0;
-            for (int64_t r = 0; r < n; ++r)
-                s += X[r * d + p] * X[r * d + q];
-            G[p * d + q] = s;
-            G[q * d + p] = s;
+    /* G[p][q] (q <= p) = sum over the rows r in order of X[r][p] X[r][q]; each
+     * thread owns 16 rows of G and streams the rows of X once */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p0 = 0; p0 < d; p0 += 16) {
+        const int64_t p1 = p0 + 16 < d ? p0 + 16 : d;
+        for (int64_t r = 0; r < n; ++r) {
+            const double *x = X + r * d;
+            for (int64_t p = p0; p < p1; ++p) {
+                const double xp = x[p];
+                double *g = G + p * d;
+                for (int64_t q = 0; q <= p; ++q)
+                    g[q] += xp * x[q];
+            }
         }
+    }
+    for (int64_t p = 0; p < d; ++p)
+        for (int64_t q = 0; q < p; ++q)
+            G[q * d + p] = G[p * d + q];
     int rc = oracle_cholesky(G, d, L, NULL);
     if (rc == ORACLE_OK) {
 #pragma omp parallel

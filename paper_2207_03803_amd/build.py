@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgap.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["knm.hip", "knm_lp.hip", "knm_oz.hip", "potrf.hip", "geqrf.hip", "cqr.hip", "trsv.hip", "refine.hip", "diag.hip", "capi.hip"]
+SOURCES = ["knm.hip", "knm_lp.hip", "knm_oz.hip", "cur.hip", "potrf.hip", "geqrf.hip", "cqr.hip", "trsv.hip", "refine.hip", "diag.hip", "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

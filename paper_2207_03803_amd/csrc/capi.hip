@@ -244,6 +244,43 @@ gap_status dev(hipError_t e) { return e == hipSuccess ? GAP_OK : GAP_EDEVICE; }
 
 extern "C" {
 
+size_t gap_cur_workspace_bytes(int64_t n_rows, int32_t d)
+{
+    if (n_rows < 1 || d < 1 || d > cur_max_d() || n_rows < d)
+        return 0;
+    return cur_workspace_bytes(n_rows, d);
+}
+
+gap_status gap_cur_select(const double *x, int64_t n_rows, int32_t d, const double *exp_draws, int64_t M,
+                          int64_t *selected, double *leverage, void *workspace, size_t workspace_bytes,
+                          void *stream, int32_t wait)
+{
+    if (!x || !selected || !workspace || d < 1 || d > cur_max_d() || n_rows < d || M < 1 || M > n_rows)
+        return GAP_EINVAL;
+    if (workspace_bytes < cur_workspace_bytes(n_rows, d))
+        return GAP_ENOMEM;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    CurLaunch c{};
+    c.x = x;
+    c.n = n_rows;
+    c.d = d;
+    c.draws = exp_draws;
+    c.M = M;
+    c.out = selected;
+    c.lev_out = leverage;
+    c.workspace = workspace;
+    if (launch_cur_select(c, s) != hipSuccess)
+        return GAP_EDEVICE;
+    if (!wait)
+        return GAP_OK;
+    int32_t st = 0;
+    if (hipStreamSynchronize(s) != hipSuccess ||
+        hipMemcpy(&st, static_cast<char *>(workspace) + cur_status_offset(), sizeof(st), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+        return GAP_EDEVICE;
+    return st == 0 ? GAP_OK : static_cast<gap_status>(st);
+}
+
 const char *gap_status_string(gap_status s)
 {
     switch (s) {

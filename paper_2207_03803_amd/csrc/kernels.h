@@ -15,6 +15,27 @@ constexpr int CHOL_NB = 64;
 // pivot -> status DST_ENOTPD.
 hipError_t launch_potrf_upper(double *U, int64_t ld, int64_t n, int32_t *status, hipStream_t s);
 
+// ----------------------------------------------------- CUR sparse-point selection
+// Leverages of the n rows of X [n x d] (row-major FP64) over its row space, keys
+// draws[i] / lev[i] (1 / lev[i] when draws is null), and the M rows of smallest
+// key in ascending order into out.  The device status (DST_ENOTPD when X^T X is
+// not positive definite) is the first int32 of cur_status_offset() in the
+// workspace of cur_workspace_bytes(n, d) bytes.
+struct CurLaunch {
+    const double *x;
+    int64_t n;
+    int d;
+    const double *draws;  // [n] or null
+    int64_t M;
+    int64_t *out;         // [M]
+    double *lev_out;      // [n] or null
+    void *workspace;
+};
+size_t cur_workspace_bytes(int64_t n, int d);
+size_t cur_status_offset();
+int cur_max_d();
+hipError_t launch_cur_select(const CurLaunch &c, hipStream_t s);
+
 // ------------------------------------------------------------ Householder QR
 constexpr int QR_NB = 64;        // panel width
 constexpr int TS_ROWS = 256;     // rows of one TSQR tile

@@ -23,7 +23,8 @@ GAP_FLAG_KNM_INT8 = 4
 EXPORTS = ["gap_create", "gap_workspace_bytes", "gap_bind_workspace", "gap_build_knm", "gap_solve",
            "gap_predict", "gap_sync", "gap_layout", "gap_stage_times", "gap_status_string",
            "gap_set_tuning", "gap_set_model", "gap_set_stream", "gap_destroy", "gap_fit_static",
-           "gap_static_scratch_bytes", "gap_build_knm_batch", "gap_build_kmm"]
+           "gap_static_scratch_bytes", "gap_build_knm_batch", "gap_build_kmm", "gap_cur_workspace_bytes",
+           "gap_cur_select"]
 
 STAGES = ["knm", "kmm", "cholesky", "assemble_b", "qr", "trsv", "refine", "knm_lp", "diag"]
 
@@ -102,6 +103,10 @@ def lib():
     L.gap_build_knm_batch.restype = I32
     L.gap_build_kmm.argtypes = [P]
     L.gap_build_kmm.restype = I32
+    L.gap_cur_workspace_bytes.argtypes = [I64, I32]
+    L.gap_cur_workspace_bytes.restype = ctypes.c_size_t
+    L.gap_cur_select.argtypes = [P, I64, I32, P, I64, P, P, P, ctypes.c_size_t, P, I32]
+    L.gap_cur_select.restype = I32
     for n in ("gap_create", "gap_bind_workspace", "gap_build_knm", "gap_solve", "gap_predict", "gap_sync",
               "gap_layout", "gap_stage_times", "gap_set_tuning", "gap_set_model", "gap_set_stream",
               "gap_destroy"):
@@ -163,6 +168,33 @@ def build_knm_batch(handles, inputs, stream=None):
         fits[i] = GapBatchFit(X.data_ptr(), X.shape[0], offsets.data_ptr(), offsets.numel() - 1, XM.data_ptr(),
                               XM.shape[0], sigma.data_ptr())
     _check(lib().gap_build_knm_batch(hs, n, fits, ctypes.c_void_p(st.cuda_stream)), "gap_build_knm_batch")
+
+
+def cur_workspace_bytes(n_rows: int, d: int) -> int:
+    return int(lib().gap_cur_workspace_bytes(int(n_rows), int(d)))
+
+
+def cur_select(X, M, draws=None, leverage=False, stream=None, workspace=None, wait=True):
+    """gap_cur_select: CUR sparse-point selection over the rows of X (n x d device
+    FP64).  draws: Exp(1) variates per row (device FP64) or None for the M rows of
+    largest leverage.  Returns (selected row indices [M] int64, leverage [n] or
+    None).  wait=True synchronises and raises on a device error (GAP_ENOTPD for a
+    rank-deficient X)."""
+    import torch
+
+    n, d = X.shape
+    st = stream if stream is not None else torch.cuda.current_stream()
+    nb = cur_workspace_bytes(n, d)
+    if nb == 0:
+        raise GapError(GAP_EINVAL, "gap_cur_workspace_bytes")
+    if workspace is None:
+        workspace = torch.empty(nb, dtype=torch.uint8, device=X.device)
+    out = torch.empty(int(M), dtype=torch.int64, device=X.device)
+    lev = torch.empty(n, dtype=torch.float64, device=X.device) if leverage else None
+    _check(lib().gap_cur_select(_ptr(X), n, d, _ptr(draws) if draws is not None else None, int(M), _ptr(out),
+                                _ptr(lev) if lev is not None else None, _ptr(workspace), workspace.numel(),
+                                ctypes.c_void_p(st.cuda_stream), 1 if wait else 0), "gap_cur_select")
+    return out, lev
 
 
 def static_scratch_bytes() -> int:

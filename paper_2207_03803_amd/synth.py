@@ -96,6 +96,12 @@ def _draw_block(seed: int, b: int, rows: int, d: int) -> np.ndarray:
     return blk
 
 
+def cur_draws(n: int, seed: int = 0) -> np.ndarray:
+    """One Exp(1) variate per descriptor row for the sampled CUR selection, from
+    PCG64 seeded with SeedSequence([seed, 2]) (a stream of its own)."""
+    return np.random.default_rng(np.random.SeedSequence([seed, 2])).standard_exponential(n)
+
+
 def make_fit_inputs_blocked(n_configs: int, atoms=(16, 64), d: int = 400, M: int = 10_000,
                             seed: int = 0, sigma_per_atom: float = 1e-3, workers: int = 8,
                             log=None, **_unused) -> FitInputs:

@@ -16,12 +16,18 @@ the seeded generators; nothing here touches the GPU library.  Two parts:
   (``sweep.make_pools(host=True, min_configs=30000)``).  Stores y, c, |diag R|,
   the loss and kappa per fit in ``sweep_fits_seed0.npz``.  About 15 minutes.
 
+* ``cur``: CUR sparse-point selection over the realistic workload's descriptor
+  rows (the same arrays as ``realistic``): the oracle's leverages, their sum,
+  8192 sampled rows' leverages, and the M = 1e4 rows selected with the draws of
+  ``synth.cur_draws(n_atoms, 0)`` and by largest leverage, with the keys at the
+  threshold, in ``cur_realistic_seed0.npz``.  A few minutes.
+
 Targets are y = K_NM c_true + sigma * noise with K_NM from the oracle (the
 model's prediction with c_true, Eqs. 1-2), and the fit follows the oracle's
 stages in the paper's order (Sec. Theory): K_NM, K_MM + jitter, Cholesky, the
 stacked problem, Householder QR with Q^T b, back-substitution.
 
-Usage: python tests/golden/make_reference_fits.py {realistic|sweep} [--log FILE]
+Usage: python tests/golden/make_reference_fits.py {realistic|sweep|cur} [--log FILE]
 """
 from __future__ import annotations
 
@@ -121,9 +127,36 @@ def run_sweep(log):
     log("wrote sweep_fits_seed0.npz: " + json.dumps(meta))
 
 
+def run_cur(log):
+    w = dict(synth.WORKLOADS["realistic_fp64"])
+    t0 = time.time()
+    inp = synth.make_fit_inputs_blocked(seed=0, log=log, **w)
+    X, n, d, M = inp.X, inp.n_atoms, w["d"], w["M"]
+    log(f"descriptors: {n} x {d} in {time.time() - t0:.0f} s")
+    orc = oracle.Oracle()
+    t0 = time.time()
+    lev = orc.cur_leverage(X)
+    t_lev = time.time() - t0
+    log(f"leverages in {t_lev:.0f} s; sum {lev.sum():.12f}")
+    draws = synth.cur_draws(n, 0)
+    out = {}
+    for mode, dr in (("sampled", draws), ("top", None)):
+        idx, keys, _ = orc.cur_select(X, M, draws=dr, lev=lev)
+        ks = np.sort(keys)
+        out[f"{mode}_idx"] = idx
+        out[f"{mode}_kth"] = np.array([ks[M - 1], ks[M]])
+    rows = np.sort(np.random.default_rng(11).choice(n, 8192, replace=False))
+    meta = dict(workload="realistic_fp64", seed=0, generator="synth.make_fit_inputs_blocked",
+                draws="synth.cur_draws(n_atoms, 0)", n_rows=n, d=d, M=M, sum_lev=float(lev.sum()),
+                leverage_s=t_lev, threads=os.cpu_count())
+    np.savez(os.path.join(HERE, "cur_realistic_seed0.npz"), meta=json.dumps(meta), rows=rows, lev_rows=lev[rows],
+             **out)
+    log("wrote cur_realistic_seed0.npz: " + json.dumps(meta))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("part", choices=["realistic", "sweep"])
+    ap.add_argument("part", choices=["realistic", "sweep", "cur"])
     ap.add_argument("--log", default=None)
     a = ap.parse_args()
     fh = open(a.log, "a") if a.log else None
@@ -135,7 +168,7 @@ def main():
             fh.write(line + "\n")
             fh.flush()
 
-    {"realistic": run_realistic, "sweep": run_sweep}[a.part](log)
+    {"realistic": run_realistic, "sweep": run_sweep, "cur": run_cur}[a.part](log)
 
 
 if __name__ == "__main__":

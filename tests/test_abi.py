@@ -96,3 +96,22 @@ def test_fit_static_checks_arguments_and_size_without_a_gpu():
     assert gap.workspace_bytes(gap.params(64, 2), big[0], 40 * big[0], big[1]) > cap
     assert call(gap.params(64, 2), 40 * big[0], *big) == gap.GAP_ENOMEM
     assert gap.workspace_bytes(gap.params(64, 2), 200, 7200, 256) <= cap
+
+
+def test_cur_select_argument_checks_without_a_gpu():
+    """gap_cur_workspace_bytes is a pure host function; gap_cur_select rejects bad
+    shapes and a short workspace before touching the device."""
+    lib = gap.lib()
+    assert gap.cur_workspace_bytes(0, 8) == 0
+    assert gap.cur_workspace_bytes(100, 0) == 0
+    assert gap.cur_workspace_bytes(7, 8) == 0        # fewer rows than columns
+    assert gap.cur_workspace_bytes(100, 5000) == 0   # d above the supported 4096
+    nb = gap.cur_workspace_bytes(4_000_000, 400)
+    assert 8 * 4_000_000 * 5 <= nb <= 8 * 4_000_000 * 8  # keys + row parts, a few MB besides
+    fake = ctypes.c_void_p(0x1000)
+    call = lambda x, n, d, M, ws, wsb: lib.gap_cur_select(x, n, d, None, M, fake, None, ws, wsb, None, 1)
+    assert call(None, 100, 8, 10, fake, 1 << 30) == gap.GAP_EINVAL
+    assert call(fake, 100, 8, 0, fake, 1 << 30) == gap.GAP_EINVAL
+    assert call(fake, 100, 8, 101, fake, 1 << 30) == gap.GAP_EINVAL
+    assert call(fake, 100, 8, 10, None, 1 << 30) == gap.GAP_EINVAL
+    assert call(fake, 100, 8, 10, fake, gap.cur_workspace_bytes(100, 8) - 1) == gap.GAP_ENOMEM

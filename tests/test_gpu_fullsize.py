@@ -228,3 +228,32 @@ def test_int8_knm_fit_at_full_size(full, ref):
     assert info.device_status == gap.GAP_OK
     assert dk <= 1e-13 and ko <= 1e-13
     assert err <= 1e-10
+
+
+def test_cur_selection_at_full_size(full):
+    """CUR sparse-point selection over the realistic workload's 4e6 descriptor rows
+    (d = 400, M = 1e4) against the oracle's (tests/golden/cur_realistic_seed0.npz):
+    8192 sampled leverages within 1e-10, their sum d, and both selections (sampled
+    with the stored draws, and by largest leverage) equal to the oracle's except
+    where a key lies within 1e-9 of the threshold."""
+    import torch
+
+    from paper_2207_03803_amd import gap
+
+    z = np.load(os.path.join(HERE, "golden", "cur_realistic_seed0.npz"), allow_pickle=False)
+    n = f_n = full["inp"].n_atoms
+    M = 10_000
+    draws = torch.from_numpy(synth.cur_draws(n, 0)).cuda()
+    rows = z["rows"]
+    for mode, dr in (("sampled", draws), ("top", None)):
+        idx, lev = gap.cur_select(full["X"], M, draws=dr, leverage=True)
+        idx, lev = idx.cpu().numpy(), lev.cpu().numpy()
+        err = np.max(np.abs(lev[rows] - z["lev_rows"]) / z["lev_rows"])
+        diff = np.setxor1d(idx, z[f"{mode}_idx"])
+        kth = z[f"{mode}_kth"][0]
+        keys = (synth.cur_draws(n, 0)[diff] if dr is not None else 1.0) / lev[diff]
+        log(f"  CUR {mode}: {f_n} rows: sampled leverage max rel err {err:.2e}; sum {lev.sum():.12f}; "
+            f"selection differs from the oracle's in {len(diff)} rows")
+        assert err <= 1e-10
+        assert abs(lev.sum() - 400.0) <= 1e-9 * 400
+        assert np.all(np.abs(keys - kth) <= 1e-9 * kth)
