@@ -50,9 +50,11 @@ def _bind(lib):
                                ctypes.c_double, P, P, P, P, P, P, P, P, P, P]
     lib.oracle_singular_extremes.argtypes = [P, I64, I64, ctypes.c_int, ctypes.c_double, P, P, P]
     lib.oracle_cur_leverage.argtypes = [P, I64, I64, P]
+    lib.oracle_kdm.argtypes = [P, P, P, P, I64, P, P, P, I64, I64, ctypes.c_int, ctypes.c_double, P]
     for name in ("oracle_knm", "oracle_kmm", "oracle_cholesky", "oracle_stack",
                  "oracle_householder_qr", "oracle_back_substitution", "oracle_predict",
-                 "oracle_gradient", "oracle_fit", "oracle_singular_extremes", "oracle_cur_leverage"):
+                 "oracle_gradient", "oracle_fit", "oracle_singular_extremes", "oracle_cur_leverage",
+                 "oracle_kdm"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -183,6 +185,34 @@ class Oracle:
         order = np.argsort(keys, kind="stable")  # library sort; ties keep row order
         return np.sort(order[:M]), keys, lev
 
+    def kdm(self, X, x_grad, grad_atom, obs_offsets, pos_grad, pos_weight, XM, zeta, sigma_w=1.0):
+        """Derivative observation rows of K [n_obs x M] (forces, virials)."""
+        X, x_grad, XM, pos_weight = map(self._f64, (X, x_grad, XM, pos_weight))
+        grad_atom, obs_offsets, pos_grad = map(self._i64, (grad_atom, obs_offsets, pos_grad))
+        n_obs, M, d = len(obs_offsets) - 1, XM.shape[0], X.shape[1]
+        K = np.empty((n_obs, M))
+        rc = self.lib.oracle_kdm(self._p(X), self._p(x_grad), self._p(grad_atom), self._p(obs_offsets), n_obs,
+                                 self._p(pos_grad), self._p(pos_weight), self._p(XM), M, d, zeta, sigma_w,
+                                 self._p(K))
+        assert rc == ORACLE_OK, rc
+        return K
+
+    def fit_deriv(self, D, y, zeta, sigma_w=1.0, jitter=1e-8):
+        """The fit with energy and derivative rows (synth.DerivInputs D, targets y of
+        all N_E + n_obs rows), in the paper's order: K_NM, the derivative rows, K_MM +
+        jitter, Cholesky, the stacked problem A = [Sigma^-1/2 [K_NM ; K_D] ; L^T],
+        Householder QR with Q^T b, back-substitution.  Returns (c, loss_tail, K_all)."""
+        Knm = self.knm(D.X, D.offsets, D.XM, zeta, sigma_w)
+        Kd = self.kdm(D.X, D.x_grad, D.grad_atom, D.obs_offsets, D.pos_grad, D.pos_weight, D.XM, zeta, sigma_w)
+        K = np.vstack([Knm, Kd])
+        rc, L, fail = self.cholesky(self.kmm(D.XM, zeta, sigma_w, jitter))
+        assert rc == ORACLE_OK, (rc, fail)
+        A, b = self.stack(K, D.sigma, y, L)
+        A, qtb, _ = self.householder_qr(A, b, overwrite=True)
+        M = K.shape[1]
+        c = self.back_substitution(A, qtb[:M])
+        return c, float(np.sum(qtb[M:] ** 2)), K
+
     def predict(self, X, offsets, XM, c, zeta, sigma_w=1.0):
         X, XM, c, offsets = self._f64(X), self._f64(XM), self._f64(c), self._i64(offsets)
         N, M, d = len(offsets) - 1, XM.shape[0], X.shape[1]
@@ -232,6 +262,14 @@ class FitResult:
     A: np.ndarray | None = None
     qtb: np.ndarray | None = None
     tau: np.ndarray | None = None
+
+
+def deriv_targets(orc: Oracle, D, zeta, sigma_w=1.0):
+    """y for every row of a synth.DerivInputs: K c_true + sigma * noise (energies,
+    then derivative observations), computed by the oracle."""
+    yE = orc.predict(D.X, D.offsets, D.XM, D.c_true, zeta, sigma_w)
+    Kd = orc.kdm(D.X, D.x_grad, D.grad_atom, D.obs_offsets, D.pos_grad, D.pos_weight, D.XM, zeta, sigma_w)
+    return np.concatenate([yE, Kd @ D.c_true]) + D.sigma * np.concatenate([D.noise_E, D.noise_D])
 
 
 def targets(orc: Oracle, inputs, zeta, sigma_w=1.0):

@@ -594,3 +594,45 @@ int oracle_cur_leverage(const double *X, int64_t n, int64_t d, double *lev)
     free(L);
     return rc;
 }
+
+/*
+ * Derivative observation rows of K (Sec. Theory: force and virial targets are
+ * obtained by differentiating the energy expression).  x_grad holds descriptor
+ * gradients, row g = d x_{i(g)} / d r for one position coordinate, i(g) =
+ * grad_atom[g].  Observation o is the weighted sum over its positions p =
+ * obs_offsets[o] .. obs_offsets[o+1] (in order) of
+ *   w_p d k(x_i, x_j) / dr = w_p zeta sigma_w^2 (x_i . x_j)^(zeta - 1) (x'_g . x_j),
+ * g = pos_grad[p], w_p = pos_weight[p] (a force component takes w = -1 over the
+ * gradients of its coordinate; a virial component w = -r over those of its
+ * configuration).  K[o * M + j]; X is [n_atoms x d], XM [M x d], x_grad [n_grad x d].
+ */
+int oracle_kdm(const double *X, const double *x_grad, const int64_t *grad_atom, const int64_t *obs_offsets,
+               int64_t n_obs, const int64_t *pos_grad, const double *pos_weight, const double *XM, int64_t M,
+               int64_t d, int zeta, double sigma_w, double *K)
+{
+    if (n_obs < 0 || M < 1 || d < 1 || zeta < 1)
+        return ORACLE_EINVAL;
+    const double s2 = sigma_w * sigma_w;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t o = 0; o < n_obs; ++o) {
+        for (int64_t j = 0; j < M; ++j) {
+            const double *xj = XM + j * d;
+            double s = 0.0;
+            for (int64_t p = obs_offsets[o]; p < obs_offsets[o + 1]; ++p) {
+                const int64_t g = pos_grad[p];
+                const double *xi = X + grad_atom[g] * d, *xg = x_grad + g * d;
+                double gi = 0.0, gp = 0.0;
+                for (int64_t k = 0; k < d; ++k) {
+                    gi += xi[k] * xj[k];
+                    gp += xg[k] * xj[k];
+                }
+                double pw = 1.0;
+                for (int z = 1; z < zeta; ++z)
+                    pw *= gi;
+                s += pos_weight[p] * (zeta * s2 * pw * gp);
+            }
+            K[o * M + j] = s;
+        }
+    }
+    return ORACLE_OK;
+}
