@@ -184,6 +184,50 @@ gap_status gap_build_knm(gap_handle h, const double *x_atoms, int64_t n_atoms,
                          const double *x_sparse, int64_t M, const double *sigma);
 
 /* One fit's inputs for gap_build_knm_batch (device pointers, as in gap_build_knm). */
+/*
+ * Derivative observations (forces, virials; Sec. Theory: their rows of K_NM follow
+ * by differentiating the energy expression).  x_grad holds descriptor gradients:
+ * row g is d x_i / d r for one position coordinate r, i = grad_atom[g] (an index
+ * into x_atoms).  Observation o is a weighted sum over its positions p =
+ * obs_offsets[o] .. obs_offsets[o+1]: row o of K is
+ *   sum_p pos_weight[p] zeta sigma_w^2 (x_i . x_j)^(zeta - 1) (x_grad[pos_grad[p]] . x_j),
+ * i = grad_atom[pos_grad[p]].  A force component F_{k,alpha} = -dE/dr_{k,alpha}
+ * takes weight -1 over the gradients with respect to r_{k,alpha}; a virial
+ * component -sum_k r_{k,alpha} dE/dr_{k,beta} takes weight -r_{k,alpha} over
+ * those with respect to r_{k,beta} (a gradient row may serve several
+ * observations).  All arrays are device arrays owned by the caller, kept alive
+ * until the build has run.  Checked on the device (GAP_EINVAL in the status,
+ * nothing read out of range): obs_offsets[0] == 0, nondecreasing,
+ * obs_offsets[n_obs] == n_pos; pos_grad values in [0, n_grad); grad_atom values
+ * in [0, n_atoms).
+ */
+typedef struct gap_deriv_obs {
+    const double *x_grad;        /* [n_grad x d] FP64 row-major */
+    int64_t n_grad;
+    const int64_t *grad_atom;    /* [n_grad] */
+    const int64_t *obs_offsets;  /* [n_obs + 1] */
+    int64_t n_obs;
+    const int64_t *pos_grad;     /* [n_pos] gradient row of each position */
+    const double *pos_weight;    /* [n_pos] */
+    int64_t n_pos;
+} gap_deriv_obs;
+
+/* Workspace bytes for a fit with n_configs energies and n_obs derivative
+ * observations over n_pos positions (0 on bad arguments). */
+size_t gap_workspace_bytes_obs(const gap_params *p, int64_t n_configs, int64_t n_atoms, int64_t n_obs,
+                               int64_t n_pos, int64_t M);
+
+/* gap_build_knm with derivative observations: A's rows are the n_configs
+ * energies (as gap_build_knm), then the obs->n_obs derivative observations, then
+ * L^T; sigma [n_configs + obs->n_obs] holds every row's standard deviation, and
+ * gap_solve then takes y of the same length.  The derivative rows need an extra
+ * n_atoms x M FP64 block of the workspace (the powers (x_i . x_j)^(zeta - 1)).
+ * GAP_EINVAL with GAP_MIXED_BF16 / GAP_MIXED_FP16 (their low-precision block has
+ * energy rows only) or incomplete obs. */
+gap_status gap_build_knm_obs(gap_handle h, const double *x_atoms, int64_t n_atoms, const int64_t *config_offsets,
+                             int64_t n_configs, const gap_deriv_obs *obs, const double *x_sparse, int64_t M,
+                             const double *sigma);
+
 typedef struct gap_batch_fit {
     const double *x_atoms;
     int64_t n_atoms;
@@ -215,7 +259,8 @@ gap_status gap_build_kmm(gap_handle h);
 /*
  * Solve for the weights (Sec. Theory: b = [Sigma^-1/2 y ; 0], Householder QR of
  * [A | b] giving R and Q^T b, back-substitution c = R^-1 (Q^T b)[0:M]).
- *   y      [n_configs] FP64 targets (device)
+ *   y      [n_configs] FP64 targets (device); after gap_build_knm_obs
+ *          [n_configs + n_obs]: energies, then the derivative observations
  *   c_out  [M] FP64 weights (device)
  *   info   host struct or NULL.  When non-NULL the call waits for the stream and
  *          returns the device status; when NULL it returns after enqueueing.
@@ -260,8 +305,9 @@ gap_status gap_layout(gap_handle h, gap_layout_info *out);
  * [0] K_NM kernel, [1] K_MM kernel, [2] Cholesky, [3] b assembly,
  * [4] Householder QR incl. Q^T b, [5] back-substitution, [6] refinement,
  * [7] low-precision K_NM (rounding the descriptors and the BF16/FP16 kernel),
- * [8] solution diagnostics (grad_rel, and est_err when requested).
- * Waits for the stream.  n = number of floats in ms (up to 9). */
+ * [8] solution diagnostics (grad_rel, and est_err when requested),
+ * [9] derivative observation rows (gap_build_knm_obs).
+ * Waits for the stream.  n = number of floats in ms (up to 10). */
 gap_status gap_stage_times(gap_handle h, float *ms, int n);
 
 /* Launch-shape and method knobs an autotuner may set per handle (0 = library default).

@@ -13,12 +13,15 @@ using namespace gap;
 
 namespace {
 
-constexpr int N_STAGES = 9;
+constexpr int N_STAGES = 10;
 
 enum State { ST_CREATED = 0, ST_BOUND = 1, ST_KNM = 2, ST_BUILT = 3, ST_SOLVED = 4 };
 
 struct Layout {
+    // N = all observation rows: NE energies (configurations) then n_obs derivative observations
     int64_t N = 0, M = 0, n_atoms = 0, m = 0, lda = 0, ncols = 0, max_tiles = 0;
+    int64_t NE = 0, n_obs = 0, n_pos = 0, max_tiles_d = 0;
+    size_t off_tiles_d = 0, off_plan_d = 0, off_D = 0;
     TsqrTree tree;
     size_t off_A = 0, off_tau = 0, off_wpart = 0, off_T = 0, off_Tin = 0, off_U = 0, off_W = 0, off_ts_tiles = 0,
            off_ts_X = 0, off_ts_tau = 0, off_rhs = 0, off_misc = 0, off_tiles = 0, off_counters = 0,
@@ -44,9 +47,14 @@ bool is_lp(int32_t precision) { return precision == GAP_MIXED_BF16 || precision 
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, int32_t precision, int d, uint32_t flags)
+Layout make_layout(int64_t NE, int64_t n_atoms, int64_t M, int32_t precision, int d, uint32_t flags,
+                   int64_t n_obs = 0, int64_t n_pos = 0)
 {
     Layout L;
+    const int64_t N = NE + n_obs;
+    L.NE = NE;
+    L.n_obs = n_obs;
+    L.n_pos = n_pos;
     const bool mixed = is_mixed(precision);
     L.mixed = mixed;
     L.lp = is_lp(precision);
@@ -56,7 +64,7 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, int32_t precision, int
     L.m = N + M;
     L.lda = (L.m + 63) / 64 * 64;
     L.ncols = M + 1;
-    L.max_tiles = knm_max_tiles(N, n_atoms);
+    L.max_tiles = knm_max_tiles(NE, n_atoms);
     L.tree = tsqr_tree(L.m);
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -77,7 +85,14 @@ Layout make_layout(int64_t N, int64_t n_atoms, int64_t M, int32_t precision, int
     L.off_rhs = take(sizeof(double) * (size_t)M);
     L.off_misc = take(sizeof(double) * 512);
     L.off_tiles = take(sizeof(int32_t) * (size_t)(L.max_tiles + 2));
-    L.off_plan = take(sizeof(int32_t) * (size_t)(N + knm_plan_chunks(N) * (2049 + 1)));
+    L.off_plan = take(sizeof(int32_t) * (size_t)(NE + knm_plan_chunks(NE) * (2049 + 1)));
+    if (n_obs > 0) {
+        // derivative observations: their tile plan over the positions, and D = (X X_M^T)^(zeta - 1)
+        L.max_tiles_d = knm_max_tiles(n_obs, n_pos);
+        L.off_tiles_d = take(sizeof(int32_t) * (size_t)(L.max_tiles_d + 2));
+        L.off_plan_d = take(sizeof(int32_t) * (size_t)(n_obs + knm_plan_chunks(n_obs) * (2049 + 1)));
+        L.off_D = take(sizeof(double) * (size_t)n_atoms * (size_t)M);
+    }
     L.off_counters = take(sizeof(unsigned) * 16);
     L.off_status = take(sizeof(int32_t) * 4);
     L.n_tflags = trsv_sync_ints(M);
@@ -138,6 +153,7 @@ struct gap_handle_s {
     const double *sigma = nullptr;
     const double *x_atoms = nullptr;      // inputs of the current build
     const int64_t *offsets = nullptr;
+    gap_deriv_obs obs = {};   // derivative observations of the current build (n_obs = 0: none)
     int64_t model_M = 0;      // set by gap_set_model
     bool model_only = false;  // predict-only handle (no workspace)
     hipEvent_t ev[2 * N_STAGES] = {};
@@ -415,7 +431,8 @@ static bool create_lookahead(gap_handle h)
 // Checks, layout and input pointers of a build; creates the look-ahead stream
 // when the fit uses one.
 static gap_status build_prepare(gap_handle h, const double *x_atoms, int64_t n_atoms, const int64_t *config_offsets,
-                                int64_t n_configs, const double *x_sparse, int64_t M, const double *sigma)
+                                int64_t n_configs, const double *x_sparse, int64_t M, const double *sigma,
+                                const gap_deriv_obs *obs = nullptr)
 {
     if (!h)
         return GAP_EINVAL;
@@ -424,10 +441,16 @@ static gap_status build_prepare(gap_handle h, const double *x_atoms, int64_t n_a
     if (!x_atoms || !config_offsets || !x_sparse || !sigma || n_atoms < 1 || n_configs < 1 || M < 1 ||
         n_configs > INT32_MAX - 1)
         return GAP_EINVAL;
-    const Layout L = make_layout(n_configs, n_atoms, M, h->p.precision, h->p.d, h->p.flags);
+    if (obs && (!obs->x_grad || !obs->grad_atom || !obs->obs_offsets || !obs->pos_grad || !obs->pos_weight ||
+                obs->n_grad < 1 || obs->n_obs < 1 || obs->n_pos < 1 || is_lp(h->p.precision)))
+        return GAP_EINVAL;
+    const Layout L = make_layout(n_configs, n_atoms, M, h->p.precision, h->p.d, h->p.flags, obs ? obs->n_obs : 0,
+                                 obs ? obs->n_pos : 0);
     if (L.total > h->ws_bytes)
         return GAP_ENOMEM;
     h->L = L;
+    h->obs = obs ? *obs : gap_deriv_obs{};
+    h->timed[9] = false;
     h->x_atoms = x_atoms;
     h->offsets = config_offsets;
     h->x_sparse = x_sparse;
@@ -453,8 +476,23 @@ static KnmPlan plan_of(gap_handle h)
     kp.tile_start = tiles;
     kp.n_tiles = tiles + L.max_tiles + 1;
     kp.cfg_list = plan;
-    kp.lstart = plan + L.N;
-    kp.lcount = kp.lstart + knm_plan_chunks(L.N) * 2049;
+    kp.lstart = plan + L.NE;
+    kp.lcount = kp.lstart + knm_plan_chunks(L.NE) * 2049;
+    return kp;
+}
+
+// The derivative observations' tile plan (over their positions).
+static KnmPlan plan_of_d(gap_handle h)
+{
+    const Layout &L = h->L;
+    int32_t *tiles = h->at<int32_t>(L.off_tiles_d);
+    int32_t *plan = h->at<int32_t>(L.off_plan_d);
+    KnmPlan kp;
+    kp.tile_start = tiles;
+    kp.n_tiles = tiles + L.max_tiles_d + 1;
+    kp.cfg_list = plan;
+    kp.lstart = plan + L.n_obs;
+    kp.lcount = kp.lstart + knm_plan_chunks(L.n_obs) * 2049;
     return kp;
 }
 
@@ -467,7 +505,7 @@ static gap_status build_setup(gap_handle h, hipStream_t s, KnmArgs *a)
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned *>(h->status()), 4);
     hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(256), 0, s, h->at<int32_t>(L.off_tflags), L.n_tflags);
     const KnmPlan kp = plan_of(h);
-    GAP_TRY(dev(launch_plan_tiles(h->offsets, L.N, L.n_atoms, kp, L.max_tiles, h->status(), s)));
+    GAP_TRY(dev(launch_plan_tiles(h->offsets, L.NE, L.n_atoms, kp, L.max_tiles, h->status(), s)));
     *a = KnmArgs{};
     a->X = h->x_atoms;
     a->offsets = h->offsets;
@@ -593,6 +631,90 @@ gap_status gap_build_knm(gap_handle h, const double *x_atoms, int64_t n_atoms, c
         GAP_TRY(dev(launch_knm(a, h->L.max_tiles, h->stream)));
     h->mark(0, true);
     return build_rest(h);
+}
+
+// Derivative observation rows N_E .. N_E + n_obs - 1 of A: D = (X X_M^T)^(zeta - 1) for
+// every atom (none for zeta = 1), the positions' tile plan, then the derivative tiles.
+static gap_status build_derivatives(gap_handle h)
+{
+    const Layout &L = h->L;
+    const gap_params &p = h->p;
+    hipStream_t s = h->stream;
+    const gap_deriv_obs &o = h->obs;
+    h->mark(9, false);
+    double *D = nullptr;
+    if (p.zeta > 1) {
+        D = h->at<double>(L.off_D);
+        KnmArgs k{};
+        k.X = h->x_atoms;
+        k.offsets = nullptr;
+        k.n_rows_unit = L.n_atoms;
+        k.XM = h->x_sparse;
+        k.M = L.M;
+        k.d = p.d;
+        k.zeta = p.zeta - 1;
+        k.sw2 = 1.0;
+        k.out = D;
+        k.ldo = L.n_atoms;
+        k.status = h->status();
+        GAP_TRY(dev(launch_knm(k, (L.n_atoms + KNM_BM - 1) / KNM_BM, s)));
+    }
+    const KnmPlan kp = plan_of_d(h);
+    GAP_TRY(dev(launch_plan_tiles(o.obs_offsets, L.n_obs, L.n_pos, kp, L.max_tiles_d, h->status(), s)));
+    KnmArgs a{};
+    a.X = o.x_grad;
+    a.offsets = o.obs_offsets;
+    a.tile_start = kp.tile_start;
+    a.cfg_list = kp.cfg_list;
+    a.n_tiles_dev = kp.n_tiles;
+    a.XM = h->x_sparse;
+    a.M = L.M;
+    a.d = p.d;
+    a.zeta = p.zeta;
+    a.sw2 = p.sigma_w * p.sigma_w;
+    a.sigma = h->sigma + L.NE;
+    a.out = h->A();
+    a.ldo = L.lda;
+    a.row_off = L.NE;
+    a.status = h->status();
+    a.pos_grad = o.pos_grad;
+    a.pos_weight = o.pos_weight;
+    a.grad_atom = o.grad_atom;
+    a.D = D;
+    a.ldd = L.n_atoms;
+    a.n_grad = o.n_grad;
+    a.n_src = L.n_atoms;
+    GAP_TRY(dev(launch_kdm(a, L.max_tiles_d, s)));
+    h->mark(9, true);
+    return GAP_OK;
+}
+
+gap_status gap_build_knm_obs(gap_handle h, const double *x_atoms, int64_t n_atoms, const int64_t *config_offsets,
+                             int64_t n_configs, const gap_deriv_obs *obs, const double *x_sparse, int64_t M,
+                             const double *sigma)
+{
+    if (!obs)
+        return GAP_EINVAL;
+    GAP_TRY(build_prepare(h, x_atoms, n_atoms, config_offsets, n_configs, x_sparse, M, sigma, obs));
+    KnmArgs a;
+    GAP_TRY(build_setup(h, h->stream, &a));
+    h->mark(0, false);
+    if (h->L.oz)
+        GAP_TRY(launch_knm_int8(h, h->stream));
+    else
+        GAP_TRY(dev(launch_knm(a, h->L.max_tiles, h->stream)));
+    h->mark(0, true);
+    GAP_TRY(build_derivatives(h));
+    return build_rest(h);
+}
+
+size_t gap_workspace_bytes_obs(const gap_params *p, int64_t n_configs, int64_t n_atoms, int64_t n_obs,
+                               int64_t n_pos, int64_t M)
+{
+    if (!valid_params(p) || n_configs < 1 || n_atoms < 1 || M < 1 || n_obs < 0 || n_pos < 0 ||
+        (n_obs > 0 && n_pos < 1) || n_configs + n_obs > INT32_MAX - 1 || n_obs > INT32_MAX - 1)
+        return 0;
+    return make_layout(n_configs, n_atoms, M, p->precision, p->d, p->flags, n_obs, n_pos).total;
 }
 
 gap_status gap_build_knm_batch(gap_handle *handles, int32_t n, const gap_batch_fit *fits, void *stream)

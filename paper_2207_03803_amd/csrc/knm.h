@@ -32,6 +32,15 @@ struct KnmArgs {
     int64_t n_ct, total_pad;   // filled by launch_knm
     int32_t *status;
     int bn;                    // column tile: 64 sparse points (0 or 64) or 32
+    // derivative observation rows (launch_kdm only): the segments are observations over
+    // positions p (offsets is their CSR); row p reads X[pos_grad[p]], X = the descriptor
+    // gradients, and its products are scaled by zeta sw2 pos_weight[p] D(grad_atom[g], j)
+    const int64_t *pos_grad;   // [n_pos]
+    const double *pos_weight;  // [n_pos]
+    const int64_t *grad_atom;  // [n_grad]
+    const double *D;           // column-major, D[j * ldd + i] = (x_i . x_j)^(zeta - 1); null: 1 (zeta = 1)
+    int64_t ldd;
+    int64_t n_grad, n_src;     // bounds of pos_grad and grad_atom values (out of range: zero row, DST_EINVAL)
 };
 
 int64_t knm_max_tiles(int64_t N, int64_t n_atoms);
@@ -44,6 +53,10 @@ struct KnmPlan {
 hipError_t launch_plan_tiles(const int64_t *offsets, int64_t N, int64_t n_atoms, const KnmPlan &p, int64_t max_tiles,
                              int32_t *status, hipStream_t s);
 hipError_t launch_knm(KnmArgs a, int64_t max_tiles, hipStream_t s);
+// Derivative observation rows (forces, virials): with the tile plan built over the
+// observations' positions, row o of out is sum_p w_p zeta sw2 D(i(p), j) (x'_{g(p)} . x_j),
+// divided by sigma[o].  a.X holds the gradients, a.zeta the kernel exponent.
+hipError_t launch_kdm(KnmArgs a, int64_t max_tiles, hipStream_t s);
 // The K_NM of n fits as grouped launches (up to KNM_GROUP fits per launch, the
 // table passed as the kernel argument); each fit's tiles compute exactly what
 // launch_knm computes for it.

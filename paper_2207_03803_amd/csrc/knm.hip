@@ -284,7 +284,14 @@ constexpr int knm_lds_doubles()
 
 // One workgroup's tile; bid = the workgroup's index within this K_NM's own grid
 // (a multiple-of-8 offset into a grouped grid keeps bid's XCD the hardware's).
-template <int BN>
+// A derivative position whose gradient row and atom are in range.
+DEV bool kdm_valid(const KnmArgs &a, int64_t pos)
+{
+    const int64_t g = a.pos_grad[pos];
+    return g >= 0 && g < a.n_grad && a.grad_atom[g] >= 0 && a.grad_atom[g] < a.n_src;
+}
+
+template <int BN, bool DERIV = false>
 DEV void knm_body(const KnmArgs &a, int64_t bid)
 {
     using KS = KSB<BN>;
@@ -295,6 +302,8 @@ DEV void knm_body(const KnmArgs &a, int64_t bid)
     __shared__ int64_t sbase[KNM_MAX_SEG];       // first atom (row of X) of each segment
     __shared__ int32_t srow[KNM_MAX_SEG];        // output row of each segment
     __shared__ double carry[KNM_BN];
+    __shared__ double rowf[DERIV ? KNM_BM : 1];      // derivative rows: zeta sw2 w of tile row r
+    __shared__ int64_t rowatom[DERIV ? KNM_BM : 1];  // and its gradient's atom (-1 past the tile)
 
     // The grid is sized for the largest possible tile count; the remap uses
     // the actual count so that all eight XCDs get an equal share of the tiles.
@@ -406,24 +415,63 @@ DEV void knm_body(const KnmArgs &a, int64_t bid)
             else
                 hi = mid - 1;
         }
-        xr_packed = a.X + (sbase[lo] + (tid - sstart[lo])) * (int64_t)a.d;
+        const int64_t pos = sbase[lo] + (tid - sstart[lo]);
+        xr_packed = a.X + (DERIV ? a.pos_grad[pos] : pos) * (int64_t)a.d;
+        if (DERIV && !kdm_valid(a, pos)) {
+            xr_packed = nullptr;
+            set_status(a.status, DST_EINVAL);
+        }
     }
     d4 acc[KS::FM][KS::FN];
     for (int64_t cs = 0; cs < n_at; cs += KNM_BM) {
         const bool first = (cs == 0), last = (cs + KNM_BM >= n_at);
-        const double *xr = multi ? ((cs + tid < n_at) ? a.X + (sbase[0] + cs + tid) * (int64_t)a.d : nullptr)
-                                 : xr_packed;
+        const double *xr = xr_packed;
+        if (multi) {
+            const int64_t pos = sbase[0] + cs + tid;
+            xr = (cs + tid < n_at) ? a.X + (DERIV ? a.pos_grad[pos] : pos) * (int64_t)a.d : nullptr;
+            if (DERIV && xr && !kdm_valid(a, pos)) {
+                xr = nullptr;
+                set_status(a.status, DST_EINVAL);
+            }
+        }
+        if constexpr (DERIV) {
+            // this thread's tile row: its weight and its gradient's atom
+            int64_t pos = -1;
+            if (multi) {
+                if (cs + tid < n_at)
+                    pos = sbase[0] + cs + tid;
+            } else if (xr) {
+                int lo = 0, hi = n_seg - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (sstart[mid] <= tid)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                pos = sbase[lo] + (tid - sstart[lo]);
+            }
+            if (pos >= 0 && !kdm_valid(a, pos))
+                pos = -1;  // reported above; the row reads as zero
+            rowf[tid] = pos >= 0 ? a.zeta * a.sw2 * a.pos_weight[pos] : 0.0;
+            rowatom[tid] = pos >= 0 ? a.grad_atom[a.pos_grad[pos]] : -1;
+        }
         __syncthreads();
         knm_gemm<BN>(acc, lds, xr, a.XM, col0, a.M, a.d);
 
-        // k = sigma_w^2 g^zeta, in registers.
+        if constexpr (DERIV) {
+            // d k / dr = zeta sigma_w^2 (x_i . x_j)^(zeta - 1) (x' . x_j), times the
+            // position's weight: applied below as the values are parked
+        } else {
+            // k = sigma_w^2 g^zeta, in registers.
 #pragma unroll
-        for (int i = 0; i < KS::FM; ++i)
+            for (int i = 0; i < KS::FM; ++i)
 #pragma unroll
-            for (int j = 0; j < KS::FN; ++j)
+                for (int j = 0; j < KS::FN; ++j)
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    acc[i][j][e] = a.sw2 * ipow(acc[i][j][e], a.zeta);
+                    for (int e = 0; e < 4; ++e)
+                        acc[i][j][e] = a.sw2 * ipow(acc[i][j][e], a.zeta);
+        }
 
         double *E = lds;  // [256][EPLD], reused after the GEMM
         for (int p = 0; p < (KNM_BN + EPC - 1) / EPC; ++p) {
@@ -436,8 +484,17 @@ DEV void knm_body(const KnmArgs &a, int64_t bid)
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
                             const int cl = acc_col<KS>(wn, j, lane, e) - p * EPC;
-                            if (cl >= 0 && cl < EPC)
-                                E[acc_row<KS>(wm, i, lane, e) * EPLD + cl] = acc[i][j][e];
+                            if (cl >= 0 && cl < EPC) {
+                                const int r = acc_row<KS>(wm, i, lane, e);
+                                double v = acc[i][j][e];
+                                if constexpr (DERIV) {
+                                    // (rowf / rowatom were written before the GEMM's barriers)
+                                    const int64_t at = rowatom[r], colg = col0 + p * EPC + cl;
+                                    const double dv = (a.D && at >= 0 && colg < a.M) ? a.D[colg * a.ldd + at] : 1.0;
+                                    v = v * (rowf[r] * dv);
+                                }
+                                E[r * EPLD + cl] = v;
+                            }
                         }
             }
             __syncthreads();
@@ -494,6 +551,9 @@ DEV void knm_body(const KnmArgs &a, int64_t bid)
 
 template <int BN>
 __global__ __launch_bounds__(256, 2) void knm_kernel(KnmArgs a) { knm_body<BN>(a, blockIdx.x); }
+
+// Derivative observation rows: the K_NM tile loop over the observations' positions.
+__global__ __launch_bounds__(256, 2) void kdm_kernel(KnmArgs a) { knm_body<64, true>(a, blockIdx.x); }
 
 // The K_NM of several fits in one grid: fit i owns workgroups [base[i], base[i+1]).
 template <int BN>
@@ -670,6 +730,17 @@ hipError_t launch_knm_group(const KnmArgs *fits, const int64_t *max_tiles, int n
         }
         flush();
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_kdm(KnmArgs a, int64_t max_tiles, hipStream_t s)
+{
+    a.n_ct = (a.M + 63) / 64;
+    const int64_t total = max_tiles * a.n_ct;
+    a.total_pad = (total + 7) & ~int64_t(7);
+    if (a.total_pad == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(kdm_kernel, dim3((unsigned)a.total_pad), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

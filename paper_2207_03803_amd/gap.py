@@ -24,9 +24,9 @@ EXPORTS = ["gap_create", "gap_workspace_bytes", "gap_bind_workspace", "gap_build
            "gap_predict", "gap_sync", "gap_layout", "gap_stage_times", "gap_status_string",
            "gap_set_tuning", "gap_set_model", "gap_set_stream", "gap_destroy", "gap_fit_static",
            "gap_static_scratch_bytes", "gap_build_knm_batch", "gap_build_kmm", "gap_cur_workspace_bytes",
-           "gap_cur_select"]
+           "gap_cur_select", "gap_workspace_bytes_obs", "gap_build_knm_obs"]
 
-STAGES = ["knm", "kmm", "cholesky", "assemble_b", "qr", "trsv", "refine", "knm_lp", "diag"]
+STAGES = ["knm", "kmm", "cholesky", "assemble_b", "qr", "trsv", "refine", "knm_lp", "diag", "kdm"]
 
 
 class GapParams(ctypes.Structure):
@@ -47,6 +47,12 @@ class GapBatchFit(ctypes.Structure):
     _fields_ = [("x_atoms", ctypes.c_void_p), ("n_atoms", ctypes.c_int64), ("config_offsets", ctypes.c_void_p),
                 ("n_configs", ctypes.c_int64), ("x_sparse", ctypes.c_void_p), ("M", ctypes.c_int64),
                 ("sigma", ctypes.c_void_p)]
+
+
+class GapDerivObs(ctypes.Structure):
+    _fields_ = [("x_grad", ctypes.c_void_p), ("n_grad", ctypes.c_int64), ("grad_atom", ctypes.c_void_p),
+                ("obs_offsets", ctypes.c_void_p), ("n_obs", ctypes.c_int64), ("pos_grad", ctypes.c_void_p),
+                ("pos_weight", ctypes.c_void_p), ("n_pos", ctypes.c_int64)]
 
 
 class GapTuning(ctypes.Structure):
@@ -103,6 +109,10 @@ def lib():
     L.gap_build_knm_batch.restype = I32
     L.gap_build_kmm.argtypes = [P]
     L.gap_build_kmm.restype = I32
+    L.gap_workspace_bytes_obs.argtypes = [ctypes.POINTER(GapParams), I64, I64, I64, I64, I64]
+    L.gap_workspace_bytes_obs.restype = ctypes.c_size_t
+    L.gap_build_knm_obs.argtypes = [P, P, I64, P, I64, ctypes.POINTER(GapDerivObs), P, I64, P]
+    L.gap_build_knm_obs.restype = I32
     L.gap_cur_workspace_bytes.argtypes = [I64, I32]
     L.gap_cur_workspace_bytes.restype = ctypes.c_size_t
     L.gap_cur_select.argtypes = [P, I64, I32, P, I64, P, P, P, ctypes.c_size_t, P, I32]
@@ -233,6 +243,29 @@ class Handle:
         ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self.bind(ws)
         return ws
+
+    def alloc_workspace_obs(self, n_configs, n_atoms, n_obs, n_pos, M):
+        """Workspace for a fit with derivative observations (gap_workspace_bytes_obs)."""
+        import torch
+
+        nbytes = int(lib().gap_workspace_bytes_obs(ctypes.byref(self.p), n_configs, n_atoms, n_obs, n_pos, M))
+        if nbytes == 0:
+            raise GapError(GAP_EINVAL, "gap_workspace_bytes_obs")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.bind(ws)
+        return ws
+
+    def build_knm_obs(self, X, offsets, obs, XM, sigma):
+        """gap_build_knm_obs: energies and derivative observations.  obs: dict of device
+        tensors x_grad [n_grad, d], grad_atom [n_grad], obs_offsets [n_obs + 1],
+        pos_grad [n_pos], pos_weight [n_pos]; sigma covers every row (energies, then
+        the derivative observations)."""
+        o = GapDerivObs(obs["x_grad"].data_ptr(), obs["x_grad"].shape[0], obs["grad_atom"].data_ptr(),
+                        obs["obs_offsets"].data_ptr(), obs["obs_offsets"].numel() - 1, obs["pos_grad"].data_ptr(),
+                        obs["pos_weight"].data_ptr(), obs["pos_grad"].numel())
+        self._inputs = (X, offsets, XM, sigma, obs)
+        _check(lib().gap_build_knm_obs(self.h, _ptr(X), X.shape[0], _ptr(offsets), offsets.numel() - 1,
+                                       ctypes.byref(o), _ptr(XM), XM.shape[0], _ptr(sigma)), "gap_build_knm_obs")
 
     def build_knm(self, X, offsets, XM, sigma):
         # the library keeps these pointers (sigma for gap_solve, XM for gap_predict):

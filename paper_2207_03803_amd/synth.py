@@ -189,15 +189,20 @@ def make_fit_inputs_torch(n_configs: int, atoms=(16, 64), d: int = 400, M: int =
 # ---------------------------------------------------------------------------
 # Derivative observations (forces, virials).  A smooth synthetic descriptor
 # model supplies descriptors together with their exact position gradients:
-# atoms sit in a cube per configuration, each has a species (one of four) and
-# its n_neigh nearest atoms of the configuration as neighbours (fixed lists),
-# and
-#   x_i = (U0[t_i] + sum_{k in nb(i)} phi(|r_i - r_k|^2) U[t_k]) / C,
-#   phi(s) = exp(-s / 2),  C = 1 + 0.6 n_neigh,
-# with U0, U fixed non-negative unit vectors per species.  The gradients
-# dx_i / dr_{k, alpha} follow by the chain rule.  The fit's arithmetic on them
-# (the derivative rows of K) is left to the caller.
+# atoms sit in a cube per configuration, each has a species (one of
+# N_SPECIES) and its n_neigh nearest atoms of the configuration as neighbours
+# (fixed lists), and
+#   x_i = (U0[t_i] + sum_{k in nb(i)} sum_b phi_b(|r_i - r_k|^2) U[t_k, b]) / C,
+#   phi_b(s) = exp(-s / (2 w_b^2)),  C = 1 + 0.3 n_neigh N_RADIAL,
+# with U0, U fixed random unit vectors (per species and radial function b;
+# entries of both signs, so that descriptors of different environments are far
+# from parallel and K stays well conditioned).  The gradients dx_i / dr_{k, alpha} follow by the chain rule.  The fit's
+# arithmetic on them (the derivative rows of K) is left to the caller.
 # ---------------------------------------------------------------------------
+N_SPECIES = 8
+RADIAL_WIDTHS = np.array([0.6, 0.9, 1.3, 2.0])
+N_RADIAL = len(RADIAL_WIDTHS)
+
 
 @dataclass
 class DerivInputs:
@@ -205,8 +210,8 @@ class DerivInputs:
     R: np.ndarray            # float64 [n_atoms, 3] positions
     species: np.ndarray      # int64 [n_atoms]
     nb: np.ndarray           # int64 [n_atoms, n_neigh] neighbour lists (global atom indices)
-    U0: np.ndarray           # float64 [4, d]
-    U: np.ndarray            # float64 [4, d]
+    U0: np.ndarray           # float64 [N_SPECIES, d]
+    U: np.ndarray            # float64 [N_SPECIES, N_RADIAL, d]
     X: np.ndarray            # float64 [n_atoms, d] descriptors at R
     sparse_idx: np.ndarray   # int64 [M]
     XM: np.ndarray           # float64 [M, d] = X[sparse_idx] (held fixed)
@@ -243,13 +248,18 @@ class DerivInputs:
         return np.concatenate([self.sigma_E, self.sigma_D])
 
 
+def _radial(R, nb):
+    diff = R[:, None, :] - R[nb]                                        # r_i - r_k, [n, n_neigh, 3]
+    s2 = np.sum(diff * diff, axis=2)                                    # [n, n_neigh]
+    phi = np.exp(-s2[:, :, None] / (2.0 * RADIAL_WIDTHS ** 2))          # [n, n_neigh, N_RADIAL]
+    return diff, phi
+
+
 def deriv_descriptors(R, offsets, species, nb, U0, U):
     """Descriptors of the synthetic model at positions R (neighbour lists fixed)."""
-    n_neigh = nb.shape[1]
-    C = 1.0 + 0.6 * n_neigh
-    diff = R[:, None, :] - R[nb]                      # [n, n_neigh, 3]
-    phi = np.exp(-0.5 * np.sum(diff * diff, axis=2))  # [n, n_neigh]
-    return (U0[species] + np.einsum("nk,nkd->nd", phi, U[species[nb]])) / C
+    C = 1.0 + 0.3 * nb.shape[1] * N_RADIAL
+    _, phi = _radial(R, nb)
+    return (U0[species] + np.einsum("nkb,nkbd->nd", phi, U[species[nb]])) / C
 
 
 def make_deriv_inputs(n_configs: int, atoms=(20, 60), d: int = 64, M: int = 128, n_neigh: int = 12,
@@ -274,22 +284,21 @@ def make_deriv_inputs(n_configs: int, atoms=(20, 60), d: int = 64, M: int = 128,
         dist = np.sum((r[:, None, :] - r[None, :, :]) ** 2, axis=2)
         np.fill_diagonal(dist, np.inf)
         nb[lo:lo + na] = lo + np.argsort(dist, axis=1, kind="stable")[:, :n_neigh]
-    species = rng.integers(0, 4, size=n)
-    U0 = np.abs(rng.standard_normal((4, d)))
+    species = rng.integers(0, N_SPECIES, size=n)
+    U0 = rng.standard_normal((N_SPECIES, d))
     U0 /= np.linalg.norm(U0, axis=1, keepdims=True)
-    U = np.abs(rng.standard_normal((4, d)))
-    U /= np.linalg.norm(U, axis=1, keepdims=True)
+    U = rng.standard_normal((N_SPECIES, N_RADIAL, d))
+    U /= np.linalg.norm(U, axis=2, keepdims=True)
     X = deriv_descriptors(R, offsets, species, nb, U0, U)
     sparse_idx = np.sort(rng.choice(n, size=M, replace=False)).astype(np.int64)
     XM = np.ascontiguousarray(X[sparse_idx])
     # gradient rows (i, k, alpha): k = i first, then i's neighbours
-    C = 1.0 + 0.6 * n_neigh
-    diff = R[:, None, :] - R[nb]                                   # r_i - r_k
-    phi = np.exp(-0.5 * np.sum(diff * diff, axis=2))               # [n, n_neigh]
-    dphi = -0.5 * phi                                              # phi'(s)
-    Uk = U[species[nb]]                                            # [n, n_neigh, d]
-    # d x_i / d r_{k, alpha} = phi'(s_ik) 2 (r_k - r_i)_alpha U[t_k] / C for a neighbour k
-    g_nb = (dphi[:, :, None] * (-2.0 * diff))[:, :, :, None] * Uk[:, :, None, :] / C  # [n, nn, 3, d]
+    C = 1.0 + 0.3 * n_neigh * N_RADIAL
+    diff, phi = _radial(R, nb)
+    dphi = -phi / (2.0 * RADIAL_WIDTHS ** 2)                       # phi_b'(s), [n, nn, N_RADIAL]
+    # d x_i / d r_{k, alpha} = sum_b phi_b'(s_ik) 2 (r_k - r_i)_alpha U[t_k, b] / C for a neighbour k
+    v = np.einsum("nkb,nkbd->nkd", dphi, U[species[nb]])           # [n, nn, d]
+    g_nb = (-2.0 * diff)[:, :, :, None] * v[:, :, None, :] / C     # [n, nn, 3, d]
     g_self = -np.sum(g_nb, axis=1)                                 # [n, 3, d]
     n_grad = n * (n_neigh + 1) * 3
     x_grad = np.empty((n, n_neigh + 1, 3, d))
