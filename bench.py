@@ -9,6 +9,8 @@ M = 1e4 sparse points, zeta = 4, FP64, beside the three forms around it:
          (Ozaki scheme: 7 slices per value, 28 exact slice products)
   cur    CUR sparse-point selection of M rows from the descriptor rows
          (leverages on FP64 MFMA, sampling by exponential keys)
+  forces a fit with energies, forces and virials (2e4 atoms, 6.2e4
+         derivative observations, d = 400, M = 4000), FP64 and mixed
   sweep  64 uneven fits of a hyperparameter sweep, one HIP graph per fit
          replayed on several streams (FP32 QR + FP64 refinement), against the
          same fits run one after another in plain FP64
@@ -17,7 +19,7 @@ M = 1e4 sparse points, zeta = 4, FP64, beside the three forms around it:
 
 Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms mixed,bf16,fp16,int8,cur,sweep,serve | none]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms mixed,bf16,fp16,int8,cur,forces,sweep,serve | none]
                   [--workload realistic_fp64|tiny_fp64] [--no-cpu-baseline]
 
 A step is one whole fit on inputs already resident in HBM; `value` is the FP64
@@ -111,6 +113,60 @@ def bench_cur(args, X, n, d, M, host_inputs):
         out["rows_differing_from_oracle_selection"] = int(len(np.setxor1d(idx.cpu().numpy(), z["sampled_idx"])))
         out["oracle_seconds"] = json.loads(str(z["meta"]))["leverage_s"]
     log(f"[bench] cur: {ms:.2f} ms per selection ({out['tflops']:.1f} TFLOP/s)")
+    return out
+
+
+def bench_forces(args, gap, log):
+    """The energies-forces-virials workload (synth.WORKLOADS["forces_fp64"]): whole
+    fits (gap_build_knm_obs + gap_solve) in FP64 and mixed precision, timed like the
+    main fit; c against the oracle's reference fit when it is available."""
+    import numpy as np
+    import torch
+
+    from paper_2207_03803_amd import synth
+
+    w = dict(synth.WORKLOADS["forces_fp64"])
+    D = synth.make_deriv_inputs(seed=args.seed, **w)
+    dev = "cuda"
+    golden = os.path.join(ROOT, "tests", "golden", "forces_fp64_seed0.npz")
+    z = np.load(golden, allow_pickle=False) if args.seed == 0 and os.path.exists(golden) else None
+    y = torch.from_numpy(z["y"] if z is not None else D.sigma * np.concatenate([D.noise_E, D.noise_D])).to(dev)
+    X, offs, XM = (torch.from_numpy(a).to(dev) for a in (D.X, D.offsets, D.XM))
+    sig = torch.from_numpy(D.sigma).to(dev)
+    obs = {k: torch.from_numpy(getattr(D, k)).to(dev)
+           for k in ("x_grad", "grad_atom", "obs_offsets", "pos_grad", "pos_weight")}
+    M, d, n_pos = D.XM.shape[0], w["d"], len(D.pos_grad)
+    out = {"n_configs": D.n_configs, "n_atoms": D.n_atoms, "n_derivative_obs": D.n_obs, "n_positions": n_pos,
+           "M": M, "d": d, "zeta": w["zeta"], "stacked_matrix": [D.n_configs + D.n_obs + M, M]}
+    kdm_flops = 2.0 * n_pos * M * d + (2.0 * D.n_atoms * M * d if w["zeta"] > 1 else 0.0)
+    for name, prec in (("fp64", gap.GAP_FP64), ("mixed", gap.GAP_MIXED_FP32)):
+        with torch.cuda.stream(torch.cuda.Stream()):
+            h = gap.Handle(gap.params(d, w["zeta"], w["sigma_w"], w["jitter"], precision=prec,
+                                      flags=gap.GAP_FLAG_TIMING, max_refine_iters=30, refine_tol=1e-12))
+            h.set_tuning(qr_free_cus=32)
+            h.alloc_workspace_obs(D.n_configs, D.n_atoms, D.n_obs, n_pos, M)
+            c = torch.empty(M, dtype=torch.float64, device=dev)
+            stage_sum, per = {}, []
+            for i in range(args.warmup + args.steps):
+                ts = time.perf_counter()
+                h.build_knm_obs(X, offs, obs, XM, sig)
+                h.solve(y, c, info=False)
+                st = h.stage_times()
+                if i >= args.warmup:
+                    per.append(time.perf_counter() - ts)
+                    for k, v in st.items():
+                        stage_sum[k] = stage_sum.get(k, 0.0) + v
+            status, info = h.sync()
+            h.close()
+        stages = {k: v / args.steps for k, v in stage_sum.items() if v > 0}
+        r = {"s_per_fit": float(np.mean(per)), "median_ms": 1e3 * float(np.median(per)), "stages_ms": stages,
+             "status": gap.status_string(status), "refine_iters": info.refine_iters,
+             "kdm_tflops": kdm_flops / (stages["kdm"] / 1e3) / 1e12}
+        if z is not None:
+            r["c_rel_err_vs_oracle"] = float(np.linalg.norm(c.cpu().numpy() - z["c"]) / np.linalg.norm(z["c"]))
+        out[name] = r
+        log(f"[bench] forces {name}: {1e3 * r['s_per_fit']:.1f} ms per fit (derivative rows "
+            f"{stages['kdm']:.1f} ms, {r['kdm_tflops']:.1f} TFLOP/s)")
     return out
 
 
@@ -241,7 +297,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="realistic_fp64")
-    ap.add_argument("--forms", default="mixed,bf16,fp16,int8,cur,sweep,serve",
+    ap.add_argument("--forms", default="mixed,bf16,fp16,int8,cur,forces,sweep,serve",
                     help="comma-separated forms to measure beside the FP64 fit, or none")
     ap.add_argument("--inputs", choices=("host", "device"), default="host",
                     help="host: numpy descriptors (the arrays the oracle's full-size reference fit used); "
@@ -460,6 +516,12 @@ def main():
         rooflines.append({"stage": "cur", "kernel": "cur_gram_kernel + cur_proj_kernel (+ selection)",
                           "bound": "mfma", "dtype": "f64", "achieved": r["tflops"], "peak": PEAK_FP64_MFMA / 1e12,
                           "unit": "TFLOP/s", "frac": r["tflops"] / (PEAK_FP64_MFMA / 1e12)})
+    if "forces" in forms:
+        extra["forces"] = bench_forces(args, gap, log)
+        r = extra["forces"]["fp64"]
+        rooflines.append({"stage": "kdm", "kernel": "kdm_kernel (+ the power block)", "bound": "mfma",
+                          "dtype": "f64", "achieved": r["kdm_tflops"], "peak": PEAK_FP64_MFMA / 1e12,
+                          "unit": "TFLOP/s", "frac": r["kdm_tflops"] / (PEAK_FP64_MFMA / 1e12)})
     if "sweep" in forms or "serve" in forms:
         from paper_2207_03803_amd import serve, sweep
 

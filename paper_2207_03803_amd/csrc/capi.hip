@@ -644,20 +644,22 @@ static gap_status build_derivatives(gap_handle h)
     h->mark(9, false);
     double *D = nullptr;
     if (p.zeta > 1) {
+        // row-major D[i * M + j]: the sparse points as the unit rows and the atoms as the
+        // columns of the column-major output, so that a position's row of D is contiguous
         D = h->at<double>(L.off_D);
         KnmArgs k{};
-        k.X = h->x_atoms;
+        k.X = h->x_sparse;
         k.offsets = nullptr;
-        k.n_rows_unit = L.n_atoms;
-        k.XM = h->x_sparse;
-        k.M = L.M;
+        k.n_rows_unit = L.M;
+        k.XM = h->x_atoms;
+        k.M = L.n_atoms;
         k.d = p.d;
         k.zeta = p.zeta - 1;
         k.sw2 = 1.0;
         k.out = D;
-        k.ldo = L.n_atoms;
+        k.ldo = L.M;
         k.status = h->status();
-        GAP_TRY(dev(launch_knm(k, (L.n_atoms + KNM_BM - 1) / KNM_BM, s)));
+        GAP_TRY(dev(launch_knm(k, (L.M + KNM_BM - 1) / KNM_BM, s)));
     }
     const KnmPlan kp = plan_of_d(h);
     GAP_TRY(dev(launch_plan_tiles(o.obs_offsets, L.n_obs, L.n_pos, kp, L.max_tiles_d, h->status(), s)));
@@ -681,7 +683,7 @@ static gap_status build_derivatives(gap_handle h)
     a.pos_weight = o.pos_weight;
     a.grad_atom = o.grad_atom;
     a.D = D;
-    a.ldd = L.n_atoms;
+    a.ldd = L.M;
     a.n_grad = o.n_grad;
     a.n_src = L.n_atoms;
     GAP_TRY(dev(launch_kdm(a, L.max_tiles_d, s)));

@@ -38,7 +38,7 @@ struct KnmArgs {
     const int64_t *pos_grad;   // [n_pos]
     const double *pos_weight;  // [n_pos]
     const int64_t *grad_atom;  // [n_grad]
-    const double *D;           // column-major, D[j * ldd + i] = (x_i . x_j)^(zeta - 1); null: 1 (zeta = 1)
+    const double *D;           // row-major, D[i * ldd + j] = (x_i . x_j)^(zeta - 1); null: 1 (zeta = 1)
     int64_t ldd;
     int64_t n_grad, n_src;     // bounds of pos_grad and grad_atom values (out of range: zero row, DST_EINVAL)
 };

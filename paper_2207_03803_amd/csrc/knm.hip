@@ -309,14 +309,30 @@ DEV void knm_body(const KnmArgs &a, int64_t bid)
     // the actual count so that all eight XCDs get an equal share of the tiles.
     const bool unit = (a.offsets == nullptr);
     const int64_t n_tiles = unit ? (a.n_rows_unit + KNM_BM - 1) / KNM_BM : (int64_t)*a.n_tiles_dev;
-    const int64_t total = n_tiles * a.n_ct;
-    const int64_t total_pad = (total + 7) & ~int64_t(7);
-    if (bid >= total_pad)
-        return;
-    const int64_t lw = xcd_remap(bid, total_pad);
-    if (lw >= total)
-        return;
-    const int64_t t = lw / a.n_ct, ct = lw % a.n_ct;
+    int64_t t, ct;
+    if constexpr (DERIV) {
+        // tiles dealt to the XCDs in turn (tile t to XCD t mod 8), each tile's column
+        // tiles on its XCD in order: observations of very different sizes (multi-chunk
+        // virials beside small force components) spread evenly over the XCDs
+        const int64_t tiles8 = (n_tiles + 7) / 8;
+        if (bid >= tiles8 * 8 * a.n_ct)
+            return;
+        const int64_t x = bid & 7, q = bid >> 3;
+        t = 8 * (q / a.n_ct) + x;
+        ct = q % a.n_ct;
+        if (t >= n_tiles)
+            return;
+    } else {
+        const int64_t total = n_tiles * a.n_ct;
+        const int64_t total_pad = (total + 7) & ~int64_t(7);
+        if (bid >= total_pad)
+            return;
+        const int64_t lw = xcd_remap(bid, total_pad);
+        if (lw >= total)
+            return;
+        t = lw / a.n_ct;
+        ct = lw % a.n_ct;
+    }
     const int64_t col0 = ct * KNM_BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / KS::WN, wn = wave % KS::WN;
@@ -490,7 +506,7 @@ DEV void knm_body(const KnmArgs &a, int64_t bid)
                                 if constexpr (DERIV) {
                                     // (rowf / rowatom were written before the GEMM's barriers)
                                     const int64_t at = rowatom[r], colg = col0 + p * EPC + cl;
-                                    const double dv = (a.D && at >= 0 && colg < a.M) ? a.D[colg * a.ldd + at] : 1.0;
+                                    const double dv = (a.D && at >= 0 && colg < a.M) ? a.D[at * a.ldd + colg] : 1.0;
                                     v = v * (rowf[r] * dv);
                                 }
                                 E[r * EPLD + cl] = v;
@@ -736,8 +752,7 @@ hipError_t launch_knm_group(const KnmArgs *fits, const int64_t *max_tiles, int n
 hipError_t launch_kdm(KnmArgs a, int64_t max_tiles, hipStream_t s)
 {
     a.n_ct = (a.M + 63) / 64;
-    const int64_t total = max_tiles * a.n_ct;
-    a.total_pad = (total + 7) & ~int64_t(7);
+    a.total_pad = (max_tiles + 7) / 8 * 8 * a.n_ct;  // whole rounds of 8 tiles (see knm_body)
     if (a.total_pad == 0)
         return hipSuccess;
     hipLaunchKernelGGL(kdm_kernel, dim3((unsigned)a.total_pad), dim3(256), 0, s, a);

@@ -309,6 +309,12 @@ def make_deriv_inputs(n_configs: int, atoms=(20, 60), d: int = 64, M: int = 128,
     ks = np.concatenate([np.arange(n, dtype=np.int64)[:, None], nb], axis=1)  # [n, nn + 1]
     grad_k = np.repeat(ks.reshape(-1), 3)
     grad_alpha = np.tile(np.arange(3, dtype=np.int64), n * (n_neigh + 1))
+    # store the gradient rows by (configuration, alpha, k, i): the rows of one force
+    # component, and those of one virial component, are then contiguous
+    g_cfg = np.repeat(np.arange(n_configs, dtype=np.int64), counts)[grad_atom]
+    order = np.lexsort((grad_atom, grad_k, grad_alpha, g_cfg))
+    x_grad = x_grad[order]
+    grad_atom, grad_k, grad_alpha = grad_atom[order], grad_k[order], grad_alpha[order]
     # force rows (k, alpha), in atom order: positions = gradient rows with that (k, alpha), ascending
     fkey = grad_k * 3 + grad_alpha
     order = np.argsort(fkey, kind="stable")
@@ -321,7 +327,7 @@ def make_deriv_inputs(n_configs: int, atoms=(20, 60), d: int = 64, M: int = 128,
     if virials:
         # virial (alpha, beta), alpha <= beta: -sum_k r_{k, alpha} dE / dr_{k, beta}
         comps = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
-        g_cfg = np.repeat(np.arange(n_configs, dtype=np.int64), counts)[grad_atom]
+        g_cfg = np.repeat(np.arange(n_configs, dtype=np.int64), counts)[grad_atom]  # sorted
         vp, vw, vs = [], [], []
         for a in range(n_configs):
             rows = np.nonzero(g_cfg == a)[0]

@@ -22,12 +22,17 @@ the seeded generators; nothing here touches the GPU library.  Two parts:
   ``synth.cur_draws(n_atoms, 0)`` and by largest leverage, with the keys at the
   threshold, in ``cur_realistic_seed0.npz``.  A few minutes.
 
+* ``forces``: the energies-forces-virials workload (500 configurations of 20..60
+  atoms, 12 neighbours, d = 400, M = 4000, zeta = 4; ``synth.make_deriv_inputs``,
+  seed 0): y of every row, the oracle's c, the minimum loss and kappa_2(A), in
+  ``forces_fp64_seed0.npz``.  About half an hour.
+
 Targets are y = K_NM c_true + sigma * noise with K_NM from the oracle (the
 model's prediction with c_true, Eqs. 1-2), and the fit follows the oracle's
 stages in the paper's order (Sec. Theory): K_NM, K_MM + jitter, Cholesky, the
 stacked problem, Householder QR with Q^T b, back-substitution.
 
-Usage: python tests/golden/make_reference_fits.py {realistic|sweep|cur} [--log FILE]
+Usage: python tests/golden/make_reference_fits.py {realistic|sweep|cur|forces} [--log FILE]
 """
 from __future__ import annotations
 
@@ -154,9 +159,48 @@ def run_cur(log):
     log("wrote cur_realistic_seed0.npz: " + json.dumps(meta))
 
 
+def run_forces(log):
+    w = dict(synth.WORKLOADS["forces_fp64"])
+    t0 = time.time()
+    D = synth.make_deriv_inputs(seed=0, **w)
+    log(f"inputs: {D.n_configs} configs, {D.n_atoms} atoms, {D.n_obs} derivative observations over "
+        f"{len(D.pos_grad)} positions in {time.time() - t0:.0f} s")
+    orc = oracle.Oracle()
+    zeta, sigma_w, jitter = w["zeta"], w["sigma_w"], w["jitter"]
+    t0 = time.time()
+    y = oracle.deriv_targets(orc, D, zeta, sigma_w)
+    t_y = time.time() - t0
+    log(f"targets in {t_y:.0f} s")
+    t0 = time.time()
+    Knm = orc.knm(D.X, D.offsets, D.XM, zeta, sigma_w)
+    Kd = orc.kdm(D.X, D.x_grad, D.grad_atom, D.obs_offsets, D.pos_grad, D.pos_weight, D.XM, zeta, sigma_w)
+    t_k = time.time() - t0
+    log(f"K_NM and derivative rows in {t_k:.0f} s")
+    K = np.vstack([Knm, Kd])
+    del Knm, Kd
+    rc, L, fail = orc.cholesky(orc.kmm(D.XM, zeta, sigma_w, jitter))
+    assert rc == oracle.ORACLE_OK, (rc, fail)
+    A, b = orc.stack(K, D.sigma, y, L)
+    del K
+    t0 = time.time()
+    A, qtb, _ = orc.householder_qr(A, b, overwrite=True)
+    t_qr = time.time() - t0
+    M = D.XM.shape[0]
+    c = orc.back_substitution(A, qtb[:M])
+    loss_tail = float(np.sum(qtb[M:] ** 2))
+    smax, smin, _ = orc.singular_extremes(A[:M])
+    log(f"QR in {t_qr:.0f} s; kappa {smax / smin:.3e}")
+    meta = dict(workload="forces_fp64", seed=0, generator="synth.make_deriv_inputs", n_configs=D.n_configs,
+                n_atoms=D.n_atoms, n_obs=D.n_obs, n_pos=len(D.pos_grad), M=M, d=w["d"], zeta=zeta,
+                kappa=smax / smin, loss_tail=loss_tail, targets_s=t_y, rows_s=t_k, qr_s=t_qr, threads=os.cpu_count())
+    np.savez(os.path.join(HERE, "forces_fp64_seed0.npz"), meta=json.dumps(meta), y=y, c=c, loss_tail=loss_tail,
+             smax=smax, smin=smin)
+    log("wrote forces_fp64_seed0.npz: " + json.dumps(meta))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("part", choices=["realistic", "sweep", "cur"])
+    ap.add_argument("part", choices=["realistic", "sweep", "cur", "forces"])
     ap.add_argument("--log", default=None)
     a = ap.parse_args()
     fh = open(a.log, "a") if a.log else None
@@ -168,7 +212,7 @@ def main():
             fh.write(line + "\n")
             fh.flush()
 
-    {"realistic": run_realistic, "sweep": run_sweep, "cur": run_cur}[a.part](log)
+    {"realistic": run_realistic, "sweep": run_sweep, "cur": run_cur, "forces": run_forces}[a.part](log)
 
 
 if __name__ == "__main__":

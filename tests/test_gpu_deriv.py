@@ -144,3 +144,50 @@ def test_low_precision_forms_reject_derivative_observations():
             _build(h, D)
         assert e.value.status == gap.GAP_EINVAL
         h.close()
+
+
+def test_forces_workload_at_full_size(orc):
+    """The energies-forces-virials workload at full size (500 configurations,
+    19,537 atoms, 61,611 derivative observations over 2.3e6 positions, d = 400,
+    M = 4000, zeta = 4) against the oracle's reference fit
+    (tests/golden/forces_fp64_seed0.npz): c within 1e-10 (FP64) and 1e-8 (mixed),
+    the minimum loss, and 24 sampled derivative rows against the oracle one by one."""
+    import os
+
+    import torch
+
+    from paper_2207_03803_amd import gap
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "forces_fp64_seed0.npz")
+    z = np.load(path, allow_pickle=False)
+    w = dict(synth.WORKLOADS["forces_fp64"])
+    D = synth.make_deriv_inputs(seed=0, **w)
+    log(f"forces workload: {D.n_atoms} atoms, {D.n_obs} derivative observations, {len(D.pos_grad)} positions")
+    y = to_dev(z["y"])
+    rng = np.random.default_rng(12)
+    pick = np.sort(np.concatenate([rng.choice(3 * D.n_atoms, 16, replace=False),
+                                   3 * D.n_atoms + rng.choice(6 * D.n_configs, 8, replace=False)]))
+    sizes = np.diff(D.obs_offsets)[pick]
+    sub_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    sub_pos = np.concatenate([np.arange(D.obs_offsets[o], D.obs_offsets[o + 1]) for o in pick])
+    ref_rows = orc.kdm(D.X, D.x_grad, D.grad_atom, sub_off, D.pos_grad[sub_pos], D.pos_weight[sub_pos], D.XM,
+                       w["zeta"], w["sigma_w"])
+    for prec in (gap.GAP_FP64, gap.GAP_MIXED_FP32):
+        h = _handle(D, w["zeta"], precision=prec, max_refine_iters=30, refine_tol=1e-12)
+        h.set_tuning(qr_free_cus=32)
+        _build(h, D)
+        if prec == gap.GAP_FP64:
+            rows = _rows(h, D)[D.n_configs + pick] * D.sigma_D[pick][:, None]
+            err_rows = np.max(np.abs(rows - ref_rows)) / np.max(np.abs(ref_rows))
+        c = torch.empty(D.XM.shape[0], dtype=torch.float64, device="cuda")
+        info = h.solve(y, c)
+        err = float(np.linalg.norm(c.cpu().numpy() - z["c"]) / np.linalg.norm(z["c"]))
+        lerr = abs(info.residual_norm2 - float(z["loss_tail"])) / float(z["loss_tail"])
+        log(f"  precision {prec}: {gap.status_string(info.device_status)}, {info.refine_iters} refinement steps; "
+            f"c rel err vs oracle {err:.2e}; loss {lerr:.2e}; eta {info.grad_rel:.1e}"
+            + (f"; sampled rows {err_rows:.2e}" if prec == gap.GAP_FP64 else ""))
+        assert info.device_status == gap.GAP_OK
+        assert err <= (1e-10 if prec == gap.GAP_FP64 else 1e-8)
+        assert lerr <= 1e-9
+        h.close()
+    assert err_rows <= 1e-13
