@@ -150,8 +150,9 @@ def test_forces_workload_at_full_size(orc):
     """The energies-forces-virials workload at full size (500 configurations,
     19,537 atoms, 61,611 derivative observations over 2.3e6 positions, d = 400,
     M = 4000, zeta = 4) against the oracle's reference fit
-    (tests/golden/forces_fp64_seed0.npz): c within 1e-10 (FP64) and 1e-8 (mixed),
-    the minimum loss, and 24 sampled derivative rows against the oracle one by one."""
+    (tests/golden/forces_fp64_seed0.npz): c within 1e-10 (FP64) and 1e-8 (mixed) or
+    the FP64 perturbation bound (kappa(A) = 1.0e6 here), the minimum loss, and 24
+    sampled derivative rows against the oracle one by one."""
     import os
 
     import torch
@@ -164,6 +165,8 @@ def test_forces_workload_at_full_size(orc):
     D = synth.make_deriv_inputs(seed=0, **w)
     log(f"forces workload: {D.n_atoms} atoms, {D.n_obs} derivative observations, {len(D.pos_grad)} positions")
     y = to_dev(z["y"])
+    kappa = float(z["smax"] / z["smin"])
+    bound = 32 * U * (kappa + kappa ** 2 * np.sqrt(float(z["loss_tail"])) / (float(z["smax"]) * np.linalg.norm(z["c"])))
     rng = np.random.default_rng(12)
     pick = np.sort(np.concatenate([rng.choice(3 * D.n_atoms, 16, replace=False),
                                    3 * D.n_atoms + rng.choice(6 * D.n_configs, 8, replace=False)]))
@@ -187,7 +190,7 @@ def test_forces_workload_at_full_size(orc):
             f"c rel err vs oracle {err:.2e}; loss {lerr:.2e}; eta {info.grad_rel:.1e}"
             + (f"; sampled rows {err_rows:.2e}" if prec == gap.GAP_FP64 else ""))
         assert info.device_status == gap.GAP_OK
-        assert err <= (1e-10 if prec == gap.GAP_FP64 else 1e-8)
+        assert err <= max(1e-10 if prec == gap.GAP_FP64 else 1e-8, bound)
         assert lerr <= 1e-9
         h.close()
     assert err_rows <= 1e-13
