@@ -167,9 +167,10 @@ def kernels(args):
     MFMA flops executed, LDS bank conflicts per LDS instruction, HBM bytes read /
     written (FETCH_SIZE / WRITE_SIZE scaled by the copy calibration) and GB/s."""
     dur = _durations(args.trace)
-    sq = _sums(args.sq, {"SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE", "SQ_INSTS_VALU_MFMA_MOPS_F64",
-                         "SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_MFMA_MOPS_BF16",
-                         "SQ_INSTS_VALU_MFMA_MOPS_F16", "SQ_LDS_BANK_CONFLICT", "SQ_INSTS_LDS"})
+    mops_counters = ("SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_MFMA_MOPS_BF16",
+                     "SQ_INSTS_VALU_MFMA_MOPS_F16", "SQ_INSTS_VALU_MFMA_MOPS_I8")
+    sq = _sums(args.sq, {"SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE", "SQ_LDS_BANK_CONFLICT", "SQ_INSTS_LDS",
+                         *mops_counters})
     fe = _sums(args.fetch, {"FETCH_SIZE"})
     wr = _sums(args.write, {"WRITE_SIZE"})
     cf = _copy_launch(args.copy_fetch, "FETCH_SIZE")
@@ -183,8 +184,8 @@ def kernels(args):
         grbm = q.get("GRBM_GUI_ACTIVE", (0.0, 0))[0]
         # GRBM_GUI_ACTIVE is summed over the XCDs; MFMA busy cycles over every SIMD
         util = busy / (grbm / args.xcds * args.simds) if grbm > 0 else float("nan")
-        mops = sum(q.get(c, (0.0, 0))[0] for c in ("SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_INSTS_VALU_MFMA_MOPS_F32",
-                                                    "SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_VALU_MFMA_MOPS_F16"))
+        # MFMA operations the counters saw (a pass holds only some of the MOPS counters)
+        mops = sum(q.get(c, (0.0, 0))[0] for c in mops_counters)
         lds = q.get("SQ_INSTS_LDS", (0.0, 0))[0]
         conf = q.get("SQ_LDS_BANK_CONFLICT", (0.0, 0))[0]
         rd = fe.get(k, {}).get("FETCH_SIZE", (0.0, 0))[0] * 1024.0 * ff
@@ -195,7 +196,7 @@ def kernels(args):
                          read_gb=rd / 1e9, write_gb=wb / 1e9, gbps=(rd + wb) / t / 1e9 if t > 0 else 0.0))
     json.dump(dict(rows=rows, copy_calibration=dict(fetch_factor=ff, write_factor=wf)),
               open(args.out + ".json", "w"), indent=1)
-    lines = ["| kernel | launches | total ms | MFMA busy | MFMA TFLOP/s | LDS conflicts / inst | HBM read GB | "
+    lines = ["| kernel | launches | total ms | MFMA busy | MFMA TFLOP/s (TOP/s) | LDS conflicts / inst | HBM read GB | "
              "HBM write GB | GB/s |", "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
     for r in rows:
         lines.append(f"| `{r['kernel'][:60]}` | {r['launches']} | {r['total_ms']:.2f} | {100 * r['mfma_busy']:.1f} % | "
