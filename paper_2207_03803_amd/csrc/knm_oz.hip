@@ -22,22 +22,20 @@
 namespace gap {
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int OZ_S = 7;                          // slices
-constexpr int OZ_PAIRS = OZ_S * (OZ_S + 1) / 2;  // slice products kept
-constexpr int OZ_BITS = 54;                      // |N| < 2^54
+constexpr int OZ_S = 7;      // slices
+constexpr int OZ_BITS = 54;  // |N| < 2^54
+constexpr int OZ_KC = 32;    // bytes of k per chunk of the slice layout (one MFMA's k)
 
-// (t, u) of the slice products, by diagonal delta = t + u from the smallest
-// terms (delta = 6) to the largest, t ascending within a diagonal.
-__constant__ int8_t oz_pt[OZ_PAIRS] = {0, 1, 2, 3, 4, 5, 6, 0, 1, 2, 3, 4, 5, 0, 1, 2, 3, 4, 0, 1, 2, 3, 0, 1, 2, 0, 1, 0};
-__constant__ int8_t oz_pu[OZ_PAIRS] = {6, 5, 4, 3, 2, 1, 0, 5, 4, 3, 2, 1, 0, 4, 3, 2, 1, 0, 3, 2, 1, 0, 2, 1, 0, 1, 0, 0};
-
-int knm_oz_dpad(int d) { return (d + 63) / 64 * 64; }
+int knm_oz_dpad(int d) { return (d + OZ_KC - 1) / OZ_KC * OZ_KC; }
 int knm_oz_slices() { return OZ_S; }
 
 // One wave per row: the row's exponent, then its digits, four entries (one
-// 32-bit word per slice) per lane and step.  Slice t of row r starts at
-// out + t * rows * dp + r * dp; entries k >= d are zero.
+// 32-bit word per slice) per lane and step.  Layout, chunk-major so that the
+// 32-byte k-chunks of consecutive rows are contiguous: byte k of slice t of
+// row r is at out + t * rows * dp + (k / 32) * rows * 32 + r * 32 + k % 32.
+// Entries k >= d are zero.
 __global__ __launch_bounds__(256) void oz_split_kernel(const double *__restrict__ x, int64_t rows, int d, int dp,
                                                        int8_t *__restrict__ out, int32_t *__restrict__ ex)
 {
@@ -73,47 +71,53 @@ __global__ __launch_bounds__(256) void oz_split_kernel(const double *__restrict_
                 }
                 word[0] |= (uint32_t)(uint8_t)(int8_t)n << (8 * q);
             }
+            const int64_t pos = (int64_t)(w / 8) * rows * OZ_KC + r * OZ_KC + 4 * (w % 8);
 #pragma unroll
             for (int t = 0; t < OZ_S; ++t)
-                reinterpret_cast<uint32_t *>(out + t * slice + r * (int64_t)dp)[w] = word[t];
+                *reinterpret_cast<uint32_t *>(out + t * slice + pos) = word[t];
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Tile: the plan's tile of up to 256 atoms (whole configurations) x 128 sparse
-// points, 512 threads = 8 waves of 64 x 64 (4 along the atoms, 2 along the
-// sparse points), each a 4 x 4 grid of 16 x 16 INT32 accumulator blocks and the
-// matching FP64 sums.  A workgroup takes OCT consecutive column tiles of one
-// atom tile.  The k loop runs over the 28 slice products, each in steps of 64
-// bytes (one MFMA), staged in LDS as [row][k] with rows padded to 80 bytes; the
-// next step's global loads are in flight during the MFMAs.  After the last
-// product of a diagonal, its INT32 sums are scaled by 2^(-8 delta) into the FP64
-// sums (exact).
+// Tile: 128 atoms (a chunk of the plan's tile of up to 256 atoms, whole
+// configurations) x 64 sparse points, 512 threads = 8 waves of 32 x 32 (4 along
+// the atoms, 2 along the sparse points), two waves per SIMD.  Each wave holds the
+// seven diagonals' exact INT32 sums of its 32 x 32 outputs at once (seven
+// accumulator blocks, 112 registers), so the k loop streams every operand byte
+// once: a stage holds one 32-byte k-chunk of all seven slices of both operands
+// (42 KB), and its 28 slice products run from LDS while the next stage's direct
+// global-to-LDS loads are in flight (two stages).  Per k-chunk a wave reads its
+// seven B fragments once and keeps them, and one A fragment per slice t.  The
+// diagonals are folded into FP64 (exact scaling by 2^(-8 delta)) once, after the
+// k loop.  A workgroup takes OCT consecutive column tiles of one atom tile, and
+// for each column tile the atom tile's chunks of 128 rows in order; a
+// configuration that runs across a chunk boundary carries its partial sums in
+// LDS.
 //
-// Operand layout of v_mfma_i32_16x16x64_i8: lane l supplies row (A) or column
-// (B) l % 16 and the sixteen k of group l / 16; A and B use the same k
-// assignment.  Accumulator element e of lane l is C(4 (l / 16) + e, l % 16).
+// Operand layout of v_mfma_i32_32x32x32_i8: lane l supplies row (A) or column
+// (B) l % 32 and the sixteen k of half l / 32; accumulator element e of lane l
+// is C(8 (e / 4) + 4 (l / 32) + e % 4, l % 32).
 // ---------------------------------------------------------------------------
-constexpr int OBM = KNM_BM;   // atoms per tile (the plan's tiles)
-constexpr int OBN = 128;      // sparse points per tile
-constexpr int OBK = 64;       // k (bytes) per step
-constexpr int OLDK = OBK + 16;
+constexpr int OBM = 128;                 // atoms per chunk
+constexpr int OBN = 64;                  // sparse points per tile
 constexpr int ONT = 512;
-constexpr int OCT = 8;        // column tiles per workgroup
-constexpr int OEPC = 32;      // epilogue columns per pass
+constexpr int OCT = 8;                   // column tiles per workgroup
+constexpr int OSA = OBM * OZ_KC;         // one slice's A rows in a stage: 4 KB
+constexpr int OSB = OBN * OZ_KC;         // one slice's B rows: 2 KB
+constexpr int OSTAGE = OZ_S * (OSA + OSB);  // A slices 0..6, then B slices 0..6: 42 KB
+constexpr int OITEMS = OSTAGE / 1024;    // 1 KB loads per stage: 28 of A, then 14 of B
+constexpr int OEPC = 32;                 // epilogue columns per pass
 constexpr int OEPLD = OEPC + 1;
-constexpr int OA_BYTES = OBM * OLDK, OB_BYTES = OBN * OLDK, OSTAGE = OA_BYTES + OB_BYTES;
-constexpr int O_LDS_GEMM = 2 * OSTAGE;
-constexpr int O_LDS_EPI = OBM * OEPLD * 8;
-constexpr int O_LDS = O_LDS_GEMM > O_LDS_EPI ? O_LDS_GEMM : O_LDS_EPI;
-static_assert(OBM == 256 && ONT == 512, "loader mapping assumes 256 atoms and 512 threads");
+static_assert(ONT == 512 && OSA == 4 * 1024 && OSB == 2 * 1024, "load mapping: A parts = wave % 4, B = wave % 2");
+static_assert(2 * OBM == KNM_BM, "a plan tile is two chunks (or one configuration in several)");
 
 struct KnmOzArgs {
-    const int8_t *X, *XM;     // slices: X + t * x_slice + atom * dp, XM + t * xm_slice + col * dp
+    const int8_t *X, *XM;     // slices (chunk-major, see oz_split_kernel)
     int64_t x_slice, xm_slice;
+    int64_t x_chunk, xm_chunk;  // rows * 32: bytes between consecutive k-chunks of a slice
     const int32_t *xe, *xme;  // row exponents
-    int dp;
+    int nk;                   // k-chunks per row
     const int64_t *offsets;
     const int32_t *tile_start, *cfg_list, *n_tiles_dev;
     int64_t M;
@@ -125,6 +129,11 @@ struct KnmOzArgs {
     int64_t n_ct, n_cg;
 };
 
+// Half of a stage row that holds k-half h of row r: the halves of rows are
+// swapped in a pattern that gives the 16 rows read by one group of lanes
+// distinct banks.
+DEV int oz_half(int r, int h) { return h ^ (((r >> 2) ^ (r >> 3)) & 1); }
+
 DEV double ipow_oz(double g, int zeta)
 {
     double p = g;
@@ -133,13 +142,18 @@ DEV double ipow_oz(double g, int zeta)
     return p;
 }
 
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(3))) char lds_char;
+
 __global__ __launch_bounds__(ONT) __attribute__((amdgpu_waves_per_eu(2, 2))) void knm_oz_kernel(KnmOzArgs a)
 {
-    __shared__ __align__(16) unsigned char lds[O_LDS];
+    // two stages as separate arrays: loads into one never alias the reads of the other
+    __shared__ __align__(16) unsigned char stage0[OSTAGE], stage1[OSTAGE];
+    __shared__ double E[OBM * OEPLD];
+    __shared__ double carry[2][OBN];  // partial sums of the configuration crossing a chunk boundary
     __shared__ int32_t sstart[KNM_MAX_SEG + 1];
     __shared__ int64_t sbase[KNM_MAX_SEG];
     __shared__ int32_t srow[KNM_MAX_SEG];
-    __shared__ double carry[OBN];
     __shared__ int32_t scan[KNM_MAX_SEG];
     __shared__ int32_t sexp[OBM];
     __shared__ int32_t cexp[OBN];
@@ -202,9 +216,10 @@ __global__ __launch_bounds__(ONT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         }
         return;
     }
-    const bool multi = n_at > OBM;  // then n_seg == 1: one configuration in several atom chunks
+    const bool multi = n_at > KNM_BM;  // then n_seg == 1: one configuration in several chunks
 
-    auto atom_of = [&](int r) -> int64_t {
+    // the segment holding tile row r (r < n_at)
+    auto seg_of = [&](int64_t r) -> int {
         int lo = 0, hi = n_seg - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -213,173 +228,149 @@ __global__ __launch_bounds__(ONT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             else
                 hi = mid - 1;
         }
-        return sbase[lo] + (r - sstart[lo]);
+        return lo;
     };
-    // this thread's two A chunks (rows ra0, ra0 + 128; 16-byte part pa) and one B chunk (row rb, part pb)
-    const int ra0 = tid >> 2, pa = tid & 3;
-    const int rb = tid >> 2, pb = tid & 3;
-    const int nk = a.dp / OBK;
-    const int n_steps = OZ_PAIRS * nk;
+    auto atom_of = [&](int64_t r) -> int64_t {  // descriptor row of tile row r, -1 past the tile
+        if (r >= n_at)
+            return -1;
+        if (multi)
+            return sbase[0] + r;
+        const int s = seg_of(r);
+        return sbase[s] + (r - sstart[s]);
+    };
 
-    i32x4 acc[4][4];
-    double sum[4][4][4];
+    // Direct global-to-LDS loads of 1 KB each (lane l lands at 16 l): load i of a
+    // stage is A slice i / 4, rows 32 (i % 4) ..  (i < 28), else B slice (i - 28) / 2,
+    // rows 32 ((i - 28) % 2) ..; wave w issues loads w, w + 8, .., so it always
+    // loads the A rows 32 (w % 4) + l / 2 and the B rows 32 (w % 2) + l / 2, lane l
+    // the k-half that lands in stage half l % 2 (oz_half).
+    const int arow = 32 * (wave & 3) + (lane >> 1), brow = 32 * (wave & 1) + (lane >> 1);
+    const int ahalf = oz_half(arow, lane & 1), bhalf = oz_half(brow, lane & 1);
+    // fragment reads: A rows 32 wm + l % 32, B columns 32 wn + l % 32
+    const int fr = 32 * wm + (lane & 31), fc = 32 * wn + (lane & 31);
+    const int a_off = fr * OZ_KC + 16 * oz_half(fr, lane >> 5);
+    const int b_off = OZ_S * OSA + fc * OZ_KC + 16 * oz_half(fc, lane >> 5);
+    const int nk = a.nk;
+
+    i32x16 acc[OZ_S];
+    int chunk_no = 0;
     for (int64_t ct = ct_lo; ct < ct_hi; ++ct) {
         const int64_t col0 = ct * OBN;
-        const int64_t colb = col0 + rb;
-        const int8_t *bsrc = (colb < a.M) ? a.XM + colb * (int64_t)a.dp + pb * 16 : nullptr;
-        for (int64_t cs = 0; cs < n_at; cs += OBM) {
-            const bool first = (cs == 0), last = (cs + OBM >= n_at);
-            const int8_t *asrc[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int r = ra0 + 128 * h;
-                asrc[h] = nullptr;
-                if (multi) {
-                    if (cs + r < n_at)
-                        asrc[h] = a.X + (sbase[0] + cs + r) * (int64_t)a.dp + pa * 16;
-                } else if (r < n_at) {
-                    asrc[h] = a.X + atom_of(r) * (int64_t)a.dp + pa * 16;
-                }
+        const int64_t colb = col0 + brow;
+        const int64_t boff = (colb < a.M ? colb * OZ_KC : 0) + 16 * bhalf;  // past M: any valid row
+        for (int64_t cs = 0; cs < n_at; cs += OBM, ++chunk_no) {
+            const int64_t at = atom_of(cs + arow);
+            const int64_t aoff = (at >= 0 ? at * OZ_KC : 0) + 16 * ahalf;  // rows past the tile: unused
+            __syncthreads();  // the previous chunk's epilogue is done with the LDS and the exponents
+            if (tid < OBM) {
+                const int64_t ar = atom_of(cs + tid);
+                sexp[tid] = ar >= 0 ? a.xe[ar] : 0;
+            } else if (tid < OBM + OBN) {
+                const int c = tid - OBM;
+                cexp[c] = (col0 + c < a.M) ? a.xme[col0 + c] : 0;
             }
-            __syncthreads();  // the previous pass's epilogue is done with the LDS and the exponents
-            for (int r = tid; r < OBM; r += ONT) {
-                int64_t at = -1;
-                if (multi) {
-                    if (cs + r < n_at)
-                        at = sbase[0] + cs + r;
-                } else if (r < n_at) {
-                    at = atom_of(r);
-                }
-                sexp[r] = at >= 0 ? a.xe[at] : 0;
-            }
-            if (tid < OBN)
-                cexp[tid] = (col0 + tid < a.M) ? a.xme[col0 + tid] : 0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    acc[i][j] = i32x4{0, 0, 0, 0};
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        sum[i][j][e] = 0.0;
-                }
+            for (int dl = 0; dl < OZ_S; ++dl)
+                acc[dl] = i32x16{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 
-            i32x4 ra[2], rbv;
-            const i32x4 zero4 = {0, 0, 0, 0};
-            auto load = [&](int st) {
-                const int p = st / nk, kc = st - p * nk;
-                const int64_t ka = (int64_t)oz_pt[p] * a.x_slice + kc * OBK;
-                const int64_t kb = (int64_t)oz_pu[p] * a.xm_slice + kc * OBK;
+            auto issue = [&](int kc, unsigned char *stg) {  // k-chunk kc of all fourteen slice tiles
+                const int8_t *xa = a.X + kc * a.x_chunk + aoff;
+                const int8_t *xb = a.XM + kc * a.xm_chunk + boff;
 #pragma unroll
-                for (int h = 0; h < 2; ++h)
-                    ra[h] = asrc[h] ? *reinterpret_cast<const i32x4 *>(asrc[h] + ka) : zero4;
-                rbv = bsrc ? *reinterpret_cast<const i32x4 *>(bsrc + kb) : zero4;
-            };
-            auto store = [&](unsigned char *As, unsigned char *Bs) {
-#pragma unroll
-                for (int h = 0; h < 2; ++h)
-                    *reinterpret_cast<i32x4 *>(As + (ra0 + 128 * h) * OLDK + pa * 16) = ra[h];
-                *reinterpret_cast<i32x4 *>(Bs + rb * OLDK + pb * 16) = rbv;
-            };
-            load(0);
-            store(lds, lds + OA_BYTES);
-            __syncthreads();
-            int p = 0, kc = 0;  // the current step's slice product and k step
-            for (int st = 0; st < n_steps; ++st) {
-                unsigned char *cur = lds + (st & 1) * OSTAGE;
-                unsigned char *nxt = lds + ((st + 1) & 1) * OSTAGE;
-                const bool more = st + 1 < n_steps;
-                if (more)
-                    load(st + 1);
-                const unsigned char *As = cur, *Bs = cur + OA_BYTES;
-                i32x4 af[4], bfr[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    af[i] = *reinterpret_cast<const i32x4 *>(As + (wm * 64 + i * 16 + (lane & 15)) * OLDK +
-                                                             (lane >> 4) * 16);
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    bfr[j] = *reinterpret_cast<const i32x4 *>(Bs + (wn * 64 + j * 16 + (lane & 15)) * OLDK +
-                                                              (lane >> 4) * 16);
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[i], bfr[j], acc[i][j], 0, 0, 0);
-                if (kc == nk - 1 && oz_pu[p] == 0) {
-                    // the diagonal delta = t ends with u = 0: fold it into the FP64 sums
-                    const double sc = ldexp(1.0, -8 * (int)oz_pt[p]);
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-#pragma unroll
-                            for (int e = 0; e < 4; ++e)
-                                sum[i][j][e] = fma((double)acc[i][j][e], sc, sum[i][j][e]);
-                            acc[i][j] = i32x4{0, 0, 0, 0};
-                        }
-                }
-                if (++kc == nk) {
-                    kc = 0;
-                    ++p;
-                }
-                if (more)
-                    store(nxt, nxt + OA_BYTES);
-                __syncthreads();
-            }
-
-            // g = 2^(e_i + e_j - 12) sum, k = sigma_w^2 g^zeta, in registers
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int r = wm * 64 + i * 16 + 4 * (lane >> 4) + e;
-                        const int c = wn * 64 + j * 16 + (lane & 15);
-                        const double g = ldexp(sum[i][j][e], sexp[r] + cexp[c] - 12);
-                        sum[i][j][e] = a.sw2 * ipow_oz(g, a.zeta);
+                for (int m = 0; m < (OITEMS + 7) / 8; ++m) {
+                    const int i = wave + 8 * m;
+                    if (i < 4 * OZ_S) {
+                        const int t = i >> 2;
+                        __builtin_amdgcn_global_load_lds((const void *)(xa + t * a.x_slice),
+                                                         (lds_void *)(stg + t * OSA + 1024 * (i & 3)), 16, 0, 0);
+                    } else if (i < OITEMS) {
+                        const int j = i - 4 * OZ_S, u = j >> 1;
+                        __builtin_amdgcn_global_load_lds((const void *)(xb + u * a.xm_slice),
+                                                         (lds_void *)(stg + OZ_S * OSA + u * OSB + 1024 * (j & 1)),
+                                                         16, 0, 0);
                     }
+                }
+            };
+            auto compute = [&](const unsigned char *stg) {  // the 28 slice products of one k-chunk
+                i32x4 bf[OZ_S];
+#pragma unroll
+                for (int u = 0; u < OZ_S; ++u)
+                    bf[u] = *reinterpret_cast<const i32x4 *>(stg + u * OSB + b_off);
+#pragma unroll
+                for (int t = 0; t < OZ_S; ++t) {
+                    const i32x4 af = *reinterpret_cast<const i32x4 *>(stg + t * OSA + a_off);
+#pragma unroll
+                    for (int u = 0; u + t < OZ_S; ++u)
+                        acc[t + u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af, bf[u], acc[t + u], 0, 0, 0);
+                }
+            };
 
-            double *E = reinterpret_cast<double *>(lds);  // [256][OEPLD], reused after the GEMM
+            __syncthreads();  // the exponents are in place; both stages are free
+            issue(0, stage0);
+            for (int kc = 0; kc < nk; kc += 2) {
+                __syncthreads();  // (waits for this wave's loads) stage 0 holds chunk kc; stage 1 is free
+                if (kc + 1 < nk)
+                    issue(kc + 1, stage1);
+                compute(stage0);
+                if (kc + 1 < nk) {
+                    __syncthreads();  // stage 1 holds chunk kc + 1; stage 0 is free
+                    if (kc + 2 < nk)
+                        issue(kc + 2, stage0);
+                    compute(stage1);
+                }
+            }
+
+            // Epilogue in passes of 32 columns (the waves wn = q): the diagonals folded
+            // into FP64, g = 2^(e_i + e_j - 12) sum, k = sigma_w^2 g^zeta into E, then
+            // the sums over each configuration's atoms in atom order.
+            // This chunk, rows [cs, ce), handles the segments that meet it, the empty ones
+            // at positions in [cs, ce) and, if it is the last, the empty ones at n_at:
+            // segments [s_lo, s_hi) with s_lo the first that ends after cs or starts at
+            // or after it, s_hi the first that starts at or after ce.
+            const int64_t ce = (cs + OBM < n_at) ? cs + OBM : n_at;
+            auto first_seg = [&](auto pred) {  // first s in [0, n_seg) with pred(s), else n_seg
+                int lo = 0, hi = n_seg;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (pred(mid))
+                        hi = mid;
+                    else
+                        lo = mid + 1;
+                }
+                return lo;
+            };
+            const int s_lo = first_seg([&](int q) { return sstart[q] >= cs || sstart[q + 1] > cs; });
+            const int s_hi = (ce == n_at) ? n_seg : first_seg([&](int q) { return sstart[q] >= ce; });
+            const int n_cs = s_hi - s_lo;
+            const double *cin = carry[chunk_no & 1];
+            double *cout = carry[(chunk_no + 1) & 1];
             for (int q = 0; q < OBN / OEPC; ++q) {
-                // columns [32 q, 32 q + 32) are blocks j = 2 (q & 1), 2 (q & 1) + 1 of waves wn = q / 2
-                if (wn == (q >> 1)) {
+                if (wn == q) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
+                    for (int e = 0; e < 16; ++e) {
+                        double s = 0.0;
 #pragma unroll
-                        for (int jj = 0; jj < 2; ++jj) {
-                            const int j = 2 * (q & 1) + jj;
-#pragma unroll
-                            for (int e = 0; e < 4; ++e)
-                                E[(wm * 64 + i * 16 + 4 * (lane >> 4) + e) * OEPLD + jj * 16 + (lane & 15)] =
-                                    sum[i][j][e];
-                        }
+                        for (int dl = OZ_S - 1; dl >= 0; --dl)
+                            s = fma((double)acc[dl][e], ldexp(1.0, -8 * dl), s);
+                        const int r = 32 * wm + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+                        const int c = lane & 31;
+                        const double g = ldexp(s, sexp[r] + cexp[q * OEPC + c] - 12);
+                        E[r * OEPLD + c] = a.sw2 * ipow_oz(g, a.zeta);
+                    }
                 }
                 __syncthreads();
-                if (!multi) {
-                    for (int item = tid; item < n_seg * OEPC; item += ONT) {
-                        const int s = item % n_seg, c = item / n_seg;
-                        const int64_t colg = col0 + q * OEPC + c;
-                        if (colg >= a.M)
-                            continue;
-                        const int a1 = sstart[s + 1];
-                        double acc_s = 0.0;
-                        for (int r = sstart[s]; r < a1; ++r)  // atom order
-                            acc_s += E[r * OEPLD + c];
-                        emit(s, colg, acc_s);
-                    }
-                } else if (tid < OEPC) {
-                    const int c = tid;
+                for (int item = tid; item < n_cs * OEPC; item += ONT) {
+                    const int s = s_lo + item / OEPC, c = item % OEPC;
+                    const int64_t lo = sstart[s] > cs ? sstart[s] : cs;
+                    const int64_t hi = sstart[s + 1] < ce ? sstart[s + 1] : ce;
+                    double part = (sstart[s] < cs) ? cin[q * OEPC + c] : 0.0;  // began in an earlier chunk
+                    for (int64_t r = lo; r < hi; ++r)  // atom order
+                        part += E[(r - cs) * OEPLD + c];
                     const int64_t colg = col0 + q * OEPC + c;
-                    const int nr = (int)((n_at - cs) < OBM ? (n_at - cs) : OBM);
-                    double acc_s = 0.0;
-                    for (int r = 0; r < nr; ++r)
-                        acc_s += E[r * OEPLD + c];
-                    const double tot = first ? acc_s : carry[q * OEPC + c] + acc_s;
-                    carry[q * OEPC + c] = tot;
-                    if (last && colg < a.M)
-                        emit(0, colg, tot);
+                    if (sstart[s + 1] > ce)  // continues in the next chunk
+                        cout[q * OEPC + c] = part;
+                    else if (colg < a.M)
+                        emit(s, colg, part);
                 }
                 __syncthreads();
             }
@@ -401,11 +392,14 @@ hipError_t launch_oz_split(const double *x, int64_t rows, int d, int8_t *out, in
 hipError_t launch_knm_oz(const KnmOzLaunch &l, hipStream_t s)
 {
     KnmOzArgs a{};
-    a.dp = knm_oz_dpad(l.d);
+    const int dp = knm_oz_dpad(l.d);
+    a.nk = dp / OZ_KC;
     a.X = l.X;
     a.XM = l.XM;
-    a.x_slice = l.n_atoms * (int64_t)a.dp;
-    a.xm_slice = l.M * (int64_t)a.dp;
+    a.x_slice = l.n_atoms * (int64_t)dp;
+    a.xm_slice = l.M * (int64_t)dp;
+    a.x_chunk = l.n_atoms * (int64_t)OZ_KC;
+    a.xm_chunk = l.M * (int64_t)OZ_KC;
     a.xe = l.xe;
     a.xme = l.xme;
     a.offsets = l.offsets;
@@ -422,7 +416,7 @@ hipError_t launch_knm_oz(const KnmOzLaunch &l, hipStream_t s)
     a.n_cg = (a.n_ct + OCT - 1) / OCT;
     const int64_t total = l.max_tiles * a.n_cg;
     const int64_t total_pad = (total + 7) & ~int64_t(7);
-    if (total_pad == 0)
+    if (total_pad == 0 || a.nk == 0)
         return hipSuccess;
     hipLaunchKernelGGL(knm_oz_kernel, dim3((unsigned)total_pad), dim3(ONT), 0, s, a);
     return hipGetLastError();

@@ -58,6 +58,30 @@ def test_int8_knm_matches_oracle_elementwise(orc, n_configs, atoms, d, M, zeta, 
     assert np.linalg.norm(low - Lt) / np.linalg.norm(Lt) <= 1e-12
 
 
+def test_int8_knm_large_and_empty_configurations(orc):
+    """Configurations over one and two 128-atom chunks of the kernel's tile, ending at
+    or just past a chunk boundary, and empty ones between, before and after them: each
+    row once, empty ones zero."""
+    rng = np.random.default_rng(19)
+    counts = np.array([0, 3, 0, 300, 17, 0, 0, 600, 128, 0, 129, 1, 257, 256, 0, 5, 0] * 2, dtype=np.int64)
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    d, M, zeta = 40, 150, 3
+    X = rng.standard_normal((offsets[-1], d))
+    XM = X[rng.choice(offsets[-1], M, replace=False)]
+    sigma = 1e-3 * np.maximum(counts, 1).astype(float)
+    log("INT8 K_NM: large and empty configurations, d=40, M=150")
+    g = _int8_fit(X, offsets, XM, sigma, np.ones(len(counts)), zeta, jitter=1e-6)
+    g.build()
+    got = _knm_top(g) * sigma[:, None]
+    expect = orc.knm(X, offsets, XM, zeta)
+    scale = orc.knm(np.abs(X), offsets, np.abs(XM), zeta)
+    empty = counts == 0
+    assert np.all(got[empty] == 0.0)
+    err = np.max(np.abs(got[~empty] - expect[~empty]) / scale[~empty])
+    log(f"  max rel err (to the sum of absolute terms) {err:.2e}")
+    assert err <= TOL_K
+
+
 def test_int8_knm_signed_and_rescaled_rows(orc):
     """Entries of both signs and rows scaled by powers of two from 2^-40 to 2^40
     (each row's slices carry their own exponent): the error is bounded by 1e-13 of
