@@ -303,6 +303,14 @@ __global__ __launch_bounds__(ONT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                     for (int u = 0; u + t < OZ_S; ++u)
                         acc[t + u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af, bf[u], acc[t + u], 0, 0, 0);
                 }
+                // schedule: four reads ahead, then one read per MFMA until the reads are issued
+                __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+#pragma unroll
+                for (int r = 0; r < 2 * OZ_S - 4; ++r) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x008, OZ_S * (OZ_S + 1) / 2 - (2 * OZ_S - 4), 0);
             };
 
             __syncthreads();  // the exponents are in place; both stages are free
