@@ -829,6 +829,7 @@ gap_status gap_solve(gap_handle h, const double *y, double *c_out, gap_solve_inf
     w.A = A;
     w.lda = L.lda;
     w.m = L.m;
+    w.tri0 = L.N;  // rows N.. hold L^T, upper triangular
     w.n = L.M;
     w.ncols = L.ncols;
     w.ldw = (L.ncols + 63) / 64 * 64;

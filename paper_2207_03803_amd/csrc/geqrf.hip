@@ -992,10 +992,23 @@ static void chunking(int64_t rows, int64_t ncb, int64_t &chunk, int64_t &nch, in
     nch = (rows + chunk - 1) / chunk;
 }
 
+// w with its rows cut to those that can be nonzero in columns [0, j_end): below a
+// trailing upper-triangular block's row tri0 + j_end, every column before j_end
+// is still zero, so the reflectors of those columns are zero there and leave
+// those rows unchanged.
+static QrWork rows_to(const QrWork &w, int64_t j_end)
+{
+    QrWork r = w;
+    if (w.tri0 > 0 && w.tri0 + j_end < w.m)
+        r.m = w.tri0 + j_end;
+    return r;
+}
+
 // TSQR + reconstruction of the panel at (j0, j0) of width pw; its T goes to Tout.
 template <class T>
-static void factor_panel(const QrWork &w, int64_t j0, int pw, double *Tout, hipStream_t s)
+static void factor_panel(const QrWork &wf, int64_t j0, int pw, double *Tout, hipStream_t s)
 {
+    const QrWork w = rows_to(wf, j0 + pw);
     if (w.panel == 0) {
         if constexpr (sizeof(T) == 8)
             cqr_panel_f64(w, j0, pw, Tout, s);
@@ -1047,11 +1060,12 @@ struct BlockT {
 
 // C := (I - Y T Y^T)^T C for the columns c0 .. c0+nt, Y the block at (J, J).
 template <class T>
-static void apply_block(const QrWork &w, int64_t J, const BlockT &bt, int64_t c0, int64_t nt, hipStream_t s)
+static void apply_block(const QrWork &wf, int64_t J, const BlockT &bt, int64_t c0, int64_t nt, hipStream_t s)
 {
     if (nt <= 0)
         return;
     const int pw = bt.pw();
+    const QrWork w = rows_to(wf, J + pw);
     const int64_t rows = w.m - J;
     const int64_t ncb = (nt + WS::BN - 1) / WS::BN;
     int64_t chunk, nch;
@@ -1127,11 +1141,12 @@ static int factor_pair(const QrWork &w, int64_t J, double *Tdst, hipStream_t s)
     BlockT pa{nullptr, pwa, 0, Ta, NB};  // panel A alone
     apply_block<T>(w, J, pa, jb, pwb, s);
     factor_panel<T>(w, jb, pwb, Tb, s);
-    const int64_t rows = w.m - jb;
+    const QrWork wg = rows_to(w, jb + pwb);  // G = Y_a^T Y_b
+    const int64_t rows = wg.m - jb;
     int64_t chunk, nch;
-    chunking(rows, 1, chunk, nch, w.max_chunks);
-    launch_wpart<T>(w, J, pwa, jb, (int64_t)pwb, 1, jb, chunk, 1, nch, 1, s);
-    hipLaunchKernelGGL(qr_gsum_kernel, dim3(NB * NB / 256), dim3(256), 0, s, w, pwb, nch, w.cq_G, NB);
+    chunking(rows, 1, chunk, nch, wg.max_chunks);
+    launch_wpart<T>(wg, J, pwa, jb, (int64_t)pwb, 1, jb, chunk, 1, nch, 1, s);
+    hipLaunchKernelGGL(qr_gsum_kernel, dim3(NB * NB / 256), dim3(256), 0, s, wg, pwb, nch, wg.cq_G, NB);
     hipLaunchKernelGGL(qr_tcombine_kernel, dim3(1), dim3(256), 0, s, w, (const double *)w.cq_G, Tdst);
     return pwa + pwb;
 }
@@ -1151,11 +1166,12 @@ static int factor_block(const QrWork &w, int64_t J, BlockT &bt, hipStream_t s)
     BlockT a{bt.store, bt.pwa, 0};
     apply_block<T>(w, J, a, jb, pwb_max, s);
     bt.pwb = factor_pair<T>(w, jb, bt.Tb(), s);
-    const int64_t rows = w.m - jb;
+    const QrWork wg = rows_to(w, jb + bt.pwb);  // G = Y_a^T Y_b
+    const int64_t rows = wg.m - jb;
     int64_t chunk, nch;
-    chunking(rows, 1, chunk, nch, w.max_chunks);
-    launch_wpart<T>(w, J, bt.pwa, jb, (int64_t)bt.pwb, 1, jb, chunk, 1, nch, 1, s);
-    hipLaunchKernelGGL(qr_gsum_kernel, dim3(OB * OB / 256), dim3(256), 0, s, w, bt.pwb, nch, bt.G(), OB);
+    chunking(rows, 1, chunk, nch, wg.max_chunks);
+    launch_wpart<T>(wg, J, bt.pwa, jb, (int64_t)bt.pwb, 1, jb, chunk, 1, nch, 1, s);
+    hipLaunchKernelGGL(qr_gsum_kernel, dim3(OB * OB / 256), dim3(256), 0, s, wg, bt.pwb, nch, bt.G(), OB);
     hipLaunchKernelGGL(qr_hmat_kernel, dim3(OB), dim3(OB), 0, s, (const double *)bt.Ta(), OB, bt.pwa,
                        (const double *)bt.G(), bt.pwb, bt.H());
     return bt.pw();

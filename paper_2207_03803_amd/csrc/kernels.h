@@ -59,6 +59,8 @@ struct QrWork {
     double *A;        // column-major [lda x ncols]: factor columns 0..n-1, apply to n..ncols-1
     float *A32;       // when non-null: factor this FP32 copy instead (same layout); A is not touched
     int64_t lda, m, n, ncols;
+    int64_t tri0;     // rows [tri0, m) are upper triangular from column 0 (row tri0 + i is zero in the
+                      // columns before i) and are skipped until the factorisation reaches them; 0: none
     int64_t ldw;      // leading dimension of W (ncols rounded up to 64)
     double *tau;      // [n]
     double *wpart;    // [max_chunks * 4 QR_NB * wp_ld] split-K partials of Y^T C
