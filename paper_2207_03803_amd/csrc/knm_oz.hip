@@ -107,8 +107,7 @@ constexpr int OSA = OBM * OZ_KC;         // one slice's A rows in a stage: 4 KB
 constexpr int OSB = OBN * OZ_KC;         // one slice's B rows: 2 KB
 constexpr int OSTAGE = OZ_S * (OSA + OSB);  // A slices 0..6, then B slices 0..6: 42 KB
 constexpr int OITEMS = OSTAGE / 1024;    // 1 KB loads per stage: 28 of A, then 14 of B
-constexpr int OEPC = 32;                 // epilogue columns per pass
-constexpr int OEPLD = OEPC + 1;
+constexpr int OEPLD = OBN + 1;           // the epilogue's row stride (all 64 columns at once)
 static_assert(ONT == 512 && OSA == 4 * 1024 && OSB == 2 * 1024, "load mapping: A parts = wave % 4, B = wave % 2");
 static_assert(2 * OBM == KNM_BM, "a plan tile is two chunks (or one configuration in several)");
 
@@ -155,8 +154,8 @@ __global__ __launch_bounds__(ONT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     __shared__ int64_t sbase[KNM_MAX_SEG];
     __shared__ int32_t srow[KNM_MAX_SEG];
     __shared__ int32_t scan[KNM_MAX_SEG];
-    __shared__ int32_t sexp[OBM];
-    __shared__ int32_t cexp[OBN];
+    __shared__ int32_t sexp[2][OBM];  // row and column exponents, by unit parity
+    __shared__ int32_t cexp[2][OBN];
 
     const int64_t n_tiles = (int64_t)*a.n_tiles_dev;
     const int64_t total = n_tiles * a.n_cg;
@@ -252,45 +251,58 @@ __global__ __launch_bounds__(ONT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int b_off = OZ_S * OSA + fc * OZ_KC + 16 * oz_half(fc, lane >> 5);
     const int nk = a.nk;
 
-    i32x16 acc[OZ_S];
-    int chunk_no = 0;
-    for (int64_t ct = ct_lo; ct < ct_hi; ++ct) {
-        const int64_t col0 = ct * OBN;
-        const int64_t colb = col0 + brow;
-        const int64_t boff = (colb < a.M ? colb * OZ_KC : 0) + 16 * bhalf;  // past M: any valid row
-        for (int64_t cs = 0; cs < n_at; cs += OBM, ++chunk_no) {
-            const int64_t at = atom_of(cs + arow);
-            const int64_t aoff = (at >= 0 ? at * OZ_KC : 0) + 16 * ahalf;  // rows past the tile: unused
-            __syncthreads();  // the previous chunk's epilogue is done with the LDS and the exponents
-            if (tid < OBM) {
-                const int64_t ar = atom_of(cs + tid);
-                sexp[tid] = ar >= 0 ? a.xe[ar] : 0;
-            } else if (tid < OBM + OBN) {
-                const int c = tid - OBM;
-                cexp[c] = (col0 + c < a.M) ? a.xme[col0 + c] : 0;
+    // Units: (column tile, chunk of 128 tile rows), chunks inner.  A unit's setup (its
+    // load offsets and exponents, double-buffered by unit parity) and its first stage's
+    // loads are issued before the previous unit's epilogue, which then hides them.
+    const int64_t n_chunks = (n_at + OBM - 1) / OBM;
+    const int64_t n_units = (ct_hi - ct_lo) * n_chunks;
+    int64_t aoff = 0, boff = 0;  // this lane's load offsets for the unit being loaded
+    auto setup = [&](int64_t u) {
+        const int64_t ct = ct_lo + u / n_chunks, cs = (u % n_chunks) * OBM;
+        const int64_t col0 = ct * OBN, colb = col0 + brow;
+        boff = (colb < a.M ? colb * OZ_KC : 0) + 16 * bhalf;  // past M: any valid row
+        const int64_t at = atom_of(cs + arow);
+        aoff = (at >= 0 ? at * OZ_KC : 0) + 16 * ahalf;  // rows past the tile: unused
+        int32_t *se = sexp[u & 1], *ce = cexp[u & 1];
+        if (tid < OBM) {
+            const int64_t ar = atom_of(cs + tid);
+            se[tid] = ar >= 0 ? a.xe[ar] : 0;
+        } else if (tid < OBM + OBN) {
+            const int c = tid - OBM;
+            ce[c] = (col0 + c < a.M) ? a.xme[col0 + c] : 0;
+        }
+    };
+    auto issue = [&](int kc, unsigned char *stg) {  // k-chunk kc of all fourteen slice tiles
+        const int8_t *xa = a.X + kc * a.x_chunk + aoff;
+        const int8_t *xb = a.XM + kc * a.xm_chunk + boff;
+#pragma unroll
+        for (int m = 0; m < (OITEMS + 7) / 8; ++m) {
+            const int i = wave + 8 * m;
+            if (i < 4 * OZ_S) {
+                const int t = i >> 2;
+                __builtin_amdgcn_global_load_lds((const void *)(xa + t * a.x_slice),
+                                                 (lds_void *)(stg + t * OSA + 1024 * (i & 3)), 16, 0, 0);
+            } else if (i < OITEMS) {
+                const int j = i - 4 * OZ_S, u = j >> 1;
+                __builtin_amdgcn_global_load_lds((const void *)(xb + u * a.xm_slice),
+                                                 (lds_void *)(stg + OZ_S * OSA + u * OSB + 1024 * (j & 1)), 16, 0,
+                                                 0);
             }
+        }
+    };
+
+    i32x16 acc[OZ_S];
+    setup(0);
+    issue(0, stage0);
+    for (int64_t unit = 0; unit < n_units; ++unit) {
+        const int64_t ct = ct_lo + unit / n_chunks, cs = (unit % n_chunks) * OBM;
+        const int64_t col0 = ct * OBN;
+        const int32_t *se = sexp[unit & 1], *ce_exp = cexp[unit & 1];
+        {
 #pragma unroll
             for (int dl = 0; dl < OZ_S; ++dl)
                 acc[dl] = i32x16{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 
-            auto issue = [&](int kc, unsigned char *stg) {  // k-chunk kc of all fourteen slice tiles
-                const int8_t *xa = a.X + kc * a.x_chunk + aoff;
-                const int8_t *xb = a.XM + kc * a.xm_chunk + boff;
-#pragma unroll
-                for (int m = 0; m < (OITEMS + 7) / 8; ++m) {
-                    const int i = wave + 8 * m;
-                    if (i < 4 * OZ_S) {
-                        const int t = i >> 2;
-                        __builtin_amdgcn_global_load_lds((const void *)(xa + t * a.x_slice),
-                                                         (lds_void *)(stg + t * OSA + 1024 * (i & 3)), 16, 0, 0);
-                    } else if (i < OITEMS) {
-                        const int j = i - 4 * OZ_S, u = j >> 1;
-                        __builtin_amdgcn_global_load_lds((const void *)(xb + u * a.xm_slice),
-                                                         (lds_void *)(stg + OZ_S * OSA + u * OSB + 1024 * (j & 1)),
-                                                         16, 0, 0);
-                    }
-                }
-            };
             auto compute = [&](const unsigned char *stg) {  // the 28 slice products of one k-chunk
                 i32x4 bf[OZ_S];
 #pragma unroll
@@ -313,8 +325,6 @@ __global__ __launch_bounds__(ONT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 __builtin_amdgcn_sched_group_barrier(0x008, OZ_S * (OZ_S + 1) / 2 - (2 * OZ_S - 4), 0);
             };
 
-            __syncthreads();  // the exponents are in place; both stages are free
-            issue(0, stage0);
             for (int kc = 0; kc < nk; kc += 2) {
                 __syncthreads();  // (waits for this wave's loads) stage 0 holds chunk kc; stage 1 is free
                 if (kc + 1 < nk)
@@ -328,9 +338,11 @@ __global__ __launch_bounds__(ONT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 }
             }
 
-            // Epilogue in passes of 32 columns (the waves wn = q): the diagonals folded
-            // into FP64, g = 2^(e_i + e_j - 12) sum, k = sigma_w^2 g^zeta into E, then
-            // the sums over each configuration's atoms in atom order.
+            __syncthreads();  // every wave is done with the stages
+            if (unit + 1 < n_units) {  // the next unit's setup and first stage, hidden by this epilogue
+                setup(unit + 1);
+                issue(0, stage0);
+            }
             // This chunk, rows [cs, ce), handles the segments that meet it, the empty ones
             // at positions in [cs, ce) and, if it is the last, the empty ones at n_at:
             // segments [s_lo, s_hi) with s_lo the first that ends after cs or starts at
@@ -350,40 +362,38 @@ __global__ __launch_bounds__(ONT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             const int s_lo = first_seg([&](int q) { return sstart[q] >= cs || sstart[q + 1] > cs; });
             const int s_hi = (ce == n_at) ? n_seg : first_seg([&](int q) { return sstart[q] >= ce; });
             const int n_cs = s_hi - s_lo;
-            const double *cin = carry[chunk_no & 1];
-            double *cout = carry[(chunk_no + 1) & 1];
-            for (int q = 0; q < OBN / OEPC; ++q) {
-                if (wn == q) {
+            const double *cin = carry[unit & 1];  // written by the previous unit
+            double *cout = carry[(unit + 1) & 1];
+            // Epilogue: the diagonals folded into FP64, g = 2^(e_i + e_j - 12) sum,
+            // k = sigma_w^2 g^zeta into E (every wave its block), then the sums over each
+            // configuration's atoms in atom order (the next chunk's first barrier ends it).
 #pragma unroll
-                    for (int e = 0; e < 16; ++e) {
-                        double s = 0.0;
+            for (int e = 0; e < 16; ++e) {
+                double sum = 0.0;
 #pragma unroll
-                        for (int dl = OZ_S - 1; dl >= 0; --dl)
-                            s = fma((double)acc[dl][e], ldexp(1.0, -8 * dl), s);
-                        const int r = 32 * wm + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-                        const int c = lane & 31;
-                        const double g = ldexp(s, sexp[r] + cexp[q * OEPC + c] - 12);
-                        E[r * OEPLD + c] = a.sw2 * ipow_oz(g, a.zeta);
-                    }
-                }
-                __syncthreads();
-                for (int item = tid; item < n_cs * OEPC; item += ONT) {
-                    const int s = s_lo + item / OEPC, c = item % OEPC;
-                    const int64_t lo = sstart[s] > cs ? sstart[s] : cs;
-                    const int64_t hi = sstart[s + 1] < ce ? sstart[s + 1] : ce;
-                    double part = (sstart[s] < cs) ? cin[q * OEPC + c] : 0.0;  // began in an earlier chunk
-                    for (int64_t r = lo; r < hi; ++r)  // atom order
-                        part += E[(r - cs) * OEPLD + c];
-                    const int64_t colg = col0 + q * OEPC + c;
-                    if (sstart[s + 1] > ce)  // continues in the next chunk
-                        cout[q * OEPC + c] = part;
-                    else if (colg < a.M)
-                        emit(s, colg, part);
-                }
-                __syncthreads();
+                for (int dl = OZ_S - 1; dl >= 0; --dl)
+                    sum = fma((double)acc[dl][e], ldexp(1.0, -8 * dl), sum);
+                const int r = 32 * wm + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+                const int c = 32 * wn + (lane & 31);
+                const double g = ldexp(sum, se[r] + ce_exp[c] - 12);
+                E[r * OEPLD + c] = a.sw2 * ipow_oz(g, a.zeta);
+            }
+            __syncthreads();
+            for (int item = tid; item < n_cs * OBN; item += ONT) {
+                const int s = s_lo + item / OBN, c = item % OBN;
+                const int64_t lo = sstart[s] > cs ? sstart[s] : cs;
+                const int64_t hi = sstart[s + 1] < ce ? sstart[s + 1] : ce;
+                double part = (sstart[s] < cs) ? cin[c] : 0.0;  // began in an earlier chunk
+                for (int64_t r = lo; r < hi; ++r)  // atom order
+                    part += E[(r - cs) * OEPLD + c];
+                const int64_t colg = col0 + c;
+                if (sstart[s + 1] > ce)  // continues in the next chunk
+                    cout[c] = part;
+                else if (colg < a.M)
+                    emit(s, colg, part);
             }
         }
-    }  // column tiles of the group
+    }  // units
 }
 
 hipError_t launch_oz_split(const double *x, int64_t rows, int d, int8_t *out, int32_t *ex, hipStream_t s)
