@@ -5,7 +5,7 @@ M = 1e4 sparse points, zeta = 4, FP64, beside the three forms around it:
   mixed  the same fit with an FP32 Householder QR and FP64 refinement of c
   bf16   mixed, with the factored K_NM block from BF16 descriptor dot products
   fp16   mixed, with FP16 descriptor dot products
-  int8   the FP64 fit with its K_NM dot products emulated on INT8 MFMA
+  int8   the FP64 fit with its K_NM dot products emulated on INT8 MFMA, and the mixed fit on that K_NM
          (Ozaki scheme: 7 slices per value, 28 exact slice products)
   cur    CUR sparse-point selection of M rows from the descriptor rows
          (leverages on FP64 MFMA, sampling by exponential keys)
@@ -507,6 +507,19 @@ def main():
                           "unit": "TOP/s"})
         log(f"[bench] fp64_int8: {oz['ms']:.1f} ms per fit, K_NM {1e3 * t_oz:.1f} ms")
         del oz
+        # the mixed fit (FP32 QR, FP64 refinement) on the same FP64-accurate K_NM
+        mo = run_fit(gap.GAP_MIXED_FP32, args.steps, args.warmup, y=fp["y"], flags=gap.GAP_FLAG_KNM_INT8)
+        extra["mixed_int8"] = {
+            "s_per_fit": mo["ms"] / 1e3, "median_ms": mo["ms_median"], "min_ms": mo["ms_min"],
+            "speedup_vs_fp64": ms_per_step / mo["ms"], "stages_ms": mo["stages_ms"],
+            "status": gap.status_string(mo["status"]), "refine_iters": mo["info"].refine_iters,
+            "cgls_iters": mo["info"].cgls_iters, "eta": mo["info"].grad_rel,
+            "c_rel_err_vs_fp64_path": float((mo["c"] - fp["c"]).norm() / fp["c"].norm()), **vs_oracle(mo),
+            "note": "mixed fit (FP32 Householder QR, FP64 refinement) whose FP64 K_NM comes from INT8 slice "
+                    "products, as in fp64_int8"}
+        log(f"[bench] mixed_int8: {mo['ms']:.1f} ms per fit ({gap.status_string(mo['status'])}, "
+            f"{mo['info'].refine_iters} refinement steps)")
+        del mo
     for r in rooflines:
         r.setdefault("unit", "TFLOP/s")
         r["frac"] = r["achieved"] / r["peak"]

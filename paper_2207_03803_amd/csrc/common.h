@@ -74,10 +74,12 @@ DEV double wave_sum(double v)
 // g = (l/4)%4: A(m, k) of block g at lane 16k + 4g + (m%4), B(k, n) at lane
 // 16k + 4g + (n%4), result (m, n) at lane 16(m%4) + 4g + (n%4).  With the A
 // register holding A(l%16, l/16) (rows 4g..4g+3 in group g) and the s-th B
-// register holding B(l/16, 4((g+s)%4) + l%4), instruction s computes the
-// 4x4 blocks (row group g, column group (g+s)%4); the four instructions
-// together cover the 16x16 block.  Accumulator element s of lane l is
-// C(4g + l/16, 4((g+s)%4) + l%4) with g = (l/4)%4 (layout measured on gfx950).
+// register holding B(l/16, 4s + l%4) in every group, instruction s computes
+// the 4x4 blocks (row group g, column group s) for g = 0..3; the four
+// instructions together cover the 16x16 block.  The four lanes of a k-row
+// that share l%4 read the same B element (an LDS broadcast), so a B read moves
+// 16 distinct values.  Accumulator element s of lane l is
+// C(4g + l/16, 4s + l%4) with g = (l/4)%4 (layout measured on gfx950).
 // ---------------------------------------------------------------------------
 template <int BM_, int BN_, int BK_, int WM_, int WN_>
 struct TileShape {
@@ -104,24 +106,9 @@ DEV void zero_acc(d4 (&acc)[S::FM][S::FN])
 }
 
 // Column (within a 16-wide block) that B register s of lane l carries.
-DEV int bcol16(int lane, int s) { return 4 * ((((lane >> 2) & 3) + s) & 3) + (lane & 3); }
+DEV int bcol16(int lane, int s) { return 4 * s + (lane & 3); }
 
-// Value of v held by lane (l + 4 s) mod 16 of l's 16-lane row (a DPP row
-// rotation; no LDS traffic): the B operand of rotation s from that of s = 0.
-template <int SH>
-DEV double row_rot4(double v)
-{
-    static_assert(SH >= 1 && SH <= 3, "rotation by 4, 8 or 12 lanes");
-    constexpr int ctrl = 0x120 + (16 - 4 * SH);  // row_ror:(16 - 4 SH): lane i reads lane i + 4 SH
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), ctrl, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctrl, 0xF, 0xF, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-// ROT: derive the rotated B operands with DPP from one LDS read (for kernels
-// whose LDS port is the bottleneck); otherwise read all four from LDS.
-template <class S, bool ROT = false>
+template <class S>
 DEV void mma_stage(const double *__restrict__ As, const double *__restrict__ Bs,
                    d4 (&acc)[S::FM][S::FN], int wm, int wn, int lane)
 {
@@ -135,16 +122,9 @@ DEV void mma_stage(const double *__restrict__ As, const double *__restrict__ Bs,
 #pragma unroll
         for (int j = 0; j < S::FN; ++j) {
             double b[4];
-            if constexpr (ROT) {
-                b[0] = Bs[kr * S::LDB + wn * S::TN + j * 16 + (lane & 15)];  // = bcol16(lane, 0)
-                b[1] = row_rot4<1>(b[0]);
-                b[2] = row_rot4<2>(b[0]);
-                b[3] = row_rot4<3>(b[0]);
-            } else {
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    b[s] = Bs[kr * S::LDB + wn * S::TN + j * 16 + bcol16(lane, s)];
-            }
+            for (int s = 0; s < 4; ++s)
+                b[s] = Bs[kr * S::LDB + wn * S::TN + j * 16 + bcol16(lane, s)];
 #pragma unroll
             for (int i = 0; i < S::FM; ++i)
 #pragma unroll
@@ -281,7 +261,7 @@ DEV void gemm_tile(d4 (&acc)[S::FM][S::FN], double *lds, int64_t K, FA fa, FB fb
 // at the given (r, k)); likewise fb with VB.  Lets the caller issue vector
 // loads and keep bounds checks off the common path.
 // ---------------------------------------------------------------------------
-template <class S, bool A_KC, bool B_KC, bool ROT = false, class FA, class FB>
+template <class S, bool A_KC, bool B_KC, class FA, class FB>
 DEV void gemm_tile_runs(d4 (&acc)[S::FM][S::FN], double *lds, int64_t K, FA fa, FB fb)
 {
     constexpr int VA = S::BM * S::BK / S::NT;
@@ -336,7 +316,7 @@ DEV void gemm_tile_runs(d4 (&acc)[S::FM][S::FN], double *lds, int64_t K, FA fa, 
             fa(ar, (kt + 1) * S::BK + ak, ra);
             fb(br, (kt + 1) * S::BK + bk, rb);
         }
-        mma_stage<S, ROT>(cur, cur + S::A_ELEMS, acc, wm, wn, lane);
+        mma_stage<S>(cur, cur + S::A_ELEMS, acc, wm, wn, lane);
         if (more)
             store(nxt, nxt + S::A_ELEMS);
         __syncthreads();

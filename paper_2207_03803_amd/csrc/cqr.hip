@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256, 2) void cqr_gram_kernel(const T *__restrict__ 
         }
     };
     if (lo < hi)
-        gemm_tile_runs<GS, true, true, false>(acc, lds, hi - lo, f, f);
+        gemm_tile_runs<GS, true, true>(acc, lds, hi - lo, f, f);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / GS::WN, wn = wave % GS::WN;
     double *out = part + ch * (CB * CB);

@@ -494,7 +494,7 @@ __global__ __launch_bounds__(256, 2) void qr_wpart_kernel(QrWork w, int64_t j0, 
             }
         }
     };
-    gemm_tile_runs<WS, true, true, false>(acc, lds, rhi - rlo, fa, fb);
+    gemm_tile_runs<WS, true, true>(acc, lds, rhi - rlo, fa, fb);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WS::WN, wn = wave % WS::WN;
     double *P = w.wpart + (ch * OB2 + prow0) * w.wp_ld;
@@ -806,7 +806,7 @@ __global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0,
                 v[e] = ypanel(A, lda, m, j0, pw, r + e, (int)p);
         }
     };
-    gemm_tile_runs<US, false, false, false>(acc, lds, pw, fa, fb);
+    gemm_tile_runs<US, false, false>(acc, lds, pw, fa, fb);
     // recompute the store addresses rather than keep the loads' live through the product
     int64_t q0s = q0, r0s = r0;
     asm volatile("" : "+s"(q0s), "+s"(r0s));
