@@ -107,7 +107,9 @@ typedef struct gap_params {
  * in FP64 as in the FP64 build).  The dot products carry about FP64's rounding
  * error.  Applies to every precision (the FP64 A of the mixed forms included);
  * K_MM keeps the FP64 build.  The workspace grows by 7 bytes per descriptor
- * entry (rows padded to a multiple of 64) plus 4 bytes per row. */
+ * entry (rows padded to a multiple of 32) plus 4 bytes per row.  Parameters
+ * with this flag and d > 4096 are rejected (GAP_EINVAL, or 0 workspace bytes):
+ * beyond that the INT32 sums could overflow. */
 #define GAP_FLAG_KNM_INT8 4u
 
 typedef struct gap_handle_s *gap_handle;

@@ -239,6 +239,10 @@ int32_t *predict_status(gap_handle h)
 
 bool valid_params(const gap_params *p)
 {
+    // the INT8-emulated K_NM sums at most 7 slice products of d_pad terms of up to 2^14
+    // exactly in INT32 only for d_pad <= 4096
+    if (p && (p->flags & GAP_FLAG_KNM_INT8) && knm_oz_dpad(p->d) > 4096)
+        return false;
     return p && p->d >= 1 && p->zeta >= 1 && p->zeta <= 8 && p->sigma_w > 0.0 && isfinite(p->sigma_w) &&
            p->jitter >= 0.0 && isfinite(p->jitter) &&
            (p->precision == GAP_FP64 || p->precision == GAP_MIXED_FP32 || p->precision == GAP_MIXED_BF16 ||

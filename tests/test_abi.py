@@ -38,8 +38,16 @@ def test_create_rejects_bad_params_without_a_gpu():
     lib = gap.lib()
     h = ctypes.c_void_p()
     for p in (gap.params(0, 2), gap.params(8, 0), gap.params(8, 9), gap.params(8, 2, sigma_w=0.0),
-              gap.params(8, 2, jitter=-1.0), gap.params(8, 2, precision=7)):
+              gap.params(8, 2, jitter=-1.0), gap.params(8, 2, precision=7),
+              gap.params(4097, 2, flags=gap.GAP_FLAG_KNM_INT8)):
         assert lib.gap_create(ctypes.byref(p), None, ctypes.byref(h)) == gap.GAP_EINVAL
+
+
+def test_int8_knm_descriptor_length_limit():
+    """The INT8-emulated K_NM takes rows up to 4096 components (exact INT32 sums)."""
+    assert gap.workspace_bytes(gap.params(4096, 2, flags=gap.GAP_FLAG_KNM_INT8), 10, 100, 10) > 0
+    assert gap.workspace_bytes(gap.params(4097, 2, flags=gap.GAP_FLAG_KNM_INT8), 10, 100, 10) == 0
+    assert gap.workspace_bytes(gap.params(4097, 2), 10, 100, 10) > 0
 
 
 def test_workspace_bytes_bad_inputs():
