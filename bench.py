@@ -437,12 +437,24 @@ def main():
     stages_ms = fp["stages_ms"]
     knm_s = stages_ms["knm"] / 1e3
     achieved = f["knm"] / knm_s
+    # With the QR look-ahead (M >= 2048) the K_MM and its Cholesky run on the look-ahead
+    # stream beside the K_NM: their stage events then span the overlap (mostly waiting for
+    # CUs), and the K_NM's own time includes sharing the GPU with them.
+    kmm_overlapped = M >= 2048
     stage_rates = {
         "knm_tflops": f["knm"] / knm_s / 1e12,
-        "kmm_tflops": f["kmm"] / (stages_ms["kmm"] / 1e3) / 1e12,
-        "cholesky_tflops": f["cholesky"] / (stages_ms["cholesky"] / 1e3) / 1e12,
         "qr_tflops": f["qr_tri"] / (stages_ms["qr"] / 1e3) / 1e12,
     }
+    if kmm_overlapped:
+        others = sum(v for k, v in stages_ms.items() if k not in ("kmm", "cholesky"))
+        stage_rates["kmm_cholesky_overlapped"] = {
+            "side_stream_span_ms": stages_ms["kmm"] + stages_ms["cholesky"],
+            "exposed_ms": max(0.0, ms_per_step - others),
+            "note": "K_MM + Cholesky on the look-ahead stream beside the K_NM; exposed_ms = fit time minus the "
+                    "main stream's stages"}
+    else:
+        stage_rates["kmm_tflops"] = f["kmm"] / (stages_ms["kmm"] / 1e3) / 1e12
+        stage_rates["cholesky_tflops"] = f["cholesky"] / (stages_ms["cholesky"] / 1e3) / 1e12
     fp_oracle = vs_oracle(fp)
     if fp_oracle:
         log(f"[bench] fp64: c rel err vs oracle {fp_oracle['c_rel_err_vs_oracle']:.2e}")
@@ -451,9 +463,10 @@ def main():
          "achieved": f["knm"] / knm_s / 1e12, "peak": PEAK_FP64_MFMA / 1e12},
         {"stage": "qr", "kernel": "qr_wpart_kernel + qr_update_kernel (+ panels)", "bound": "mfma", "dtype": "f64",
          "achieved": stage_rates["qr_tflops"], "peak": PEAK_FP64_MFMA / 1e12},
-        {"stage": "cholesky", "kernel": "chol_*", "bound": "mfma", "dtype": "f64",
-         "achieved": stage_rates["cholesky_tflops"], "peak": PEAK_FP64_MFMA / 1e12},
     ]
+    if not kmm_overlapped:
+        rooflines.append({"stage": "cholesky", "kernel": "chol_*", "bound": "mfma", "dtype": "f64",
+                          "achieved": stage_rates["cholesky_tflops"], "peak": PEAK_FP64_MFMA / 1e12})
     # the forms are measured around the realistic workload only
     forms = [] if args.forms == "none" or args.workload != "realistic_fp64" else args.forms.split(",")
     extra = {}

@@ -197,14 +197,15 @@ struct gap_handle_s {
     }
     double *diag_out() const { return at<double>(L.off_diag) + 14 * L.M + 4 + 256; }
 
-    void mark(int stage, bool end)
+    void mark_on(int stage, bool end, hipStream_t st)
     {
         if (!timing)
             return;
-        (void)hipEventRecord(ev[2 * stage + (end ? 1 : 0)], stream);
+        (void)hipEventRecord(ev[2 * stage + (end ? 1 : 0)], st);
         if (end)
             timed[stage] = true;
     }
+    void mark(int stage, bool end) { mark_on(stage, end, stream); }
 };
 
 namespace {
@@ -563,7 +564,55 @@ static gap_status launch_knm_int8(gap_handle h, hipStream_t s)
 
 // On the handle's stream, after the K_NM: the low-precision K_NM (mixed BF16 /
 // FP16), K_MM + jitter (upper triangle) into rows N..N+M-1, then U = L^T in place.
-static gap_status build_rest(gap_handle h)
+// K_MM + jitter and its Cholesky into the bottom block of A, on stream s.
+static gap_status launch_kmm_chol(gap_handle h, hipStream_t s)
+{
+    const Layout &L = h->L;
+    const gap_params &p = h->p;
+    KnmArgs k{};
+    k.X = h->x_sparse;
+    k.offsets = nullptr;
+    k.n_rows_unit = L.M;
+    k.XM = h->x_sparse;
+    k.M = L.M;
+    k.d = p.d;
+    k.zeta = p.zeta;
+    k.sw2 = p.sigma_w * p.sigma_w;
+    k.sigma = nullptr;
+    k.out = h->A();
+    k.ldo = L.lda;
+    k.row_off = L.N;
+    k.jitter = p.jitter;
+    k.upper_only = 1;
+    k.status = h->status();
+    h->mark_on(1, false, s);
+    GAP_TRY(dev(launch_knm(k, (L.M + KNM_BM - 1) / KNM_BM, s)));
+    h->mark_on(1, true, s);
+    h->mark_on(2, false, s);
+    GAP_TRY(dev(launch_potrf_upper(h->A() + L.N, L.lda, L.M, h->status(), s)));
+    h->mark_on(2, true, s);
+    return GAP_OK;
+}
+
+// K_MM and its Cholesky need neither the K_NM nor its plan: with a look-ahead stream
+// they run there, beside the K_NM (forked after the build's set-up, joined in
+// build_rest); without one build_rest runs them in order.
+static gap_status fork_kmm(gap_handle h, bool &forked)
+{
+    forked = false;
+    if (!h->la.side || !h->la.fork || !h->la.join)
+        return GAP_OK;
+    if (hipEventRecord(h->la.fork, h->stream) != hipSuccess ||
+        hipStreamWaitEvent(h->la.side, h->la.fork, 0) != hipSuccess)
+        return GAP_EDEVICE;
+    GAP_TRY(launch_kmm_chol(h, h->la.side));
+    if (hipEventRecord(h->la.join, h->la.side) != hipSuccess)
+        return GAP_EDEVICE;
+    forked = true;
+    return GAP_OK;
+}
+
+static gap_status build_rest(gap_handle h, bool kmm_forked = false)
 {
     const Layout &L = h->L;
     hipStream_t s = h->stream;
@@ -596,28 +645,12 @@ static gap_status build_rest(gap_handle h)
         GAP_TRY(dev(launch_knm_lp(l, s)));
         h->mark(7, true);
     }
-    KnmArgs k{};
-    k.X = h->x_sparse;
-    k.offsets = nullptr;
-    k.n_rows_unit = L.M;
-    k.XM = h->x_sparse;
-    k.M = L.M;
-    k.d = p.d;
-    k.zeta = p.zeta;
-    k.sw2 = sw2;
-    k.sigma = nullptr;
-    k.out = h->A();
-    k.ldo = L.lda;
-    k.row_off = L.N;
-    k.jitter = p.jitter;
-    k.upper_only = 1;
-    k.status = h->status();
-    h->mark(1, false);
-    GAP_TRY(dev(launch_knm(k, (L.M + KNM_BM - 1) / KNM_BM, s)));
-    h->mark(1, true);
-    h->mark(2, false);
-    GAP_TRY(dev(launch_potrf_upper(h->A() + L.N, L.lda, L.M, h->status(), s)));
-    h->mark(2, true);
+    if (kmm_forked) {
+        if (hipStreamWaitEvent(s, h->la.join, 0) != hipSuccess)
+            return GAP_EDEVICE;
+    } else {
+        GAP_TRY(launch_kmm_chol(h, s));
+    }
     h->state = ST_BUILT;
     return GAP_OK;
 }
@@ -628,13 +661,15 @@ gap_status gap_build_knm(gap_handle h, const double *x_atoms, int64_t n_atoms, c
     GAP_TRY(build_prepare(h, x_atoms, n_atoms, config_offsets, n_configs, x_sparse, M, sigma));
     KnmArgs a;
     GAP_TRY(build_setup(h, h->stream, &a));
+    bool forked = false;
+    GAP_TRY(fork_kmm(h, forked));
     h->mark(0, false);
     if (h->L.oz)
         GAP_TRY(launch_knm_int8(h, h->stream));
     else
         GAP_TRY(dev(launch_knm(a, h->L.max_tiles, h->stream)));
     h->mark(0, true);
-    return build_rest(h);
+    return build_rest(h, forked);
 }
 
 // Derivative observation rows N_E .. N_E + n_obs - 1 of A: D = (X X_M^T)^(zeta - 1) for
@@ -704,6 +739,8 @@ gap_status gap_build_knm_obs(gap_handle h, const double *x_atoms, int64_t n_atom
     GAP_TRY(build_prepare(h, x_atoms, n_atoms, config_offsets, n_configs, x_sparse, M, sigma, obs));
     KnmArgs a;
     GAP_TRY(build_setup(h, h->stream, &a));
+    bool forked = false;
+    GAP_TRY(fork_kmm(h, forked));
     h->mark(0, false);
     if (h->L.oz)
         GAP_TRY(launch_knm_int8(h, h->stream));
@@ -711,7 +748,7 @@ gap_status gap_build_knm_obs(gap_handle h, const double *x_atoms, int64_t n_atom
         GAP_TRY(dev(launch_knm(a, h->L.max_tiles, h->stream)));
     h->mark(0, true);
     GAP_TRY(build_derivatives(h));
-    return build_rest(h);
+    return build_rest(h, forked);
 }
 
 size_t gap_workspace_bytes_obs(const gap_params *p, int64_t n_configs, int64_t n_atoms, int64_t n_obs,
