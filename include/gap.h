@@ -156,8 +156,10 @@ typedef struct gap_layout_info {
  * Validates p (GAP_EINVAL).  Allocates only host memory and HIP events.  The
  * first gap_build_knm of a fit that uses the QR look-ahead (gap_tuning) also
  * creates one internal HIP stream (default priority) and its events; make that
- * first call outside graph capture.  Inside gap_solve that stream forks from
- * and joins `stream`, so a graph captured on `stream` contains it. */
+ * first call outside graph capture.  Inside gap_build_knm / gap_build_knm_obs
+ * (K_MM and its Cholesky, beside the K_NM) and gap_solve (the QR's trailing
+ * updates) that stream forks from and joins `stream`, so a graph captured on
+ * `stream` contains it and the calls' work is complete when `stream`'s is. */
 gap_status gap_create(const gap_params *p, void *stream, gap_handle *out);
 
 /* Bytes of device workspace a fit of this shape needs.  Pure host function:
