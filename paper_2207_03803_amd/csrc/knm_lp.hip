@@ -93,7 +93,7 @@ constexpr int LBK = 32;       // k per slice
 constexpr int LDSK = LBK + 8; // padded LDS row (elements)
 constexpr int LNT = 512;
 constexpr int LCT = 8;        // column tiles per workgroup (the tile's setup is shared)
-constexpr int LEPC = 32;      // epilogue columns per pass
+constexpr int LEPC = 64;      // epilogue columns per pass (the columns of one wn)
 constexpr int LEPLD = LEPC + 1;
 constexpr int LA_ELEMS = LBM * LDSK, LB_ELEMS = LBN * LDSK, LSTAGE = LA_ELEMS + LB_ELEMS;
 constexpr int LDS_BYTES_GEMM = 2 * LSTAGE * 2;
@@ -302,17 +302,15 @@ __global__ __launch_bounds__(LNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
 
         float *E = reinterpret_cast<float *>(lds_raw);  // [256][LEPLD], reused after the GEMM
         for (int p = 0; p < LBN / LEPC; ++p) {
-            // columns [32 p, 32 p + 32) are blocks j = 2 (p & 1), 2 (p & 1) + 1 of waves wn = p / 2
-            if (wn == (p >> 1)) {
+            // columns [64 p, 64 p + 64) are the blocks of the waves wn = p
+            if (wn == p) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
-                    for (int jj = 0; jj < 2; ++jj) {
-                        const int j = 2 * (p & 1) + jj;
+                    for (int j = 0; j < 4; ++j)
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
-                            E[(wm * 64 + i * 16 + 4 * (lane >> 4) + e) * LEPLD + jj * 16 + (lane & 15)] = acc[i][j][e];
-                    }
+                            E[(wm * 64 + i * 16 + 4 * (lane >> 4) + e) * LEPLD + j * 16 + (lane & 15)] = acc[i][j][e];
             }
             __syncthreads();
             if (!multi) {
@@ -323,7 +321,17 @@ __global__ __launch_bounds__(LNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
                         continue;
                     const int a1 = sstart[s + 1];
                     float sum = 0.0f;
-                    for (int r = sstart[s]; r < a1; ++r)  // atom order
+                    int r = sstart[s];
+                    for (; r + 8 <= a1; r += 8) {  // atom order; the loads of 8 rows issued together
+                        float v[8];
+#pragma unroll
+                        for (int k = 0; k < 8; ++k)
+                            v[k] = E[(r + k) * LEPLD + c];
+#pragma unroll
+                        for (int k = 0; k < 8; ++k)
+                            sum += v[k];
+                    }
+                    for (; r < a1; ++r)
                         sum += E[r * LEPLD + c];
                     emit(s, colg, sum);
                 }
