@@ -68,8 +68,8 @@ DEV double wave_sum(double v)
 // operands are staged in LDS "K-major": As[k * LDA + m], Bs[k * LDB + n].  The
 // WM x WN waves each own a TM x TN sub-tile made of FM x FN blocks of 16x16.
 //
-// Each 16x16x4 block product is done with four v_mfma_f64_4x4x4_4b_f64
-// (measured on gfx950 at about twice the FP64 rate of v_mfma_f64_16x16x4_f64).
+// By default each 16x16x4 block product is done with four
+// v_mfma_f64_4x4x4_4b_f64 (the K_NM's loop measured 3 % faster with them).
 // That instruction holds four independent 4x4x4 products in the lane groups
 // g = (l/4)%4: A(m, k) of block g at lane 16k + 4g + (m%4), B(k, n) at lane
 // 16k + 4g + (n%4), result (m, n) at lane 16(m%4) + 4g + (n%4).  With the A
@@ -80,10 +80,17 @@ DEV double wave_sum(double v)
 // that share l%4 read the same B element (an LDS broadcast), so a B read moves
 // 16 distinct values.  Accumulator element s of lane l is
 // C(4g + l/16, 4s + l%4) with g = (l/4)%4 (layout measured on gfx950).
+//
+// Shapes with M16 set use one v_mfma_f64_16x16x4_f64 per 16x16 block and 4 k
+// instead: lane l supplies A(l%16, l/16) and B(l/16, l%16), and accumulator
+// element e of lane l is C(l/16 + 4e, l%16) (measured on gfx950; the FP32
+// instruction's rows run the other way).  A wave's 64 x 64 tile then takes
+// 4 + 4 LDS reads per 16 instructions instead of 4 + 16 per 64.
 // ---------------------------------------------------------------------------
-template <int BM_, int BN_, int BK_, int WM_, int WN_>
+template <int BM_, int BN_, int BK_, int WM_, int WN_, bool M16_ = false>
 struct TileShape {
     static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
+    static constexpr bool M16 = M16_;
     static constexpr int NT = WM * WN * 64;
     static constexpr int TM = BM / WM, TN = BN / WN;
     static constexpr int FM = TM / 16, FN = TN / 16;
@@ -119,17 +126,29 @@ DEV void mma_stage(const double *__restrict__ As, const double *__restrict__ Bs,
 #pragma unroll
         for (int i = 0; i < S::FM; ++i)
             a[i] = As[kr * S::LDA + wm * S::TM + i * 16 + (lane & 15)];
+        if constexpr (S::M16) {
+            double b[S::FN];
 #pragma unroll
-        for (int j = 0; j < S::FN; ++j) {
-            double b[4];
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-                b[s] = Bs[kr * S::LDB + wn * S::TN + j * 16 + bcol16(lane, s)];
+            for (int j = 0; j < S::FN; ++j)
+                b[j] = Bs[kr * S::LDB + wn * S::TN + j * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < S::FM; ++i)
 #pragma unroll
+                for (int j = 0; j < S::FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int j = 0; j < S::FN; ++j) {
+                double b[4];
+#pragma unroll
                 for (int s = 0; s < 4; ++s)
-                    acc[i][j][s] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[i], b[s], acc[i][j][s], 0, 0, 0);
+                    b[s] = Bs[kr * S::LDB + wn * S::TN + j * 16 + bcol16(lane, s)];
+#pragma unroll
+                for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        acc[i][j][s] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[i], b[s], acc[i][j][s], 0, 0, 0);
+            }
         }
     }
 }
@@ -138,11 +157,17 @@ DEV void mma_stage(const double *__restrict__ As, const double *__restrict__ Bs,
 template <class S>
 DEV int acc_row(int wm, int i, int lane, int e)
 {
-    (void)e;
+    if constexpr (S::M16)
+        return wm * S::TM + i * 16 + (lane >> 4) + 4 * e;
     return wm * S::TM + i * 16 + 4 * ((lane >> 2) & 3) + (lane >> 4);
 }
 template <class S>
-DEV int acc_col(int wn, int j, int lane, int e) { return wn * S::TN + j * 16 + bcol16(lane, e); }
+DEV int acc_col(int wn, int j, int lane, int e)
+{
+    if constexpr (S::M16)
+        return wn * S::TN + j * 16 + (lane & 15);
+    return wn * S::TN + j * 16 + bcol16(lane, e);
+}
 
 // Integer power by repeated multiplication, p = g^zeta (zeta >= 1).
 DEV double ipow(double g, int zeta)

@@ -177,6 +177,7 @@ template <int BN>
 using KSB = TileShape<KNM_BM, BN, 8, 4, 1>;
 using KS = KSB<KNM_BN>;
 static_assert(KS::NT == 256, "K_NM kernel assumes 256 threads");
+static_assert(!KS::M16, "the predict row sums assume the 4x4x4 accumulator layout");
 static_assert(KNM_BM == 256 && KNM_BN == 64, "loader mapping assumes 256-atom tiles");
 
 constexpr int EPC = 32;           // epilogue columns per pass (two 16-column blocks)

@@ -8,7 +8,10 @@
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void mfma16_kernel(double *out, int iters, double a0)
+// Two workgroups per CU requested, so that the accumulators stay in VGPRs:
+// with one, the compiler keeps them in VGPRs across the loop and copies them
+// to and from AGPRs around every iteration's MFMAs, which halves the rate.
+__global__ __launch_bounds__(256, 2) void mfma16_kernel(double *out, int iters, double a0)
 {
     d4 acc[16];
     for (int i = 0; i < 16; ++i)
@@ -25,7 +28,7 @@ __global__ __launch_bounds__(256) void mfma16_kernel(double *out, int iters, dou
     out[blockIdx.x * 256 + threadIdx.x] = s;
 }
 
-__global__ __launch_bounds__(256) void mfma4_kernel(double *out, int iters, double a0)
+__global__ __launch_bounds__(256, 2) void mfma4_kernel(double *out, int iters, double a0)
 {
     double acc[16];
     for (int i = 0; i < 16; ++i)
@@ -42,7 +45,7 @@ __global__ __launch_bounds__(256) void mfma4_kernel(double *out, int iters, doub
     out[blockIdx.x * 256 + threadIdx.x] = s;
 }
 
-__global__ __launch_bounds__(256) void mfma_i8_kernel(int *out, int iters, int a0)
+__global__ __launch_bounds__(256, 2) void mfma_i8_kernel(int *out, int iters, int a0)
 {
     v4i acc[16];
     for (int i = 0; i < 16; ++i)
