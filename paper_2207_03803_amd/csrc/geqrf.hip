@@ -428,9 +428,11 @@ DEV bool update_tile_part(int64_t n_rb, int64_t n_cb, int n_head, int64_t &rb, i
 
 constexpr int OB = 2 * NB;                 // a TSQR panel pair (one factor_block)
 constexpr int OB2 = 2 * OB;                // outer block of the trailing update: two panel pairs
-// (on 16x16x4 MFMA: 470 instead of 483 ms for the FP64 QR at N = 1e5, M = 1e4)
-using WS = TileShape<OB, 128, 16, 2, 2, true>;   // P = Y^T C over a row chunk
-using US = TileShape<128, 128, 16, 2, 2, true>;  // C^T -= W^T Y^T (rows of C along the MFMA N axis)
+// Both on 16x16x4 MFMA.  The update's 64 x 128 tiles with 8-deep slices (122
+// VGPRs, up to four waves per SIMD) measured 1-2 % faster than 128 x 128 x 16
+// tiles at two waves per SIMD.
+using WS = TileShape<OB, 128, 16, 2, 2, true>;  // P = Y^T C over a row chunk
+using US = TileShape<64, 128, 8, 2, 2, true>;   // C^T -= W^T Y^T (rows of C along the MFMA N axis)
 
 // P[ch][p][q] = sum over the chunk's rows r of Y[r][p] C[r][q].  Y is the
 // block at (j0, j0) of width pw; C is either columns c0 .. c0+nt of A
@@ -747,7 +749,7 @@ __global__ __launch_bounds__(256) void qr_tcopy_kernel(const double *__restrict_
 // The accumulators start from the C tile (its loads in flight with the first
 // operand slices) and take -W, so the epilogue is a plain store.
 template <int PART>
-__global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt,
+__global__ __launch_bounds__(256, 3) void qr_update_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt,
                                                           int n_head)
 {
     __shared__ double lds[2 * US::STAGE];
@@ -825,7 +827,7 @@ __global__ __launch_bounds__(256, 2) void qr_update_kernel(QrWork w, int64_t j0,
 }
 
 using WS32 = TileShape<OB, 128, 32, 2, 2>;   // FP32 P = Y^T C
-using US32 = TileShape<128, 128, 32, 2, 2>;  // FP32 C^T -= W^T Y^T
+using US32 = TileShape<128, 128, 16, 2, 2>;  // FP32 C^T -= W^T Y^T (16-deep: three waves per SIMD)
 
 // FP32-storage versions of qr_wpart_kernel / qr_update_kernel on FP32 MFMA.
 __global__ __launch_bounds__(256, 2) void qr_wpart32_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt,
@@ -904,7 +906,7 @@ __global__ __launch_bounds__(256, 2) void qr_wpart32_kernel(QrWork w, int64_t j0
 }
 
 template <int PART>
-__global__ __launch_bounds__(256, 2) void qr_update32_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt,
+__global__ __launch_bounds__(256, 3) void qr_update32_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt,
                                                           int n_head)
 {
     __shared__ float lds[2 * US32::STAGE];
@@ -1099,7 +1101,8 @@ static void apply_block(const QrWork &wf, int64_t J, const BlockT &bt, int64_t c
                                bt.pwb, nch, nt, w.W32, OB);
         }
     }
-    const int n_head = (pw + 127) / 128;  // row blocks of 128 that meet Y's unit triangle
+    const int n_head = (pw + US::BN - 1) / US::BN;  // row blocks of 128 that meet Y's unit triangle
+    static_assert(US::BN == US32::BN, "one row-block split for both update kernels");
     auto grid = [](int64_t tiles) { return dim3((unsigned)((tiles + 7) & ~int64_t(7))); };
     if constexpr (sizeof(T) == 8) {
         const int64_t nrb = (rows + US::BN - 1) / US::BN, ncb_u = (nt + US::BM - 1) / US::BM;
