@@ -111,6 +111,16 @@ typedef struct gap_params {
  * with this flag and d > 4096 are rejected (GAP_EINVAL, or 0 workspace bytes):
  * beyond that the INT32 sums could overflow. */
 #define GAP_FLAG_KNM_INT8 4u
+/* Checking aid (not for production runs): at the start of every build, fill
+ * every floating-point and descriptor-slice array of the workspace with
+ * all-ones bytes (a NaN in FP64, FP32, BF16 and FP16; -1 in the INT8 slices
+ * and INT32 exponents) before the build writes it.  A read of workspace memory
+ * that the build or the solve did not write first then turns into a
+ * non-finite or wrong result that the parity tests see.  The tile plans,
+ * counters, status words and flags are not filled: the build clears or writes
+ * them itself, and they hold indices and loop bounds.  Costs one pass over
+ * those arrays per build. */
+#define GAP_FLAG_POISON_WORKSPACE 8u
 
 typedef struct gap_handle_s *gap_handle;
 

@@ -40,6 +40,10 @@ struct Layout {
     bool oz = false;
     int dpo = 0;
     size_t off_Xoz = 0, off_XMoz = 0, off_xe = 0, off_xme = 0;
+    // arrays GAP_FLAG_POISON_WORKSPACE fills (numbers and slices; no plans, counters or flags)
+    static constexpr int MAX_POISON = 48;
+    int n_poison = 0;
+    size_t poison_off[MAX_POISON] = {}, poison_len[MAX_POISON] = {};
 };
 
 bool is_mixed(int32_t precision) { return precision != GAP_FP64; }
@@ -72,18 +76,26 @@ Layout make_layout(int64_t NE, int64_t n_atoms, int64_t M, int32_t precision, in
         o = align_up(o + bytes, 256);
         return at;
     };
-    L.off_A = take(sizeof(double) * (size_t)L.lda * (size_t)L.ncols);
-    L.off_tau = take(sizeof(double) * (size_t)M);
-    L.off_wpart = take(sizeof(double) * (size_t)qr_max_chunks() * 4 * QR_NB * (size_t)L.ncols);
-    L.off_T = take(sizeof(double) * 16 * QR_NB * QR_NB);
-    L.off_Tin = take(sizeof(double) * 2 * QR_NB * QR_NB);
-    L.off_U = take(sizeof(double) * QR_NB * QR_NB);
-    L.off_W = take(sizeof(double) * 4 * QR_NB * (size_t)((L.ncols + 63) / 64 * 64));
-    L.off_ts_tiles = take(sizeof(double) * (size_t)L.tree.tiles_doubles);
-    L.off_ts_X = take(sizeof(double) * (size_t)L.tree.tiles_doubles);
-    L.off_ts_tau = take(sizeof(double) * (size_t)L.tree.tau_doubles);
-    L.off_rhs = take(sizeof(double) * (size_t)M);
-    L.off_misc = take(sizeof(double) * 512);
+    auto takep = [&](size_t bytes) {  // a numeric array: filled under GAP_FLAG_POISON_WORKSPACE
+        const size_t at = take(bytes);
+        if (L.n_poison < Layout::MAX_POISON) {
+            L.poison_off[L.n_poison] = at;
+            L.poison_len[L.n_poison++] = bytes;
+        }
+        return at;
+    };
+    L.off_A = takep(sizeof(double) * (size_t)L.lda * (size_t)L.ncols);
+    L.off_tau = takep(sizeof(double) * (size_t)M);
+    L.off_wpart = takep(sizeof(double) * (size_t)qr_max_chunks() * 4 * QR_NB * (size_t)L.ncols);
+    L.off_T = takep(sizeof(double) * 16 * QR_NB * QR_NB);
+    L.off_Tin = takep(sizeof(double) * 2 * QR_NB * QR_NB);
+    L.off_U = takep(sizeof(double) * QR_NB * QR_NB);
+    L.off_W = takep(sizeof(double) * 4 * QR_NB * (size_t)((L.ncols + 63) / 64 * 64));
+    L.off_ts_tiles = takep(sizeof(double) * (size_t)L.tree.tiles_doubles);
+    L.off_ts_X = takep(sizeof(double) * (size_t)L.tree.tiles_doubles);
+    L.off_ts_tau = takep(sizeof(double) * (size_t)L.tree.tau_doubles);
+    L.off_rhs = takep(sizeof(double) * (size_t)M);
+    L.off_misc = takep(sizeof(double) * 512);
     L.off_tiles = take(sizeof(int32_t) * (size_t)(L.max_tiles + 2));
     L.off_plan = take(sizeof(int32_t) * (size_t)(NE + knm_plan_chunks(NE) * (2049 + 1)));
     if (n_obs > 0) {
@@ -91,49 +103,49 @@ Layout make_layout(int64_t NE, int64_t n_atoms, int64_t M, int32_t precision, in
         L.max_tiles_d = knm_max_tiles(n_obs, n_pos);
         L.off_tiles_d = take(sizeof(int32_t) * (size_t)(L.max_tiles_d + 2));
         L.off_plan_d = take(sizeof(int32_t) * (size_t)(n_obs + knm_plan_chunks(n_obs) * (2049 + 1)));
-        L.off_D = take(sizeof(double) * (size_t)n_atoms * (size_t)M);
+        L.off_D = takep(sizeof(double) * (size_t)n_atoms * (size_t)M);
     }
     L.off_counters = take(sizeof(unsigned) * 16);
     L.off_status = take(sizeof(int32_t) * 4);
     L.n_tflags = trsv_sync_ints(M);
     L.off_tflags = take(sizeof(int32_t) * (size_t)L.n_tflags);
-    L.off_cq_S = take(sizeof(double) * QR_NB * (size_t)L.lda);
-    L.off_cq_part = take(sizeof(double) * (size_t)CQ_MAX_CHUNKS * QR_NB * QR_NB);
-    L.off_cq_G = take(sizeof(double) * 4 * QR_NB * QR_NB);
-    L.off_cq_R = take(sizeof(double) * 4 * QR_NB * QR_NB);
-    L.off_T2 = take(sizeof(double) * 16 * QR_NB * QR_NB);
-    L.off_wpart_s = take(sizeof(double) * (size_t)qr_max_chunks_s() * 4 * QR_NB * 2 * QR_NB);
-    L.off_W_s = take(sizeof(double) * 16 * QR_NB * QR_NB);
-    L.off_W32_s = take(sizeof(float) * 16 * QR_NB * QR_NB);
-    L.off_diag = take(sizeof(double) * (size_t)(14 * M + 512));
+    L.off_cq_S = takep(sizeof(double) * QR_NB * (size_t)L.lda);
+    L.off_cq_part = takep(sizeof(double) * (size_t)CQ_MAX_CHUNKS * QR_NB * QR_NB);
+    L.off_cq_G = takep(sizeof(double) * 4 * QR_NB * QR_NB);
+    L.off_cq_R = takep(sizeof(double) * 4 * QR_NB * QR_NB);
+    L.off_T2 = takep(sizeof(double) * 16 * QR_NB * QR_NB);
+    L.off_wpart_s = takep(sizeof(double) * (size_t)qr_max_chunks_s() * 4 * QR_NB * 2 * QR_NB);
+    L.off_W_s = takep(sizeof(double) * 16 * QR_NB * QR_NB);
+    L.off_W32_s = takep(sizeof(float) * 16 * QR_NB * QR_NB);
+    L.off_diag = takep(sizeof(double) * (size_t)(14 * M + 512));
     if (mixed) {
         const int64_t ldw = (L.ncols + 63) / 64 * 64;
-        L.off_A32 = take(sizeof(float) * (size_t)L.lda * (size_t)L.ncols);
-        L.off_W32 = take(sizeof(float) * 4 * QR_NB * (size_t)ldw);
-        L.off_r = take(sizeof(double) * (size_t)L.m);
-        L.off_s = take(sizeof(double) * (size_t)M);
-        L.off_z = take(sizeof(double) * (size_t)M);
-        L.off_dc = take(sizeof(double) * (size_t)M);
-        L.off_p = take(sizeof(double) * (size_t)M);
-        L.off_q = take(sizeof(double) * (size_t)L.m);
-        L.off_part = take(sizeof(double) * 8 * (size_t)L.m);
-        L.off_rnorm = take(sizeof(double) * (size_t)((L.m + 255) / 256 + 1));
+        L.off_A32 = takep(sizeof(float) * (size_t)L.lda * (size_t)L.ncols);
+        L.off_W32 = takep(sizeof(float) * 4 * QR_NB * (size_t)ldw);
+        L.off_r = takep(sizeof(double) * (size_t)L.m);
+        L.off_s = takep(sizeof(double) * (size_t)M);
+        L.off_z = takep(sizeof(double) * (size_t)M);
+        L.off_dc = takep(sizeof(double) * (size_t)M);
+        L.off_p = takep(sizeof(double) * (size_t)M);
+        L.off_q = takep(sizeof(double) * (size_t)L.m);
+        L.off_part = takep(sizeof(double) * 8 * (size_t)L.m);
+        L.off_rnorm = takep(sizeof(double) * (size_t)((L.m + 255) / 256 + 1));
         L.off_flags = take(sizeof(int32_t) * 4);
-        L.off_stats = take(sizeof(double) * 4);
+        L.off_stats = takep(sizeof(double) * 4);
     }
     if (L.lp) {
         L.dp = knm_lp_dpad(d);
-        L.off_Xlp = take(sizeof(uint16_t) * (size_t)n_atoms * (size_t)L.dp);
-        L.off_XMlp = take(sizeof(uint16_t) * (size_t)M * (size_t)L.dp);
+        L.off_Xlp = takep(sizeof(uint16_t) * (size_t)n_atoms * (size_t)L.dp);
+        L.off_XMlp = takep(sizeof(uint16_t) * (size_t)M * (size_t)L.dp);
     }
     if (flags & GAP_FLAG_KNM_INT8) {
         L.oz = true;
         L.dpo = knm_oz_dpad(d);
         const size_t sl = (size_t)knm_oz_slices();
-        L.off_Xoz = take(sl * (size_t)n_atoms * (size_t)L.dpo);
-        L.off_XMoz = take(sl * (size_t)M * (size_t)L.dpo);
-        L.off_xe = take(sizeof(int32_t) * (size_t)n_atoms);
-        L.off_xme = take(sizeof(int32_t) * (size_t)M);
+        L.off_Xoz = takep(sl * (size_t)n_atoms * (size_t)L.dpo);
+        L.off_XMoz = takep(sl * (size_t)M * (size_t)L.dpo);
+        L.off_xe = takep(sizeof(int32_t) * (size_t)n_atoms);
+        L.off_xme = takep(sizeof(int32_t) * (size_t)M);
     }
     L.total = o;
     return L;
@@ -220,6 +232,13 @@ __global__ void zero_i32_kernel(int32_t *p, int64_t n)
 {
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
         p[i] = 0;
+}
+
+// All-ones words over n 4-byte words (GAP_FLAG_POISON_WORKSPACE).
+__global__ void poison_kernel(uint32_t *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0xFFFFFFFFu;
 }
 
 __global__ void copy_kernel(const double *src, double *dst, int64_t n)
@@ -506,6 +525,15 @@ static KnmPlan plan_of_d(gap_handle h)
 static gap_status build_setup(gap_handle h, hipStream_t s, KnmArgs *a)
 {
     const Layout &L = h->L;
+    if (h->p.flags & GAP_FLAG_POISON_WORKSPACE)
+        for (int i = 0; i < L.n_poison; ++i) {
+            // each array starts 256-byte aligned and its padding runs to the next multiple of 256
+            const int64_t words = (int64_t)((L.poison_len[i] + 3) / 4);
+            if (words == 0)
+                continue;
+            const unsigned blocks = (unsigned)std::min<int64_t>((words + 255) / 256, 4096);
+            hipLaunchKernelGGL(poison_kernel, dim3(blocks), dim3(256), 0, s, h->at<uint32_t>(L.poison_off[i]), words);
+        }
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, h->counters(), 16);
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned *>(h->status()), 4);
     hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(256), 0, s, h->at<int32_t>(L.off_tflags), L.n_tflags);

@@ -18,6 +18,7 @@ GAP_FP64, GAP_MIXED_FP32, GAP_MIXED_BF16, GAP_MIXED_FP16 = 0, 1, 2, 3
 GAP_FLAG_TIMING = 1
 GAP_FLAG_ERROR_ESTIMATE = 2
 GAP_FLAG_KNM_INT8 = 4
+GAP_FLAG_POISON_WORKSPACE = 8
 
 # Every entry point include/gap.h declares.
 EXPORTS = ["gap_create", "gap_workspace_bytes", "gap_bind_workspace", "gap_build_knm", "gap_solve",

@@ -50,6 +50,16 @@ def test_int8_knm_descriptor_length_limit():
     assert gap.workspace_bytes(gap.params(4097, 2), 10, 100, 10) > 0
 
 
+def test_poison_flag_leaves_the_workspace_size_unchanged():
+    """GAP_FLAG_POISON_WORKSPACE only fills arrays the workspace already has."""
+    for prec in (gap.GAP_FP64, gap.GAP_MIXED_FP32, gap.GAP_MIXED_BF16):
+        for extra in (0, gap.GAP_FLAG_KNM_INT8):
+            plain = gap.workspace_bytes(gap.params(64, 2, precision=prec, flags=extra), 30, 900, 200)
+            poisoned = gap.workspace_bytes(
+                gap.params(64, 2, precision=prec, flags=extra | gap.GAP_FLAG_POISON_WORKSPACE), 30, 900, 200)
+            assert plain > 0 and poisoned == plain
+
+
 def test_workspace_bytes_bad_inputs():
     p = gap.params(64, 2)
     assert gap.workspace_bytes(p, 0, 10, 10) == 0
