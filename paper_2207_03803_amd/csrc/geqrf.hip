@@ -826,11 +826,11 @@ __global__ __launch_bounds__(256, 3) void qr_update_kernel(QrWork w, int64_t j0,
             }
 }
 
-using WS32 = TileShape<OB, 128, 32, 2, 2>;   // FP32 P = Y^T C
+using WS32 = TileShape<OB, 128, 16, 2, 2>;   // FP32 P = Y^T C (16-deep: four waves per SIMD)
 using US32 = TileShape<128, 128, 16, 2, 2>;  // FP32 C^T -= W^T Y^T (16-deep: three waves per SIMD)
 
 // FP32-storage versions of qr_wpart_kernel / qr_update_kernel on FP32 MFMA.
-__global__ __launch_bounds__(256, 2) void qr_wpart32_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt,
+__global__ __launch_bounds__(256, 3) void qr_wpart32_kernel(QrWork w, int64_t j0, int pw, int64_t c0, int64_t nt,
                                                             int ymode, int64_t r0, int64_t chunk)
 {
     __shared__ float lds[2 * WS32::STAGE];
