@@ -132,7 +132,7 @@ class Sweep:
     """The fits of one sweep with their inputs resident on the device."""
 
     def __init__(self, specs, pools, precision=gap.GAP_MIXED_FP32, streams=8, split_wgs=0, lookahead=0,
-                 max_refine_iters=20, refine_tol=1e-12, targets=None, grouped=False, shapes=None):
+                 max_refine_iters=20, refine_tol=1e-12, targets=None, grouped=False, shapes=None, flags=0):
         import torch
 
         self.specs = specs
@@ -166,7 +166,7 @@ class Sweep:
             f.sigma = torch.from_numpy(dr["sigma"]).cuda()
             f.host = dict(c_true=dr["c_true"], noise=dr["noise"], sparse_idx=dr["sparse_idx"], sigma=dr["sigma"])
             p = gap.params(s.d, s.zeta, 1.0, 1e-8, precision=precision, max_refine_iters=max_refine_iters,
-                           refine_tol=refine_tol)
+                           refine_tol=refine_tol, flags=flags)
             f.handle = gap.Handle(p, stream=self.streams[stream_of[pos]])
             shp = shapes(s) if shapes else dict(qr_split_wgs=split_wgs, qr_lookahead=lookahead)
             if any(shp.values()):

@@ -3,7 +3,8 @@ workspace is filled with all-ones bytes (a NaN in the floating-point formats)
 at the start of each build.  A build or solve that reads workspace memory it
 did not write first would then give a non-finite or different result.  Every
 form, both QR panel methods and the derivative rows give the unpoisoned
-weights bitwise, at the oracle's weights."""
+weights bitwise, at the oracle's weights; so do the captured sweep graphs, with
+per-fit and with grouped K_NM launches."""
 import numpy as np
 import pytest
 
@@ -98,3 +99,24 @@ def test_poisoned_workspace_with_derivative_rows(orc, precision):
     log(f"  precision {precision}: poisoned c rel err vs oracle {rel(cs[1], c_ref):.2e}")
     assert np.all(np.isfinite(cs[1]))
     assert np.array_equal(cs[0], cs[1])
+
+
+@pytest.mark.parametrize("grouped", [False, True])
+def test_poisoned_workspaces_in_captured_sweep_graphs(grouped):
+    from paper_2207_03803_amd import gap, sweep
+
+    specs = sweep.make_sweep(seed=4, n_fits=6, scale=0.05)
+    pools = sweep.make_pools(specs, seed=4)
+    out = {}
+    for poison in (False, True):
+        sw = sweep.Sweep(specs, pools, precision=gap.GAP_FP64, streams=3, grouped=grouped,
+                         flags=gap.GAP_FLAG_POISON_WORKSPACE if poison else 0)
+        sw.capture()
+        sw.replay(2)
+        assert all(st == gap.GAP_OK for st in sw.statuses())
+        out[poison] = sw.weights()
+        sw.close()
+    log(f"  {'grouped' if grouped else 'per-fit'} K_NM: {len(out[True])} fits, poisoned weights bitwise equal")
+    for a, b in zip(out[True], out[False]):
+        assert np.all(np.isfinite(a))
+        assert np.array_equal(a, b)
