@@ -191,6 +191,7 @@ template <int BN>
 struct KnmLoads {
     double a[8];
     double b[BN / 32];
+    bool za = false, zb = false;  // store zeros instead (a missing row, see knm_load_full)
 };
 
 template <int BN>
@@ -229,6 +230,30 @@ DEV void knm_load(KnmLoads<BN> &r, const double *__restrict__ xr, const double *
     }
 }
 
+// The same for a slice that lies inside the rows (k0 + 8 <= d), without
+// branches: a thread whose atom or sparse row is missing reads row 0 of XM
+// instead and stores zeros, so the loads stay in flight through the stage's
+// MFMAs (a divergent branch here makes the compiler wait for them before).
+template <int BN>
+DEV void knm_load_full(KnmLoads<BN> &r, const double *__restrict__ xr, const double *__restrict__ XM,
+                       int64_t col0, int64_t M, int d, int k0)
+{
+    constexpr int TPR = 256 / BN, VB = BN / 32;
+    const int tid = threadIdx.x;
+    r.za = !xr;
+    const double *sa = xr ? xr + k0 : XM + k0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        r.a[e] = sa[e];
+    const int64_t row = col0 + tid / TPR;
+    const int kb = k0 + (tid % TPR) * VB;
+    r.zb = row >= M;
+    const double *sb = row < M ? XM + row * (int64_t)d + kb : XM + kb;
+#pragma unroll
+    for (int e = 0; e < VB; ++e)
+        r.b[e] = sb[e];
+}
+
 template <int BN>
 DEV void knm_store(const KnmLoads<BN> &r, double *As, double *Bs)
 {
@@ -239,13 +264,13 @@ DEV void knm_store(const KnmLoads<BN> &r, double *As, double *Bs)
         const int row = tid;
 #pragma unroll
         for (int e = 0; e < 8; ++e)
-            As[e * S::LDA + row] = r.a[e];
+            As[e * S::LDA + row] = r.za ? 0.0 : r.a[e];
     }
     {
         const int row = tid / TPR, kb = (tid % TPR) * VB;
 #pragma unroll
         for (int e = 0; e < VB; ++e)
-            Bs[(kb + e) * S::LDB + row] = r.b[e];
+            Bs[(kb + e) * S::LDB + row] = r.zb ? 0.0 : r.b[e];
     }
 }
 
@@ -260,19 +285,27 @@ DEV void knm_gemm(d4 (&acc)[KSB<BN>::FM][KSB<BN>::FN], double *lds, const double
     const int wm = wave / S::WN, wn = wave % S::WN;
     zero_acc<S>(acc);
     const int nk = (d + S::BK - 1) / S::BK;
+    const int nkf = d / S::BK;  // slices inside the rows; a ragged last one is loaded with checks
     KnmLoads<BN> r;
-    knm_load<BN>(r, xr, XM, col0, M, d, 0);
+    if (nkf > 0)
+        knm_load_full<BN>(r, xr, XM, col0, M, d, 0);
+    else
+        knm_load<BN>(r, xr, XM, col0, M, d, 0);
     knm_store<BN>(r, lds, lds + S::A_ELEMS);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         double *cur = lds + (kt & 1) * S::STAGE;
         double *nxt = lds + ((kt + 1) & 1) * S::STAGE;
-        const bool more = kt + 1 < nk;
+        const bool more = kt + 1 < nkf;
         if (more)
-            knm_load<BN>(r, xr, XM, col0, M, d, (kt + 1) * S::BK);
+            knm_load_full<BN>(r, xr, XM, col0, M, d, (kt + 1) * S::BK);
         mma_stage<S>(cur, cur + S::A_ELEMS, acc, wm, wn, lane);
-        if (more)
+        if (more) {
             knm_store<BN>(r, nxt, nxt + S::A_ELEMS);
+        } else if (kt + 1 < nk) {  // the ragged last slice, loaded after this stage's MFMAs
+            knm_load<BN>(r, xr, XM, col0, M, d, (kt + 1) * S::BK);
+            knm_store<BN>(r, nxt, nxt + S::A_ELEMS);
+        }
         __syncthreads();
     }
 }
