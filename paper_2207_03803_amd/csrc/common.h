@@ -348,6 +348,87 @@ DEV void gemm_tile_runs(d4 (&acc)[S::FM][S::FN], double *lds, int64_t K, FA fa, 
     }
 }
 
+// Same product with two loader pairs: faf / fbf for the full slices [0, K / BK)
+// fill their run from a valid address without bounds checks and return true
+// when it must be stored as zeros (applied at the store, after the stage's
+// MFMAs); fa / fb (the checked run loaders above) load a ragged last slice,
+// after the MFMAs of the stage before it.  With no branch on the loaded values
+// in the loop, the next slice's loads stay in flight through the MFMAs.
+template <class S, bool A_KC, bool B_KC, class FAF, class FBF, class FA, class FB>
+DEV void gemm_tile_runs_ft(d4 (&acc)[S::FM][S::FN], double *lds, int64_t K, FAF faf, FBF fbf, FA fa, FB fb)
+{
+    constexpr int VA = S::BM * S::BK / S::NT;
+    constexpr int VB = S::BN * S::BK / S::NT;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave / S::WN, wn = wave % S::WN;
+    double ra[VA], rb[VB];
+    bool za = false, zb = false;
+    int ar, ak, br, bk;
+    if constexpr (A_KC) {
+        ar = t / (S::BK / VA);
+        ak = (t % (S::BK / VA)) * VA;
+    } else {
+        ak = t / (S::BM / VA);
+        ar = (t % (S::BM / VA)) * VA;
+    }
+    if constexpr (B_KC) {
+        br = t / (S::BK / VB);
+        bk = (t % (S::BK / VB)) * VB;
+    } else {
+        bk = t / (S::BN / VB);
+        br = (t % (S::BN / VB)) * VB;
+    }
+    auto store = [&](double *As, double *Bs) {
+#pragma unroll
+        for (int e = 0; e < VA; ++e) {
+            const double v = za ? 0.0 : ra[e];
+            if constexpr (A_KC)
+                As[(ak + e) * S::LDA + ar] = v;
+            else
+                As[ak * S::LDA + ar + e] = v;
+        }
+#pragma unroll
+        for (int e = 0; e < VB; ++e) {
+            const double v = zb ? 0.0 : rb[e];
+            if constexpr (B_KC)
+                Bs[(bk + e) * S::LDB + br] = v;
+            else
+                Bs[bk * S::LDB + br + e] = v;
+        }
+    };
+    const int64_t nk = (K + S::BK - 1) / S::BK, nkf = K / S::BK;
+    if (nk <= 0)
+        return;
+    if (nkf > 0) {
+        za = faf(ar, (int64_t)ak, ra);
+        zb = fbf(br, (int64_t)bk, rb);
+    } else {
+        fa(ar, (int64_t)ak, ra);
+        fb(br, (int64_t)bk, rb);
+    }
+    store(lds, lds + S::A_ELEMS);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        double *cur = lds + (kt & 1) * S::STAGE;
+        double *nxt = lds + ((kt + 1) & 1) * S::STAGE;
+        const bool more = kt + 1 < nkf;
+        if (more) {
+            za = faf(ar, (kt + 1) * S::BK + ak, ra);
+            zb = fbf(br, (kt + 1) * S::BK + bk, rb);
+        }
+        mma_stage<S>(cur, cur + S::A_ELEMS, acc, wm, wn, lane);
+        if (more) {
+            store(nxt, nxt + S::A_ELEMS);
+        } else if (kt + 1 < nk) {
+            fa(ar, (kt + 1) * S::BK + ak, ra);
+            fb(br, (kt + 1) * S::BK + bk, rb);
+            za = zb = false;
+            store(nxt, nxt + S::A_ELEMS);
+        }
+        __syncthreads();
+    }
+}
+
 // Load n consecutive doubles from p (16-byte aligned when aligned16).
 template <int N>
 DEV void load_run(const double *__restrict__ p, double (&v)[N])

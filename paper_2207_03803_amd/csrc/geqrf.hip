@@ -497,7 +497,23 @@ __global__ __launch_bounds__(256, 2) void qr_wpart_kernel(QrWork w, int64_t j0, 
             }
         }
     };
-    gemm_tile_runs<WS, true, true>(acc, lds, rhi - rlo, fa, fb);
+    if (!masked && !ymode) {
+        // Full slices without checks: a P row past pw reads row pw - 1 of Y and a
+        // column past nt column nt - 1 of C, stored as zeros.
+        const int64_t colq_max = nt - 1;
+        auto faf = [&](int p, int64_t k, double (&v)[VA]) {
+            load_run(A + (j0 + (p < pw ? p : pw - 1)) * lda + rlo + k, v);
+            return p >= pw;
+        };
+        auto fbf = [&](int qi, int64_t k, double (&v)[VB]) {
+            const int64_t q = q0 + qi;
+            load_run(A + (c0 + (q < nt ? q : colq_max)) * lda + rlo + k, v);
+            return q >= nt;
+        };
+        gemm_tile_runs_ft<WS, true, true>(acc, lds, rhi - rlo, faf, fbf, fa, fb);
+    } else {
+        gemm_tile_runs<WS, true, true>(acc, lds, rhi - rlo, fa, fb);
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WS::WN, wn = wave % WS::WN;
     double *P = w.wpart + (ch * OB2 + prow0) * w.wp_ld;
